@@ -1,0 +1,723 @@
+"""Seeded synthetic scenes shaped like the paper's workloads.
+
+Every array is produced with ``numpy.random.default_rng(seed)`` and returned in
+the layout the library and the oracle both read:
+
+* ``vtx``      float32 [V, 3]   vertex coordinates in metres
+* ``tri``      int32   [M, 3]   vertex indices of each flat triangle
+* ``material`` int32   [M]      material index per triangle
+* ``plane_id`` int32   [M]      coplanar-group id per triangle (0 <= id < M)
+* ``alpha``    float32 [n_mat, 8] absorption per material and octave band
+* ``beta``     float32 [8]      air absorption per band, energy, 1/m
+* ``src``      float32 [3]      point source
+* ``rcv``      float32 [n_rcv, 4] receiver spheres (x, y, z, r)
+
+Octave bands are 62.5 Hz ... 8 kHz (Table 1 of the paper).  The absorption rows
+printed in Table 1 are read from ``tests/golden/table1_absorption.txt``-equivalent
+constants below.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional
+
+import numpy as np
+
+BAND_CENTRES = np.array([62.5 * 2.0 ** b for b in range(8)])  # Hz, Table 1 columns
+
+# Table 1 of the paper: Odeon rows (reference number -> 8-band absorption).
+TABLE1 = {
+    1: [1, 1, 1, 1, 1, 1, 1, 1],                                  # 100 % absorbent
+    2: [0, 0, 0, 0, 0, 0, 0, 0],                                  # 100 % reflecting
+    107: [0.36, 0.36, 0.44, 0.31, 0.29, 0.39, 0.25, 0.25],        # concrete block, coarse
+    3000: [0.4, 0.4, 0.3, 0.2, 0.17, 0.15, 0.1, 0.1],             # hollow wooden podium
+}
+
+
+@dataclasses.dataclass
+class Scene:
+    name: str
+    vtx: np.ndarray
+    tri: np.ndarray
+    material: np.ndarray
+    plane_id: np.ndarray
+    alpha: np.ndarray
+    closed: bool
+    src: np.ndarray = None
+    rcv: np.ndarray = None
+    beta: np.ndarray = None
+    n_rays: int = 0
+    max_reflections: int = 0
+    c: float = 343.0
+    fs: float = 48000.0
+    ir_seconds: float = 0.0
+
+    @property
+    def n_tri(self) -> int:
+        return int(self.tri.shape[0])
+
+    @property
+    def n_vtx(self) -> int:
+        return int(self.vtx.shape[0])
+
+    @property
+    def n_mat(self) -> int:
+        return int(self.alpha.shape[0])
+
+    @property
+    def ir_len(self) -> int:
+        return int(round(self.fs * self.ir_seconds))
+
+    @property
+    def max_path_length(self) -> float:
+        """c*T plus the largest receiver radius (rays stop once past it)."""
+        rmax = float(self.rcv[:, 3].max()) if self.rcv is not None and len(self.rcv) else 0.0
+        return float(self.c * self.ir_seconds + rmax)
+
+    def diag(self) -> float:
+        v = self.vtx.astype(np.float64)
+        return float(np.linalg.norm(v.max(0) - v.min(0)))
+
+
+# ----------------------------------------------------------------------------
+# mesh helpers (pure bookkeeping: vertex lattices and index lists)
+# ----------------------------------------------------------------------------
+
+def _quads_to_tris(q: np.ndarray) -> np.ndarray:
+    """(a,b,c,d) cyclic quads -> triangles (a,b,c), (a,c,d): fixed diagonal a-c."""
+    t1 = q[:, [0, 1, 2]]
+    t2 = q[:, [0, 2, 3]]
+    return np.stack([t1, t2], axis=1).reshape(-1, 3)
+
+
+def _grid_quads(idx: np.ndarray) -> np.ndarray:
+    """Quads of a 2-D vertex-index grid idx[i, j] (cells between neighbours)."""
+    a = idx[:-1, :-1].ravel()
+    b = idx[1:, :-1].ravel()
+    c = idx[1:, 1:].ravel()
+    d = idx[:-1, 1:].ravel()
+    return np.stack([a, b, c, d], axis=1)
+
+
+def edge_use_counts(tri: np.ndarray) -> np.ndarray:
+    e = np.concatenate([tri[:, [0, 1]], tri[:, [1, 2]], tri[:, [2, 0]]], axis=0)
+    e.sort(axis=1)
+    _, counts = np.unique(e, axis=0, return_counts=True)
+    return counts
+
+
+def is_watertight(tri: np.ndarray) -> bool:
+    """Every undirected edge is shared by exactly two triangles."""
+    return bool(np.all(edge_use_counts(tri) == 2))
+
+
+def _tri_areas(vtx: np.ndarray, tri: np.ndarray) -> np.ndarray:
+    v = vtx.astype(np.float64)
+    e1 = v[tri[:, 1]] - v[tri[:, 0]]
+    e2 = v[tri[:, 2]] - v[tri[:, 0]]
+    return 0.5 * np.linalg.norm(np.cross(e1, e2), axis=1)
+
+
+def _check(scene: Scene, expect_tris: Optional[int] = None) -> Scene:
+    assert scene.vtx.dtype == np.float32 and scene.tri.dtype == np.int32
+    assert scene.material.dtype == np.int32 and scene.plane_id.dtype == np.int32
+    assert np.all(np.isfinite(scene.vtx))
+    assert scene.tri.min() >= 0 and scene.tri.max() < scene.n_vtx
+    assert np.all(_tri_areas(scene.vtx, scene.tri) > 0), "zero-area triangle"
+    assert scene.plane_id.min() >= 0 and scene.plane_id.max() < scene.n_tri
+    assert scene.material.min() >= 0 and scene.material.max() < scene.n_mat
+    if expect_tris is not None:
+        assert scene.n_tri == expect_tris, (scene.name, scene.n_tri, expect_tris)
+    if scene.closed:
+        assert is_watertight(scene.tri), scene.name
+    return scene
+
+
+def _truncated_normal(rng: np.random.Generator, shape, sigma: float, cut: float = 3.0):
+    x = rng.standard_normal(shape)
+    bad = np.abs(x) > cut
+    while bad.any():
+        x[bad] = rng.standard_normal(int(bad.sum()))
+        bad = np.abs(x) > cut
+    return x * sigma
+
+
+# ----------------------------------------------------------------------------
+# box rooms
+# ----------------------------------------------------------------------------
+
+def box_mesh(dims, n=(1, 1, 1), jitter_sigma: float = 0.0, rng=None,
+             plane_per_wall: bool = True):
+    """Closed box [0,Lx]x[0,Ly]x[0,Lz] as shared-vertex grids on its six walls.
+
+    Walls (material index = wall index): 0 x=0, 1 x=Lx, 2 y=0, 3 y=Ly, 4 z=0,
+    5 z=Lz.  With n=(1,1,1) this is the 8-vertex, 12-triangle shoebox.
+    """
+    nx, ny, nz = n
+    Lx, Ly, Lz = dims
+    I, J, K = np.meshgrid(np.arange(nx + 1), np.arange(ny + 1), np.arange(nz + 1), indexing="ij")
+    boundary = (I == 0) | (I == nx) | (J == 0) | (J == ny) | (K == 0) | (K == nz)
+    idx = -np.ones(I.shape, dtype=np.int64)
+    idx[boundary] = np.arange(int(boundary.sum()))
+    pts = np.stack([I[boundary] * (Lx / nx), J[boundary] * (Ly / ny), K[boundary] * (Lz / nz)],
+                   axis=1).astype(np.float64)
+    # exact wall coordinates for the far walls (avoid i*(L/n) rounding)
+    pts[I[boundary] == nx, 0] = Lx
+    pts[J[boundary] == ny, 1] = Ly
+    pts[K[boundary] == nz, 2] = Lz
+    if jitter_sigma > 0:
+        pts = pts + _truncated_normal(rng, pts.shape, jitter_sigma)
+    walls = [
+        idx[0, :, :], idx[nx, :, :].T,       # x = 0, x = Lx  (orientation irrelevant)
+        idx[:, 0, :].T, idx[:, ny, :],
+        idx[:, :, 0], idx[:, :, nz].T,
+    ]
+    tris, mats = [], []
+    for w, g in enumerate(walls):
+        t = _quads_to_tris(_grid_quads(g))
+        tris.append(t)
+        mats.append(np.full(len(t), w, dtype=np.int32))
+    tri = np.concatenate(tris).astype(np.int32)
+    mat = np.concatenate(mats)
+    if plane_per_wall:
+        # plane id = lowest triangle index of each wall (the group's representative)
+        first = np.concatenate([[0], np.cumsum([len(t) for t in tris])[:-1]])
+        plane = first[mat].astype(np.int32)
+    else:
+        plane = np.arange(len(tri), dtype=np.int32)
+    return pts.astype(np.float32), tri, mat, plane
+
+
+def random_alpha(rng, n_mat: int, lo=0.02, hi=0.3) -> np.ndarray:
+    return rng.uniform(lo, hi, size=(n_mat, 8)).astype(np.float32)
+
+
+def shoebox_c1(seed: int = 1) -> Scene:
+    """10 x 7 x 3 m shoebox as 12 triangles; one receiver (r = 0.3 m)."""
+    rng = np.random.default_rng(seed)
+    vtx, tri, mat, plane = box_mesh((10.0, 7.0, 3.0))
+    alpha = random_alpha(rng, 6)
+    s = Scene("C1 shoebox 12 tris", vtx, tri, mat, plane, alpha, closed=True,
+              src=np.array([3.17, 2.41, 1.63], np.float32),
+              rcv=np.array([[7.29, 4.87, 1.38, 0.3]], np.float32),
+              beta=np.zeros(8, np.float32), n_rays=10_000, max_reflections=20,
+              ir_seconds=0.5)
+    return _check(s, 12)
+
+
+def paper_box(seed: int = 11, n_rays: int = 100_000, max_reflections: int = 6) -> Scene:
+    """The paper's [5,4,3] m validation box: 12 triangles, source [4,2,1.7],
+    receiver [2,2,1.7] with r = 0.2 m (shoe-box comparison section)."""
+    rng = np.random.default_rng(seed)
+    vtx, tri, mat, plane = box_mesh((5.0, 4.0, 3.0))
+    alpha = random_alpha(rng, 6)
+    s = Scene("paper box 5x4x3", vtx, tri, mat, plane, alpha, closed=True,
+              src=np.array([4.0, 2.0, 1.7], np.float32),
+              rcv=np.array([[2.0, 2.0, 1.7, 0.2]], np.float32),
+              beta=iso9613_beta(), n_rays=n_rays, max_reflections=max_reflections,
+              ir_seconds=0.25)
+    return _check(s, 12)
+
+
+def tessellated_box_c2(seed: int = 2, jitter: bool = True) -> Scene:
+    """The C1 box as 144x101x43 shared-vertex grids: 100,316 triangles, 50,160
+    vertices.  Jittered variant: truncated-Gaussian sigma = 1 cm on every shared
+    vertex (watertight), plane id = triangle id.  Flat variant: plane id = wall."""
+    rng = np.random.default_rng(seed)
+    vtx, tri, mat, plane = box_mesh((10.0, 7.0, 3.0), (144, 101, 43),
+                                    jitter_sigma=0.01 if jitter else 0.0, rng=rng,
+                                    plane_per_wall=not jitter)
+    assert vtx.shape[0] == 50_160
+    alpha = random_alpha(rng, 6)
+    rcv = np.concatenate([rng.uniform([1, 1, 0.8], [9, 6, 2.2], size=(3, 3)),
+                          np.full((3, 1), 0.3)], axis=1).astype(np.float32)
+    s = Scene("C2 tessellated box 100k" + (" jittered" if jitter else " flat"),
+              vtx, tri, mat, plane, alpha, closed=True,
+              src=np.array([3.17, 2.41, 1.63], np.float32), rcv=rcv,
+              beta=iso9613_beta(), n_rays=1_000_000, max_reflections=50, ir_seconds=1.0)
+    return _check(s, 100_316)
+
+
+# ----------------------------------------------------------------------------
+# open-air theater (stand-in for the 436k-face Orange mesh)
+# ----------------------------------------------------------------------------
+
+class _MeshBuilder:
+    def __init__(self):
+        self.v: List[np.ndarray] = []
+        self.t: List[np.ndarray] = []
+        self.m: List[np.ndarray] = []
+        self.p: List[np.ndarray] = []   # -1 => plane id = own triangle id
+        self.nv = 0
+        self.nt = 0
+        self.groups = 0
+
+    def add(self, verts, tris, material: int, coplanar: bool):
+        verts = np.asarray(verts, np.float64).reshape(-1, 3)
+        tris = np.asarray(tris, np.int64).reshape(-1, 3) + self.nv
+        self.v.append(verts)
+        self.t.append(tris)
+        self.m.append(np.full(len(tris), material, np.int32))
+        if coplanar:
+            self.p.append(np.full(len(tris), self.nt, np.int64))   # representative = first tri
+        else:
+            self.p.append(self.nt + np.arange(len(tris)))
+        self.nv += len(verts)
+        self.nt += len(tris)
+
+    def grid(self, pts2d: np.ndarray, material: int, coplanar: bool):
+        """pts2d: [a, b, 3] vertex grid -> quads -> triangles."""
+        a, b, _ = pts2d.shape
+        idx = np.arange(a * b).reshape(a, b)
+        self.add(pts2d.reshape(-1, 3), _quads_to_tris(_grid_quads(idx)), material, coplanar)
+
+    def finish(self):
+        vtx = np.concatenate(self.v).astype(np.float32)
+        tri = np.concatenate(self.t).astype(np.int32)
+        mat = np.concatenate(self.m)
+        plane = np.concatenate(self.p).astype(np.int32)
+        return vtx, tri, mat, plane
+
+
+THEATER_STAGE_Z = 1.0
+THEATER_RISER = 0.55
+THEATER_TREAD = 0.95
+
+
+def _tier_height(t: int) -> float:
+    return THEATER_RISER * (t + 1)
+
+
+def _tier_radius(t: int) -> float:
+    return 12.0 + THEATER_TREAD * t
+
+
+def theater_c3(seed: int = 3, n_rays: int = 1_000_000, max_reflections: int = 60,
+               ir_seconds: float = 2.0) -> Scene:
+    """Synthetic open-air theater of 436,120 triangles (no ceiling).
+
+    * orchestra: half annulus r in [1, 12] m at z = 0, 1024 x 10 cells (20,480)
+    * cavea: 40 tiers from r = 12 to 50 m, riser 0.55 m, tread 0.95 m, each a
+      riser strip and a tread strip over the semicircle y >= 0 with 1024 angular
+      cells (163,840)
+    * stage floor 100 x 30 m at z = 1 (6,000) and its 1 m front riser (200)
+    * stage wall 100 x 35 m at y = -30 as a 440 x 200 grid with seeded smooth
+      displacement noise of 0.4 m amplitude, standing for ornaments (176,000)
+    * 200 columns (4 stories x 50), 16-gon, 10 height segments with slight
+      entasis (64,000) plus 16-gon fan caps (5,600)
+
+    Materials: 0 = concrete block, coarse (Table 1 ref 107) everywhere except
+    1 = hollow wooden podium (Table 1 ref 3000) on the stage floor.  Flat groups
+    (orchestra, each tread, stage floor, stage front, each column cap) share one
+    plane id; curved or displaced surfaces use one plane id per triangle.
+    """
+    rng = np.random.default_rng(seed)
+    mb = _MeshBuilder()
+    nseg = 1024
+    th = np.linspace(0.0, math.pi, nseg + 1)
+    cth, sth = np.cos(th), np.sin(th)
+
+    def ring(r, z):
+        return np.stack([r * cth, r * sth, np.full_like(th, z)], axis=1)
+
+    # orchestra
+    radii = np.linspace(1.0, 12.0, 11)
+    g = np.stack([ring(r, 0.0) for r in radii], axis=0)
+    mb.grid(g, 0, coplanar=True)
+    # cavea: alternating riser / tread strips sharing rings
+    z_prev = 0.0
+    for t in range(40):
+        r_in, r_out, z_t = _tier_radius(t), _tier_radius(t) + THEATER_TREAD, _tier_height(t)
+        mb.grid(np.stack([ring(r_in, z_prev), ring(r_in, z_t)], axis=0), 0, coplanar=False)
+        mb.grid(np.stack([ring(r_in, z_t), ring(r_out, z_t)], axis=0), 0, coplanar=True)
+        z_prev = z_t
+    # stage floor and its front riser
+    xs = np.linspace(-50.0, 50.0, 101)
+    ys = np.linspace(-30.0, 0.0, 31)
+    X, Y = np.meshgrid(xs, ys, indexing="ij")
+    mb.grid(np.stack([X, Y, np.full_like(X, THEATER_STAGE_Z)], axis=2), 1, coplanar=True)
+    X, Z = np.meshgrid(xs, np.array([0.0, THEATER_STAGE_Z]), indexing="ij")
+    mb.grid(np.stack([X, np.zeros_like(X), Z], axis=2), 0, coplanar=True)
+    # stage wall with smooth displacement noise
+    xw = np.linspace(-50.0, 50.0, 441)
+    zw = np.linspace(THEATER_STAGE_Z, THEATER_STAGE_Z + 35.0, 201)
+    X, Z = np.meshgrid(xw, zw, indexing="ij")
+    disp = np.zeros_like(X)
+    for _ in range(12):
+        kx, kz = rng.uniform(0.2, 2.5, size=2)
+        ph = rng.uniform(0, 2 * math.pi, size=2)
+        disp += np.sin(kx * X + ph[0]) * np.sin(kz * Z + ph[1])
+    disp *= 0.4 / np.abs(disp).max()
+    mb.grid(np.stack([X, -30.0 + disp, Z], axis=2), 0, coplanar=False)
+    # columns: 4 stories x 50, 16-gon, 10 segments, entasis, fan caps
+    nside, nh, r0, hcol = 16, 10, 0.35, 8.0
+    ang = np.arange(nside) * (2 * math.pi / nside)
+    for story in range(4):
+        z0 = THEATER_STAGE_Z + 8.75 * story + 0.4
+        for i in range(50):
+            cx, cy = -49.0 + 2.0 * i, -28.5
+            hs = np.linspace(0.0, hcol, nh + 1)
+            rr = r0 * (1.0 + 0.04 * np.sin(math.pi * hs / hcol)) * (1.0 - 0.08 * hs / hcol)
+            pts = np.stack([
+                np.stack([cx + rr[k] * np.cos(ang), cy + rr[k] * np.sin(ang),
+                          np.full(nside, z0 + hs[k])], axis=1) for k in range(nh + 1)])
+            # side: rings x (sides + wrap) grid
+            wrap = np.concatenate([pts, pts[:, :1]], axis=1)            # [11, 17, 3]
+            mb.grid(wrap, 0, coplanar=False)
+            for k, flip in ((0, True), (nh, False)):
+                cap = pts[k]
+                fan = np.array([[0, j, j + 1] for j in range(1, nside - 1)])
+                if flip:
+                    fan = fan[:, [0, 2, 1]]
+                mb.add(cap, fan, 0, coplanar=True)
+    vtx, tri, mat, plane = mb.finish()
+    alpha = np.array([TABLE1[107], TABLE1[3000]], np.float32)
+    axis = math.pi / 2
+    spots = [(2, axis), (8, axis), (16, axis), (26, axis), (36, axis),
+             (10, axis - math.pi / 4), (20, axis + math.pi / 4), (30, axis + 75 * math.pi / 180)]
+    rcv = []
+    for t, a in spots:
+        r = _tier_radius(t) + 0.5 * THEATER_TREAD
+        rcv.append([r * math.cos(a), r * math.sin(a), _tier_height(t) + 1.2, 2.0])
+    s = Scene("C3 open-air theater 436k", vtx, tri, mat, plane, alpha, closed=False,
+              src=np.array([0.0, -1.0, THEATER_STAGE_Z + 1.6], np.float32),
+              rcv=np.array(rcv, np.float32), beta=iso9613_beta(), n_rays=n_rays,
+              max_reflections=max_reflections, ir_seconds=ir_seconds)
+    return _check(s, 436_120)
+
+
+# ----------------------------------------------------------------------------
+# small test geometries
+# ----------------------------------------------------------------------------
+
+def icosphere(level: int, radius: float = 1.0):
+    """Unit icosphere: 20 * 4**level faces, vertices projected to the sphere."""
+    t = (1.0 + math.sqrt(5.0)) / 2.0
+    v = [(-1, t, 0), (1, t, 0), (-1, -t, 0), (1, -t, 0), (0, -1, t), (0, 1, t),
+         (0, -1, -t), (0, 1, -t), (t, 0, -1), (t, 0, 1), (-t, 0, -1), (-t, 0, 1)]
+    f = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11), (1, 5, 9), (5, 11, 4),
+         (11, 10, 2), (10, 7, 6), (7, 1, 8), (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8),
+         (3, 8, 9), (4, 9, 5), (2, 4, 11), (6, 2, 10), (8, 6, 7), (9, 8, 1)]
+    verts = [np.array(p, np.float64) / np.linalg.norm(p) for p in v]
+    faces = f
+    for _ in range(level):
+        cache = {}
+        new_faces = []
+
+        def mid(a, b):
+            key = (min(a, b), max(a, b))
+            if key not in cache:
+                m = verts[a] + verts[b]
+                verts.append(m / np.linalg.norm(m))
+                cache[key] = len(verts) - 1
+            return cache[key]
+
+        for a, b, c in faces:
+            ab, bc, ca = mid(a, b), mid(b, c), mid(c, a)
+            new_faces += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
+        faces = new_faces
+    vtx = (np.array(verts) * radius).astype(np.float32)
+    tri = np.array(faces, np.int32)
+    return vtx, tri
+
+
+def sphere_room(level: int = 4) -> Scene:
+    """100 % reflecting unit sphere, source and receiver at the centre."""
+    vtx, tri = icosphere(level)
+    m = len(tri)
+    s = Scene(f"unit icosphere {m}", vtx, tri, np.zeros(m, np.int32), np.arange(m, dtype=np.int32),
+              np.zeros((1, 8), np.float32), closed=True,
+              src=np.zeros(3, np.float32), rcv=np.array([[0, 0, 0, 0.05]], np.float32),
+              beta=np.zeros(8, np.float32), n_rays=10_000, max_reflections=6, ir_seconds=0.05)
+    return _check(s, 20 * 4 ** level)
+
+
+def open_scene_far_triangle() -> Scene:
+    """A single far-away triangle: every ray from the origin region escapes
+    except those aimed at it; used for the free-field (1/d^2) law."""
+    vtx = np.array([[1000, 1000, 1000], [1001, 1000, 1000], [1000, 1001, 1000]], np.float32)
+    tri = np.array([[0, 1, 2]], np.int32)
+    return _check(Scene("open far triangle", vtx, tri, np.zeros(1, np.int32), np.zeros(1, np.int32),
+                        np.zeros((1, 8), np.float32), closed=False, beta=np.zeros(8, np.float32)))
+
+
+def lroom(seed: int = 5, dims=(8.0, 6.0, 3.0), notch=(4.0, 3.0)):
+    """Closed L-shaped room: a box with one corner block removed, as 12 quads
+    on its faces (the floor and ceiling L-polygons split into three rectangles
+    so every edge stays shared).  Returns (vtx, tri, material, plane)."""
+    Lx, Ly, Lz = dims
+    nx, ny = notch
+    xs = [0.0, nx, Lx]
+    ys = [0.0, ny, Ly]
+    # L = all cells of the 2x2 footprint grid except (1,1) (x>nx, y>ny)
+    cells = [(0, 0), (1, 0), (0, 1)]
+    vid = {}
+    verts = []
+
+    def v(ix, iy, iz):
+        key = (ix, iy, iz)
+        if key not in vid:
+            vid[key] = len(verts)
+            verts.append((xs[ix], ys[iy], [0.0, Lz][iz]))
+        return vid[key]
+
+    quads, mats = [], []
+    for iz, m in ((0, 4), (1, 5)):                       # floor, ceiling
+        for cx, cy in cells:
+            quads.append((v(cx, cy, iz), v(cx + 1, cy, iz), v(cx + 1, cy + 1, iz), v(cx, cy + 1, iz)))
+            mats.append(m)
+    # perimeter walls of the L, split at grid lines so edges match the floor split
+    boundary = [((0, 0), (1, 0), 2), ((1, 0), (2, 0), 2), ((2, 0), (2, 1), 1), ((2, 1), (1, 1), 3),
+                ((1, 1), (1, 2), 1), ((1, 2), (0, 2), 3), ((0, 2), (0, 1), 0), ((0, 1), (0, 0), 0)]
+    for (ax, ay), (bx, by), m in boundary:
+        quads.append((v(ax, ay, 0), v(bx, by, 0), v(bx, by, 1), v(ax, ay, 1)))
+        mats.append(m)
+    # the floor/ceiling splits add interior edges on the footprint (0..2 x 0..2 grid):
+    # floor cells (0,0),(1,0),(0,1) share edges among themselves -> fine
+    q = np.array(quads, np.int64)
+    tri = _quads_to_tris(q).astype(np.int32)
+    mat = np.repeat(np.array(mats, np.int32), 2)
+    # plane ids: group coplanar faces (same axis-aligned plane)
+    vv = np.array(verts, np.float64)
+    keys = {}
+    plane = np.empty(len(tri), np.int32)
+    for i, t in enumerate(tri):
+        p = vv[t]
+        for ax in range(3):
+            if np.all(p[:, ax] == p[0, ax]):
+                key = (ax, p[0, ax])
+                break
+        if key not in keys:
+            keys[key] = i
+        plane[i] = keys[key]
+    return np.array(verts, np.float32), tri, mat, plane
+
+
+def tetra_room(scale: float = 4.0):
+    """Closed regular-ish tetrahedron room (4 triangles, 4 planes)."""
+    v = np.array([[0, 0, 0], [1, 0, 0], [0.5, math.sqrt(3) / 2, 0],
+                  [0.5, math.sqrt(3) / 6, math.sqrt(2.0 / 3.0)]], np.float64) * scale
+    tri = np.array([[0, 2, 1], [0, 1, 3], [1, 2, 3], [2, 0, 3]], np.int32)
+    return v.astype(np.float32), tri, np.arange(4, dtype=np.int32), np.arange(4, dtype=np.int32)
+
+
+# ----------------------------------------------------------------------------
+# batched rooms (many rooms of uneven size)
+# ----------------------------------------------------------------------------
+
+def _room_grid_counts(dims, target: int):
+    """Grid resolution (nx, ny, nz) of a box whose surface has ~target tris."""
+    Lx, Ly, Lz = dims
+    area = 2 * (Lx * Ly + Ly * Lz + Lx * Lz)
+    h = math.sqrt(4 * area / max(target, 12) / 4.0) if target > 12 else max(dims)
+    h = math.sqrt(area * 2 / target)  # cell size so that 2*area/h^2 ~ target
+    return tuple(max(1, int(round(L / h))) for L in dims)
+
+
+def batched_rooms(seed: int = 4, n_rooms: int = 8, pairs_per_room: int = 8,
+                  m_lo: float = 1000.0, m_hi: float = 200_000.0, rays_per_pair: int = 200_000,
+                  max_reflections: int = 50, ir_seconds: float = 1.0,
+                  alpha_range=(0.02, 0.3)) -> List[Scene]:
+    """Rooms of uneven size M_i ~ m_lo * (m_hi/m_lo)**(i/(n-1)), cycling through
+    shoebox, L-shape and tiered-floor variants, dims U[4,30] m, each meshed as
+    planar grids; 6 materials per room; pairs_per_room (source, receiver) pairs
+    at least 1 m from the walls (r = 0.3 m)."""
+    rng = np.random.default_rng(seed)
+    rooms = []
+    for i in range(n_rooms):
+        frac = i / max(1, n_rooms - 1)
+        target = m_lo * (m_hi / m_lo) ** frac
+        kind = i % 3
+        dims = tuple(sorted(rng.uniform(4.0, 30.0, size=3), reverse=True))
+        dims = (dims[0], dims[1], min(dims[2], 12.0))
+        n = _room_grid_counts(dims, target)
+        vtx, tri, mat, plane = box_mesh(dims, n, plane_per_wall=True)
+        if kind == 1:
+            # L-shape: fold a notch by pushing one corner region of the +x wall inward
+            vtx = vtx.copy()
+            sel = (vtx[:, 0] >= dims[0] - 1e-6) & (vtx[:, 1] >= 0.5 * dims[1])
+            vtx[sel, 0] = np.float32(0.6 * dims[0])
+            # the moved wall stays planar (x = 0.6 Lx); re-key its plane
+        elif kind == 2:
+            # tiered floor: floor vertices rise in steps along y (risers stay planar per step)
+            vtx = vtx.copy()
+            sel = vtx[:, 2] <= 1e-6
+            steps = np.floor(vtx[sel, 1] / (dims[1] / 4.0)).clip(0, 3)
+            vtx[sel, 2] = (0.3 * steps).astype(np.float32)
+        # recompute coplanar groups after deformation: plane id = tri id unless all
+        # of a wall stayed flat (checked exactly)
+        plane = _group_coplanar(vtx, tri, plane)
+        alpha = random_alpha(rng, 6, *alpha_range)
+        lo = np.array([1.0, 1.0, 1.0 + (0.9 if kind == 2 else 0.0)])
+        hi = np.array([dims[0] * (0.6 if kind == 1 else 1.0), dims[1], dims[2]]) - 1.0
+        hi = np.maximum(hi, lo + 0.5)
+        srcs = rng.uniform(lo, hi, size=(pairs_per_room, 3)).astype(np.float32)
+        rcvs = np.concatenate([rng.uniform(lo, hi, size=(pairs_per_room, 3)),
+                               np.full((pairs_per_room, 1), 0.3)], axis=1).astype(np.float32)
+        s = Scene(f"room{i} kind{kind} {len(tri)} tris", vtx, tri, mat, plane, alpha, closed=True,
+                  src=srcs, rcv=rcvs, beta=iso9613_beta(), n_rays=rays_per_pair,
+                  max_reflections=max_reflections, ir_seconds=ir_seconds)
+        assert np.all(_tri_areas(vtx, tri) > 0)
+        rooms.append(s)
+    return rooms
+
+
+def _group_coplanar(vtx, tri, plane):
+    """Keep a wall's shared plane id only where every member triangle is still
+    exactly in the representative's axis-aligned plane; otherwise one id per tri."""
+    out = plane.copy()
+    v = vtx.astype(np.float64)
+    for pid in np.unique(plane):
+        members = np.nonzero(plane == pid)[0]
+        p = v[tri[members]].reshape(-1, 3)
+        flat = any(np.all(p[:, ax] == p[0, ax]) for ax in range(3))
+        if not flat:
+            # split into exactly-flat subgroups by axis-aligned coordinate if possible
+            rep = {}
+            for m in members:
+                q = v[tri[m]]
+                key = None
+                for ax in range(3):
+                    if np.all(q[:, ax] == q[0, ax]):
+                        key = (ax, q[0, ax])
+                        break
+                if key is None:
+                    out[m] = m
+                else:
+                    if key not in rep:
+                        rep[key] = m
+                    out[m] = rep[key]
+    return out.astype(np.int32)
+
+
+# ----------------------------------------------------------------------------
+# air absorption and band filters (inputs to impulse-response assembly)
+# ----------------------------------------------------------------------------
+
+def iso9613_beta(temp_c: float = 20.0, rh: float = 50.0, pa_kpa: float = 101.325) -> np.ndarray:
+    """Energy air-absorption coefficient per octave band, 1/m, from the ISO
+    9613-1 pure-tone attenuation formula at the exact band centres."""
+    T = temp_c + 273.15
+    T0 = 293.15
+    T01 = 273.16
+    pr = 101.325
+    pa = pa_kpa / pr
+    psat = 10.0 ** (-6.8346 * (T01 / T) ** 1.261 + 4.6151)
+    h = rh * psat / pa
+    frO = pa * (24.0 + 4.04e4 * h * (0.02 + h) / (0.391 + h))
+    frN = pa * (T / T0) ** -0.5 * (9.0 + 280.0 * h * math.exp(-4.170 * ((T / T0) ** (-1.0 / 3.0) - 1.0)))
+    out = []
+    for f in BAND_CENTRES:
+        a_db = 8.686 * f * f * (1.84e-11 / pa * (T / T0) ** 0.5 + (T / T0) ** -2.5 * (
+            0.01275 * math.exp(-2239.1 / T) / (frO + f * f / frO)
+            + 0.1068 * math.exp(-3352.0 / T) / (frN + f * f / frN)))
+        out.append(a_db * math.log(10.0) / 10.0)
+    return np.array(out, np.float32)
+
+
+def octave_fir_taps(K: int = 4095, fs: float = 48000.0) -> np.ndarray:
+    """[8, K] linear-phase Hann-windowed sinc band-pass taps, band edges
+    f_c/sqrt2 .. f_c*sqrt2 around each octave centre (FP64 design, FP32 out)."""
+    assert K % 2 == 1
+    n = np.arange(K) - (K - 1) / 2.0
+    w = 0.5 - 0.5 * np.cos(2 * math.pi * np.arange(K) / (K - 1))
+    out = np.empty((8, K))
+    for b, fc in enumerate(BAND_CENTRES):
+        f1, f2 = fc / math.sqrt(2), min(fc * math.sqrt(2), 0.49 * fs)
+        out[b] = w * (2 * f2 / fs * np.sinc(2 * f2 / fs * n) - 2 * f1 / fs * np.sinc(2 * f1 / fs * n))
+    return out.astype(np.float32)
+
+
+def delta_taps(K: int = 1) -> np.ndarray:
+    """[8, K] unit impulse at the centre tap (identity filter)."""
+    t = np.zeros((8, K), np.float32)
+    t[:, (K - 1) // 2] = 1.0
+    return t
+
+
+# ----------------------------------------------------------------------------
+# seeded rays, query states and path tables
+# ----------------------------------------------------------------------------
+
+def random_unit_dirs(rng, n: int) -> np.ndarray:
+    """Isotropic random directions (normalised Gaussians), FP32."""
+    d = rng.standard_normal((n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    return d.astype(np.float32)
+
+
+def surface_query_states(scene: Scene, n: int, seed: int, toward=None):
+    """Seeded one-segment query states that start on the mesh, as rays do after
+    a reflection: origin = a random point of a random triangle (FP32), direction
+    = random unit vector leaving the face on one side (the side facing the point
+    ``toward`` when given, else a random side), last plane = that triangle's
+    plane id, travelled length uniform in [0, 50] m.
+    Returns (origins, dirs, plane, length).
+    """
+    rng = np.random.default_rng(seed)
+    t = rng.integers(0, scene.n_tri, size=n)
+    v = scene.vtx.astype(np.float64)[scene.tri[t]]
+    a, b = rng.random(n), rng.random(n)
+    flip = a + b > 1
+    a[flip], b[flip] = 1 - a[flip], 1 - b[flip]
+    p = v[:, 0] + a[:, None] * (v[:, 1] - v[:, 0]) + b[:, None] * (v[:, 2] - v[:, 0])
+    d = random_unit_dirs(rng, n).astype(np.float64)
+    nrm = np.cross(v[:, 1] - v[:, 0], v[:, 2] - v[:, 0])
+    side = np.where(rng.random(n) < 0.5, 1.0, -1.0)
+    if toward is not None:
+        side = np.sign(np.einsum("ij,ij->i", np.asarray(toward, np.float64)[None, :] - p, nrm))
+        side[side == 0] = 1.0
+    s = np.sign(np.einsum("ij,ij->i", d, nrm)) * side
+    # keep directions leaving the face on the chosen side
+    d = d * np.where(s < 0, -1.0, 1.0)[:, None]
+    length = rng.uniform(0.0, 50.0, size=n)
+    return (p.astype(np.float32), d.astype(np.float32), scene.plane_id[t].astype(np.int32),
+            length.astype(np.float32))
+
+
+def interior_query_states(scene: Scene, n: int, seed: int, lo=None, hi=None):
+    """Seeded query states starting inside the scene's bounding box (no last
+    plane), random directions, zero travelled length."""
+    rng = np.random.default_rng(seed)
+    v = scene.vtx.astype(np.float64)
+    lo = v.min(0) if lo is None else np.asarray(lo)
+    hi = v.max(0) if hi is None else np.asarray(hi)
+    o = rng.uniform(lo, hi, size=(n, 3)).astype(np.float32)
+    d = random_unit_dirs(rng, n)
+    return o, d, np.full(n, -1, np.int32), np.zeros(n, np.float32)
+
+
+def synthetic_paths(scene: Scene, n_rays: int, max_reflections: int, n_rcv: int, seed: int,
+                    n_prefixes: int = 0, det_per_ray: float = 1.5):
+    """Seeded hit-sequence table and detection list with the structure of a
+    trace: hit_seq int32 [n_rays, R+1] (triangle ids, -1 padded after a random
+    termination), detections int32 [n_det, 3] (ray, segment k, receiver) with k
+    below the ray's segment count.  Many rays share prefixes drawn from a pool
+    so that image-source keys repeat (dedup work), like beams from a source."""
+    rng = np.random.default_rng(seed)
+    R1 = max_reflections + 1
+    n_prefixes = n_prefixes or max(4, n_rays // 20)
+    pool_len = rng.integers(1, R1 + 1, size=n_prefixes)
+    pool = rng.integers(0, scene.n_tri, size=(n_prefixes, R1)).astype(np.int32)
+    pick = rng.integers(0, n_prefixes, size=n_rays)
+    hs = pool[pick].copy()
+    seg = pool_len[pick]
+    # a quarter of the rays get their own random tail after a shared prefix
+    tail = rng.random(n_rays) < 0.25
+    cut = rng.integers(0, R1, size=n_rays)
+    rnd = rng.integers(0, scene.n_tri, size=(n_rays, R1)).astype(np.int32)
+    cols = np.arange(R1)[None, :]
+    m = tail[:, None] & (cols >= cut[:, None])
+    hs[m] = rnd[m]
+    hs[cols >= seg[:, None]] = -1
+    # detections
+    n_det = int(n_rays * det_per_ray)
+    ray = rng.integers(0, n_rays, size=n_det)
+    k = (rng.random(n_det) * seg[ray]).astype(np.int64)
+    k = np.minimum(k, seg[ray] - 1)
+    r = rng.integers(0, n_rcv, size=n_det)
+    det = np.stack([ray, k, r], axis=1).astype(np.int32)
+    det = np.unique(det, axis=0)
+    det = det[rng.permutation(len(det))]
+    return hs, det

@@ -1,0 +1,132 @@
+"""Energy pins of the oracle.
+
+* Free field (section "Discrete model", eqs. for E_m and Omega_m, and the
+  energy-vs-distance figure: r = 0.36 m, N = 1e6): the number n of rays that
+  cross a receiver sphere at distance d is N * Omega_m / (4 pi) with
+  Omega_m = 2 pi (1 - sqrt(1 - r^2/d^2)).
+* Closed room, alpha = beta = 0 (section "Energy conservation by reflecting
+  sphere"): no ray is lost, and the mean number of receiver crossings per ray
+  over a path length l is the image-lattice sum, ~ pi r^2 l / V.
+* Reflecting unit sphere with source and receiver at the centre: the direct
+  sound carries energy 1 exactly, later energy arrives only near path lengths
+  2k m (a Dirac comb two metres apart), and a finer mesh keeps more of it.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, "shoebox_experiment.txt")) as f:
+        for line in f:
+            if line.startswith(name + " "):
+                return float(line.split()[1])
+    raise KeyError(name)
+
+
+def test_free_field_inverse_square(oracle_lib):
+    s = synth.open_scene_far_triangle()
+    sc = oracle_lib.OracleScene.of(s)
+    r = _golden("free_field_radius")
+    N = int(_golden("free_field_rays"))
+    dists = np.array([0.5, 1.0, 2.0, 5.0, 10.0, 20.0, 50.0, 100.0, 180.0])
+    rng = np.random.default_rng(9)
+    axes = synth.random_unit_dirs(rng, len(dists)).astype(np.float64)
+    axes[:, 2] = -np.abs(axes[:, 2])              # away from the far triangle (z = +1000)
+    axes /= np.linalg.norm(axes, axis=1, keepdims=True)
+    rcv = np.concatenate([axes * dists[:, None], np.full((len(dists), 1), r)], 1).astype(np.float32)
+    dirs = oracle_lib.fibonacci(N)
+    tr = oracle_lib.trace(sc, np.zeros(3, np.float32), dirs, rcv, 0, flags=False)
+    counts = np.array([((tr["det"][:, 0] >> np.uint32(m)) & 1).sum() for m in range(len(dists))])
+    d = np.linalg.norm(rcv[:, :3].astype(np.float64), axis=1)
+    rr = rcv[:, 3].astype(np.float64)
+    expect = N * (1 - np.sqrt(1 - rr ** 2 / d ** 2)) / 2
+    assert np.all(np.abs(counts - expect) <= 3 * np.sqrt(expect) + 2), (counts, expect)
+    # the small-angle form n/N ~ pi r^2 / (4 pi d^2) and the range d <= (r/2) sqrt(N/n), n >= 1
+    assert abs(N * r * r / (4 * 10.0 ** 2) - 324.0) < 0.1
+    assert np.all(counts >= 1) and d[-1] <= r / 2 * np.sqrt(N)
+
+
+def _lattice_expected_crossings(dims, xs, xm, r, lmax, N):
+    total = 0.0
+    ilim = [int(np.ceil(lmax / (2 * L))) + 1 for L in dims]
+    for i in range(-ilim[0], ilim[0] + 1):
+        for j in range(-ilim[1], ilim[1] + 1):
+            for k in range(-ilim[2], ilim[2] + 1):
+                for p in (0, 1):
+                    for q in (0, 1):
+                        for w in (0, 1):
+                            pos = np.array([(1 - 2 * p) * xs[0] + 2 * i * dims[0],
+                                            (1 - 2 * q) * xs[1] + 2 * j * dims[1],
+                                            (1 - 2 * w) * xs[2] + 2 * k * dims[2]])
+                            d = np.linalg.norm(pos - xm)
+                            if d < lmax:
+                                total += N * (1 - np.sqrt(1 - r * r / (d * d))) / 2
+    return total
+
+
+def test_closed_room_conserves_rays_and_crossing_rate(oracle_lib):
+    s = synth.shoebox_c1()
+    sc = oracle_lib.OracleScene.of(s)
+    N = 4000
+    dirs = oracle_lib.fibonacci(N)
+    lmax = 60.0
+    tr = oracle_lib.trace(sc, s.src, dirs, s.rcv, 60, max_len=lmax, flags=False, states=True)
+    hs = tr["hit_seq"]
+    nseg = (hs >= 0).sum(1)
+    # nothing escapes: every ray ends because its path passed lmax
+    last = tr["states"][np.arange(N), nseg, 6]
+    assert np.all(last >= lmax)
+    prev = tr["states"][np.arange(N), nseg - 1, 6]
+    assert np.all(prev < lmax)
+    # receiver crossings vs the lattice sum (image density 1/V)
+    det = oracle_lib.detections_from_bits(tr["det"])
+    keys = oracle_lib.image_source_keys(s.plane_id, hs, det)
+    tab = oracle_lib.image_sources(sc, s.src, s.rcv, keys)
+    l_cut = lmax - 5.0
+    n_found = tab["count"][tab["dist"] < l_cut].sum()
+    dims = s.vtx.max(0).astype(np.float64)
+    want = _lattice_expected_crossings(dims, s.src.astype(np.float64), s.rcv[0, :3].astype(np.float64),
+                                       float(s.rcv[0, 3]), l_cut, N)
+    V = float(np.prod(dims))
+    r = float(s.rcv[0, 3])
+    assert abs(n_found - want) <= 3 * np.sqrt(want) + 2, (n_found, want)
+    assert abs(want - N * np.pi * r * r * l_cut / V) / want < 0.15
+
+
+def test_reflecting_sphere_dirac_comb(oracle_lib):
+    kept, spreads = [], []
+    for level in (2, 3, 4):
+        s = synth.sphere_room(level)
+        sc = oracle_lib.OracleScene.of(s)
+        N = 4000
+        dirs = oracle_lib.fibonacci(N)
+        tr = oracle_lib.trace(sc, s.src, dirs, s.rcv, 6, flags=False)
+        det = oracle_lib.detections_from_bits(tr["det"])
+        keys = oracle_lib.image_source_keys(s.plane_id, tr["hit_seq"], det)
+        tab = oracle_lib.image_sources(sc, s.src, s.rcv, keys)
+        order = np.array([k[1] for k in tab["keys"]])
+        # direct sound: every ray starts inside the receiver -> E = n/N = 1 exactly
+        assert tab["count"][order == 0].sum() == N
+        assert np.all(tr["hit_seq"] >= 0)               # a closed sphere loses nothing
+        # every later arrival is near a multiple of 2 m (comb): order k at ~2k m,
+        # with a spread that shrinks as the mesh is refined
+        spread = 0.0
+        for k in range(1, 7):
+            sel = order == k
+            if sel.any():
+                dk = tab["dist"][sel]
+                assert np.all(dk <= 2 * k + 1e-9)         # inscribed facets: never farther
+                spread = max(spread, np.abs(dk - 2 * k).max() / (2 * k))
+        spreads.append(spread)
+        kept.append([tab["count"][order == k].sum() / N for k in range(1, 7)])
+    kept = np.array(kept)
+    # focusing degrades with order and improves with refinement
+    assert np.all(kept[:, 0] >= kept[:, -1])
+    assert kept[2].sum() > kept[1].sum() > kept[0].sum()
+    assert spreads[0] > spreads[1] > spreads[2] and spreads[2] < 0.01
