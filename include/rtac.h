@@ -1,0 +1,228 @@
+/*
+ * rtac.h -- C-ABI of librtac, a gfx950 (MI355X) implementation of the
+ * data-parallel hot path of the hybrid ray-tracing / image-source room
+ * acoustics method of Aussal & Gueguen, "Open-source platforms for fast room
+ * acoustic simulations in complex structures" (2018).
+ *
+ * Conventions (every entry point):
+ *   - Array pointers are DEVICE pointers (HIP global memory) unless the
+ *     parameter name ends in _host.  Layouts are row-major, C-contiguous.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls enqueue kernels on it and return without waiting, except
+ *     rt_build_tree, which synchronises once to validate the mesh.
+ *   - The caller owns every input and output buffer; the library owns the
+ *     rt_scene object and the scratch memory attached to it.  Scratch grows
+ *     on demand (hipMalloc outside any kernel) and is freed by
+ *     rt_scene_destroy.  Calls sharing one scene must be ordered on one
+ *     stream.
+ *   - Return value: RT_OK (0) or a negative status; rt_last_error() gives a
+ *     thread-local message.  No call throws or aborts.  Outputs that the
+ *     device can only size after the fact (detections, image sources) are
+ *     never written past their capacity: the required count is stored in the
+ *     device counter instead and the caller re-runs with a larger buffer.
+ *   - Integers are int32, counts int64.  Triangle ids, plane ids and ray ids
+ *     are the caller's indices (original order).
+ */
+#ifndef RTAC_H
+#define RTAC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    RT_OK = 0,
+    RT_EINVAL = -1,      /* bad argument or invalid mesh                       */
+    RT_ENOMEM = -2,      /* device allocation failed                           */
+    RT_ECAPACITY = -3,   /* reported only by host-side size checks             */
+    RT_EHIP = -4,        /* a HIP runtime call failed                          */
+    RT_EDEGENERATE = -5  /* zero-area triangle or non-finite vertex            */
+};
+
+typedef struct rt_scene rt_scene;
+
+/* Tree-build options.  leaf_size: largest number of triangles per leaf
+ * (1 = one element per leaf, as in the paper's tree; at most 8). */
+typedef struct {
+    int32_t leaf_size;
+} rt_build_params;
+
+/*
+ * rt_build_tree -- scene ingest and acceleration tree (section "Tree-base
+ * acceleration": a mother box containing all elements is split recursively
+ * into two daughter boxes down to leaves of one element; built once, in
+ * O(M log M), before any ray is traced).
+ *
+ * The tree is a binary radix tree over the 63-bit Morton codes of the
+ * triangle centroids (each split separates the elements of one Morton
+ * prefix: a spatial median split cycling through the axes), collapsed into
+ * a 4-wide tree for traversal.  Nearest hits do not depend on the tree.
+ *
+ *   vtx       [n_vtx, 3] float   vertex coordinates (m)
+ *   tri       [n_tri, 3] int32   vertex indices of each flat triangle
+ *   material  [n_tri]    int32   material index (>= 0) per triangle
+ *   plane_id  [n_tri]    int32   coplanar group of each triangle, 0 <= id <
+ *                                n_tri, or NULL (= triangle id).  The group's
+ *                                representative is its lowest-index triangle;
+ *                                its unit normal and first vertex define the
+ *                                plane used for reflection and image sources.
+ *                                Members must lie in that plane (1e-9 of the
+ *                                bounding-box diagonal) and share its material.
+ *   params    may be NULL (defaults).
+ *   out_scene receives the scene handle (host pointer).
+ * Errors: RT_EINVAL (index out of range, plane group not coplanar or of mixed
+ * material, n_tri < 1), RT_EDEGENERATE (zero-area triangle, NaN/Inf vertex),
+ * RT_ENOMEM, RT_EHIP.  Synchronises `stream` once.
+ */
+int rt_build_tree(const float* vtx, int64_t n_vtx, const int32_t* tri, int64_t n_tri,
+                  const int32_t* material, const int32_t* plane_id, const rt_build_params* params,
+                  void* stream, rt_scene** out_scene);
+
+/* Frees the scene and its scratch (synchronises the device). */
+int rt_scene_destroy(rt_scene* scene);
+
+/* Host-side facts about a built scene: info_host[0] = n_tri, [1] = number of
+ * materials (max material + 1), [2] = 4-wide tree nodes, [3] = tree depth,
+ * [4] = leaf size; diag_host[0] = bounding-box diagonal D (m). */
+int rt_scene_info(const rt_scene* scene, int64_t* info_host, double* diag_host);
+
+/*
+ * rt_fibonacci_directions -- omnidirectional source sampling (section
+ * "Discrete model": rays leave the source along a uniform sampling of the
+ * unit sphere, e.g. by Fibonacci's rule, each with energy 4 pi / N).
+ *   dirs [n, 3] float out:  z_i = 1 - (2i+1)/n,  phi_i = i pi (3 - sqrt 5) mod 2pi,
+ *   u_i = (sqrt(1 - z_i^2) cos phi_i, sqrt(1 - z_i^2) sin phi_i, z_i), evaluated in
+ *   FP64 and rounded once to FP32.
+ */
+int rt_fibonacci_directions(int64_t n, float* dirs, void* stream);
+
+/* Trace options. */
+typedef struct {
+    int32_t max_reflections;   /* R >= 0: segments 0..R are traced (R reflections)           */
+    float max_path_length;     /* > 0: a ray stops once its travelled length reaches it        */
+    int32_t record_states;     /* nonzero: write each segment's input state to `states`        */
+    int32_t fetch_threshold;   /* 0 = default; lanes idle before a wave fetches new rays       */
+    int32_t shade_threshold;   /* 0 = default; finished queries before a wave shades them      */
+    int32_t blocks_per_cu;     /* 0 = default; persistent workgroups per compute unit          */
+} rt_trace_params;
+
+/*
+ * rt_trace_rays -- specular ray propagation with receiver detection
+ * (sections "Presence of an obstacle", "Standard algorithm" and "Tree-base
+ * acceleration").  For each ray and each segment k = 0..R:
+ *   - nearest hit: minimal delta > 0 of o + delta u over the triangles with
+ *     0 <= lambda, mu and lambda + mu <= 1, skipping the plane of the previous
+ *     reflection; exact FP32 ties go to the lowest triangle id (watertight
+ *     FP32 ray/triangle test, 4-wide tree traversal);
+ *   - detection: receiver m is crossed when the segment [0, delta_hit]
+ *     (unbounded on escape) comes within its radius of its centre (closed
+ *     ball, FP64; the sphere is transparent);
+ *   - reflection: u' = u - 2 (u.n) n with the plane's unit normal,
+ *     o' = o + delta u, L' = L + delta |u| (FP64, rounded to FP32);
+ *   - the ray stops after segment R, once L' >= max_path_length, or when it
+ *     hits nothing (open air: eliminated).
+ *
+ *   src_host    [3] float host  source; used when origins == NULL
+ *   origins     [n_rays, 3] float or NULL  per-ray start point
+ *   dirs        [n_rays, 3] float           start direction (not normalised by the library)
+ *   start_plane [n_rays] int32 or NULL      plane excluded from segment 0 (-1 none)
+ *   start_len   [n_rays] float or NULL      travelled length at the start (0)
+ *   rcv         [n_rcv, 4] float            receiver spheres (x, y, z, r); n_rcv <= 32
+ *   hit_seq     [n_rays, R+1] int32 out     triangle id ending segment k; -1 on escape
+ *                                           and after the ray stopped
+ *   det         [det_cap, 3] int32 out      detections (ray, k, receiver), any order
+ *   counters    [4] int64 out (device)      [0] detections (may exceed det_cap: then
+ *                                           only det_cap rows were written), [1] queries
+ *                                           (ray-segments traced), [2] escapes,
+ *                                           [3] device error word (0 = none)
+ *   states      [n_rays, R+2, 8] float or NULL   when record_states: input state
+ *                                           (o, u, L, last plane as int bits) of each
+ *                                           segment, and after the last reflection
+ * The counters are overwritten (not accumulated).
+ */
+int rt_trace_rays(const rt_scene* scene, const float* src_host, const float* origins, const float* dirs,
+                  const int32_t* start_plane, const float* start_len, int64_t n_rays, const float* rcv,
+                  int32_t n_rcv, const rt_trace_params* params, int32_t* hit_seq, int32_t* det,
+                  int64_t det_cap, int64_t* counters, float* states, void* stream);
+
+/*
+ * rt_collect_image_sources -- image sources from detected rays (section
+ * "Image-sources": rays reaching the receiver are retro-propagated and focus
+ * on point image sources; each carries n rays).  Key of a detection
+ * (ray, k, m): (m, k, plane ids of the ray's hits on segments 0..k-1).  Keys
+ * are hashed, sorted and deduplicated with a full comparison; n = number of
+ * detections per key.  Position: the source mirrored through the key's
+ * planes in order (FP64); distance to the receiver centre (FP64).
+ *
+ *   src_host  [3] float host; hit_seq [n_rays, R+1]; det [det_cap, 3]
+ *   n_det     device int64 (e.g. trace counters[0]); rows beyond min(n_det,
+ *             det_cap) are ignored
+ *   is_key    [is_cap, R+2] int32 out: (m, k, planes..., -1 padding)
+ *   is_count  [is_cap] int32 out;  is_pos [is_cap, 3] double out;
+ *   is_dist   [is_cap] double out; n_is: device int64 out (may exceed is_cap:
+ *             then only is_cap rows were written).  Row order: deterministic
+ *             (by key hash), not part of the contract.
+ */
+int rt_collect_image_sources(const rt_scene* scene, const float* src_host, const float* rcv, int32_t n_rcv,
+                             const int32_t* hit_seq, int64_t n_rays, int32_t max_reflections,
+                             const int32_t* det, int64_t det_cap, const int64_t* n_det, int32_t* is_key,
+                             int32_t* is_count, double* is_pos, double* is_dist, int64_t is_cap,
+                             int64_t* n_is, void* stream);
+
+/*
+ * rt_assemble_ir -- impulse response from the image sources (section
+ * "Image-sources": E_s(f) = n/N exp(-beta(f) d_s) prod_j (1 - alpha_j(f));
+ * arrival time d_s / c; pressure p = sqrt(E); FIR filters over 8 octave
+ * bands, abstract).  Per receiver r and band b:
+ *   hist[r,b,s]    = sum of E_s(b) over image sources with floor(d_s fs / c) = s < L
+ *                    (FP64 sums in a fixed order, rounded to float)
+ *   band_ir[r,b,:] = 'same' FIR of sqrt(hist[r,b,:]) with taps fir[b, :] (K odd):
+ *                    y[n] = sum_j fir[b,j] p[n + (K-1)/2 - j]
+ *   ir[r,:]        = sum_b band_ir[r,b,:];   band_energy[r,b] = sum_s hist[r,b,s]
+ *   is_key/is_count/is_dist/n_is as written by rt_collect_image_sources;
+ *   alpha [n_mat, 8] float; beta [8] float (1/m, energy); fir [8, K] float.
+ *   Outputs: band_energy [n_rcv, 8], hist [n_rcv, 8, L], band_ir [n_rcv, 8, L],
+ *   ir [n_rcv, L], all float.
+ */
+int rt_assemble_ir(const rt_scene* scene, const int32_t* is_key, const int32_t* is_count,
+                   const double* is_dist, const int64_t* n_is, int64_t is_cap, int32_t max_reflections,
+                   int64_t n_rays, int32_t n_rcv, const float* alpha, const float* beta, float c, float fs,
+                   int64_t L, const float* fir, int32_t K, float* band_energy, float* hist, float* band_ir,
+                   float* ir, void* stream);
+
+/*
+ * rt_band_energy_adjoint -- gradient of band energies with respect to the
+ * per-material absorption (the energy of an image source is a polynomial in
+ * alpha, eq. for E_s).  For an image source with c_m reflections on material m:
+ *   dE_s(b)/dalpha[m,b] = -n/N e^{-beta_b d_s} c_m (1 - alpha[m,b])^(c_m - 1)
+ *                         prod_{m' != m} (1 - alpha[m',b])^(c_m')
+ * grad_alpha[m,b] = sum_r grad_band_energy[r,b] * sum_{s of r, bin < L} dE_s(b)/dalpha[m,b].
+ *   grad_band_energy [n_rcv, 8] float; grad_alpha [n_mat, 8] float out
+ *   (overwritten).  Deterministic (fixed-order FP64 reduction).
+ */
+int rt_band_energy_adjoint(const rt_scene* scene, const int32_t* is_key, const int32_t* is_count,
+                           const double* is_dist, const int64_t* n_is, int64_t is_cap,
+                           int32_t max_reflections, int64_t n_rays, int32_t n_rcv, const float* alpha,
+                           int32_t n_mat, const float* beta, float c, float fs, int64_t L,
+                           const float* grad_band_energy, float* grad_alpha, void* stream);
+
+/* Test hook for the exact-grouping path of rt_collect_image_sources: keep
+ * only the low `bits` bits (1..64, default 64) of the 64-bit key hash so that
+ * distinct keys collide.  Process-wide; not thread-safe with concurrent
+ * collect calls.  Grouping stays exact at any setting (full-key comparison);
+ * only speed changes. */
+int rt_debug_set_hash_bits(int bits);
+
+/* Thread-local message describing the last non-OK status of this thread. */
+const char* rt_last_error(void);
+
+/* Library version string. */
+const char* rt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RTAC_H */

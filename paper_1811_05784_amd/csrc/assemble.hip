@@ -1,0 +1,388 @@
+// Impulse response from image sources (rt_assemble_ir) and the absorption
+// adjoint (rt_band_energy_adjoint).
+//
+// Energy of an image source per octave band (eq. for E_s with air
+// absorption): n/N exp(-beta d) prod_j (1 - alpha_j), FP64.  Arrival bin
+// floor(d fs / c).  The histogram is built without floating-point atomics:
+// sources are sorted by (receiver, bin) and every bin is summed by one thread
+// in sorted order, so results are bitwise reproducible.  Pressure sqrt(E) is
+// taken per bin and filtered per band.
+//
+// The 'same'-mode FIR y[n] = sum_j h[j] x[n + c - j] (c = (K-1)/2) runs on
+// the FP32 matrix cores as a Toeplitz x Hankel product: a 16x16 output tile
+// Y[i][q] = y[n0 + i + 16 q] = sum_kk A[i][kk] B[kk][q] with
+// A[i][kk] = h[i + K - 1 - kk] and B[kk][q] = x[n0 + 16 q + kk - c].  Taps
+// and the signal window (sqrt applied on load) are staged in LDS; the window
+// is stored 20 floats per 16 samples so that the 64 lanes of one B fragment
+// hit 64 different banks.
+#include "common.h"
+
+namespace rtac {
+
+namespace {
+
+struct IsArgs {
+    const int32_t* key;
+    const int32_t* count;
+    const double* dist;
+    const int64_t* n_is;
+    int64_t is_cap;
+    int32_t R1;
+    int64_t n_rays;
+    int32_t n_rcv;
+    const float* alpha;
+    const float* beta;
+    const int32_t* plane_mat;
+    int64_t n_tri;
+    double c, fs;
+    int64_t L;
+    uint64_t invalid;   // sort key of sources outside the IR (n_rcv * L)
+};
+
+__device__ inline int64_t is_count_of(const IsArgs& a) {
+    int64_t n = *a.n_is;
+    if (n < 0) n = 0;
+    return n > a.is_cap ? a.is_cap : n;
+}
+
+// Energy per band and (receiver, bin) sort key; invalid / late -> a.invalid.
+__global__ void k_is_energy(IsArgs a, double* __restrict__ E, uint64_t* __restrict__ skey) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= is_count_of(a)) return;
+    const int32_t* row = a.key + i * (int64_t)(a.R1 + 1);
+    const int32_t m = row[0], k = row[1];
+    const double d = a.dist[i];
+    double e[8];
+    const double base = (double)a.count[i] / (double)a.n_rays;
+    for (int b = 0; b < 8; b++) e[b] = base * exp(-(double)a.beta[b] * d);
+    bool ok = m >= 0 && m < a.n_rcv && k >= 0 && k < a.R1;
+    for (int j = 0; ok && j < k; j++) {
+        const int32_t p = row[2 + j];
+        if (p < 0 || p >= a.n_tri) {
+            ok = false;
+            break;
+        }
+        const int32_t mat = a.plane_mat[p];
+        for (int b = 0; b < 8; b++) e[b] *= 1.0 - (double)a.alpha[8 * mat + b];
+    }
+    for (int b = 0; b < 8; b++) E[8 * i + b] = e[b];
+    const double sb = floor(d * a.fs / a.c);
+    uint64_t key = a.invalid;
+    if (ok && sb >= 0.0 && sb < (double)a.L) key = (uint64_t)m * (uint64_t)a.L + (uint64_t)sb;
+    skey[i] = key;
+}
+
+__global__ void k_fill_f32(float* p, int64_t n, float v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// One thread per run of equal (receiver, bin): sum in sorted order (FP64).
+__global__ void k_bin_sum(IsArgs a, const uint64_t* __restrict__ skey, const uint32_t* __restrict__ idx,
+                          const double* __restrict__ E, float* __restrict__ hist) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = is_count_of(a);
+    if (i >= n) return;
+    const uint64_t key = skey[i];
+    if (key == a.invalid) return;
+    if (i > 0 && skey[i - 1] == key) return;
+    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t j = i; j < n && skey[j] == key; j++) {
+        const uint32_t q = idx[j];
+        for (int b = 0; b < 8; b++) s[b] += E[8 * (int64_t)q + b];
+    }
+    const int64_t m = (int64_t)(key / (uint64_t)a.L), bin = (int64_t)(key % (uint64_t)a.L);
+    for (int b = 0; b < 8; b++) hist[(m * 8 + b) * a.L + bin] = (float)s[b];
+}
+
+// band_energy[r, b] = sum over bins (FP64 tree reduction, fixed order).
+__global__ void __launch_bounds__(256) k_band_energy(const float* __restrict__ hist, int64_t L,
+                                                     float* __restrict__ out) {
+    __shared__ double red[256];
+    const float* h = hist + (int64_t)blockIdx.x * L;
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < L; i += 256) s += (double)h[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = (float)red[0];
+}
+
+// ---------------------------------------------------------------------------
+// FIR on MFMA (v_mfma_f32_16x16x4_f32)
+// ---------------------------------------------------------------------------
+constexpr int kFirWaves = 4;
+constexpr int kFirTiles = 4;                                    // 16x16 tiles per wave
+constexpr int kFirOut = kFirWaves * kFirTiles * 256;            // outputs per workgroup
+
+__device__ inline int win_addr(int p) { return (p >> 4) * 20 + (p & 15); }
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// grid: (ceil(L / kFirOut), n_rcv * 8).  taps padded: hp[u] = h[u - 48] for
+// u - 48 in [0, K), else 0, length Kpad = K + 112.
+__global__ void __launch_bounds__(256) k_fir_mfma(const float* __restrict__ hist, const float* __restrict__ fir, int K,
+                                                  int64_t L, float* __restrict__ band_ir) {
+    extern __shared__ float smem[];
+    const int sig = blockIdx.y;
+    const int band = sig & 7;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int c = (K - 1) / 2;
+    const int64_t n0 = (int64_t)blockIdx.x * kFirOut;
+    // signal window: positions [w0, w0 + W) with w0 = floor16(n0 - c)
+    const int64_t s0 = n0 - c;
+    const int64_t w0 = s0 >= 0 ? (s0 & ~(int64_t)15) : -((-s0 + 15) & ~(int64_t)15);
+    const int delta = (int)(s0 - w0);                            // 0..15
+    const int S = (K + 15 + delta + 3) / 4;                      // MFMA steps (kk' in [0, 4S))
+    const int W = kFirOut + 4 * S + 16;                          // window samples
+    const int Kpad = K + 112;
+    float* hp = smem;                                            // [Kpad]
+    float* xw = smem + Kpad;                                     // [win_addr(W) + 20]
+    const float* taps = fir + (int64_t)band * K;
+    for (int u = tid; u < Kpad; u += 256) {
+        const int j = u - 48;
+        hp[u] = (j >= 0 && j < K) ? taps[j] : 0.f;
+    }
+    const float* x = hist + (int64_t)sig * L;
+    for (int p = tid; p < W; p += 256) {
+        const int64_t g = w0 + p;
+        const float v = (g >= 0 && g < L) ? x[g] : 0.f;
+        xw[win_addr(p)] = sqrtf(v);
+    }
+    __syncthreads();
+    const int i = lane & 15, kq = lane >> 4;
+    floatx4 acc[kFirTiles];
+    for (int t = 0; t < kFirTiles; t++) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    // A[i][kk'] = h[i + K - 1 + delta - kk'], kk' = 4s + kq  -> hp index + 48
+    const int abase = i + K - 1 + delta - kq + 48;
+    // B[kk'][q] = x[w0 + tile_off + 16 q + kk'], q = lane & 15
+    const int bbase = wave * (kFirTiles * 256) + 16 * i + kq;
+    for (int s = 0; s < S; s++) {
+        const int ai = abase - 4 * s;
+        const float av = (ai >= 0 && ai < Kpad) ? hp[ai] : 0.f;
+#pragma unroll
+        for (int t = 0; t < kFirTiles; t++) {
+            const float bv = xw[win_addr(bbase + t * 256 + 4 * s)];
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[t], 0, 0, 0);
+        }
+    }
+    // D[i][q]: lane = q + 16 * (i / 4), element i % 4 -> y[n0 + tile + i + 16 q]
+    float* y = band_ir + (int64_t)sig * L;
+    const int q = lane & 15, ib = 4 * (lane >> 4);
+    for (int t = 0; t < kFirTiles; t++) {
+        const int64_t o = n0 + wave * (kFirTiles * 256) + t * 256 + 16 * q + ib;
+        for (int e = 0; e < 4; e++)
+            if (o + e < L) y[o + e] = acc[t][e];
+    }
+}
+
+__global__ void k_sum_bands(const float* __restrict__ band_ir, int64_t L, int32_t n_rcv, float* __restrict__ ir) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n_rcv * L) return;
+    const int64_t m = i / L, s = i % L;
+    float acc = 0.f;
+    for (int b = 0; b < 8; b++) acc += band_ir[(m * 8 + b) * L + s];
+    ir[i] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// adjoint
+// ---------------------------------------------------------------------------
+constexpr int kAdjThreads = 256;
+
+// partial[block][m][b]: per-block sums in a fixed order (tree reduction).
+__global__ void __launch_bounds__(kAdjThreads) k_adjoint_partial(IsArgs a, int32_t n_mat, const float* __restrict__ g,
+                                                                 double* __restrict__ partial) {
+    __shared__ double red[kAdjThreads][8];
+    const int64_t i = (int64_t)blockIdx.x * kAdjThreads + threadIdx.x;
+    const int64_t n = is_count_of(a);
+    bool ok = i < n;
+    const int32_t* row = ok ? a.key + i * (int64_t)(a.R1 + 1) : nullptr;
+    int32_t m = 0, k = 0;
+    double base[8];
+    if (ok) {
+        m = row[0];
+        k = row[1];
+        ok = m >= 0 && m < a.n_rcv && k >= 0 && k < a.R1;
+        const double d = a.dist[i];
+        const double sb = floor(d * a.fs / a.c);
+        ok = ok && sb >= 0.0 && sb < (double)a.L;
+        for (int j = 0; ok && j < k; j++) ok = row[2 + j] >= 0 && row[2 + j] < a.n_tri;
+        for (int b = 0; b < 8; b++)
+            base[b] = ok ? (double)a.count[i] / (double)a.n_rays * exp(-(double)a.beta[b] * d) * (double)g[8 * m + b]
+                         : 0.0;
+    }
+    for (int mat = 0; mat < n_mat; mat++) {
+        double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (ok) {
+            int cm = 0;
+            for (int j = 0; j < k; j++) cm += a.plane_mat[row[2 + j]] == mat;
+            if (cm > 0) {
+                for (int b = 0; b < 8; b++) {
+                    const double om = 1.0 - (double)a.alpha[8 * mat + b];
+                    double dv = -(double)cm;
+                    for (int e = 0; e < cm - 1; e++) dv *= om;
+                    for (int j = 0; j < k; j++) {
+                        const int32_t mt = a.plane_mat[row[2 + j]];
+                        if (mt != mat) dv *= 1.0 - (double)a.alpha[8 * mt + b];
+                    }
+                    v[b] = base[b] * dv;
+                }
+            }
+        }
+        for (int b = 0; b < 8; b++) red[threadIdx.x][b] = v[b];
+        __syncthreads();
+        for (int off = kAdjThreads / 2; off > 0; off >>= 1) {
+            if ((int)threadIdx.x < off)
+                for (int b = 0; b < 8; b++) red[threadIdx.x][b] += red[threadIdx.x + off][b];
+            __syncthreads();
+        }
+        if (threadIdx.x < 8) partial[((int64_t)blockIdx.x * n_mat + mat) * 8 + threadIdx.x] = red[0][threadIdx.x];
+        __syncthreads();
+    }
+}
+
+__global__ void k_adjoint_final(const double* __restrict__ partial, int nblocks, int32_t n_mat, const int64_t* n_is,
+                                int64_t is_cap, float* __restrict__ grad) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_mat * 8) return;
+    int64_t n = *n_is;
+    if (n > is_cap) n = is_cap;
+    const int used = (int)((n + kAdjThreads - 1) / kAdjThreads);
+    double s = 0.0;
+    for (int b = 0; b < used && b < nblocks; b++) s += partial[(int64_t)b * n_mat * 8 + t];
+    grad[t] = (float)s;
+}
+
+inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t > 0 ? (n + t - 1) / t : 1); }
+
+int check_is_args(const rt_scene* s, const int32_t* is_key, const int32_t* is_count, const double* is_dist,
+                  const int64_t* n_is, int64_t is_cap, int32_t R, int64_t n_rays, int32_t n_rcv, const float* alpha,
+                  const float* beta, float c, float fs, int64_t L) {
+    RT_CHECK(s && n_is && alpha && beta, RT_EINVAL, "null argument");
+    RT_CHECK(is_cap >= 0 && (is_cap == 0 || (is_key && is_count && is_dist)), RT_EINVAL, "null image-source table");
+    RT_CHECK(is_cap < ((int64_t)1 << 31), RT_EINVAL, "is_cap must be < 2^31");
+    RT_CHECK(R >= 0 && R < 4096, RT_EINVAL, "max_reflections out of range");
+    RT_CHECK(n_rays >= 1, RT_EINVAL, "n_rays must be >= 1");
+    RT_CHECK(n_rcv >= 1 && n_rcv <= kMaxRcv, RT_EINVAL, "n_rcv must be in [1, %d]", kMaxRcv);
+    RT_CHECK(c > 0.f && fs > 0.f, RT_EINVAL, "c and fs must be positive");
+    RT_CHECK(L >= 1 && L <= ((int64_t)1 << 30), RT_EINVAL, "L out of range");
+    return RT_OK;
+}
+
+IsArgs make_is_args(const rt_scene* s, const int32_t* is_key, const int32_t* is_count, const double* is_dist,
+                    const int64_t* n_is, int64_t is_cap, int32_t R, int64_t n_rays, int32_t n_rcv, const float* alpha,
+                    const float* beta, float c, float fs, int64_t L) {
+    IsArgs a;
+    a.key = is_key;
+    a.count = is_count;
+    a.dist = is_dist;
+    a.n_is = n_is;
+    a.is_cap = is_cap;
+    a.R1 = R + 1;
+    a.n_rays = n_rays;
+    a.n_rcv = n_rcv;
+    a.alpha = alpha;
+    a.beta = beta;
+    a.plane_mat = s->plane_mat;
+    a.n_tri = s->n_tri;
+    a.c = c;
+    a.fs = fs;
+    a.L = L;
+    a.invalid = (uint64_t)n_rcv * (uint64_t)L;
+    return a;
+}
+
+}  // namespace
+
+}  // namespace rtac
+
+using namespace rtac;
+
+extern "C" int rt_assemble_ir(const rt_scene* scene, const int32_t* is_key, const int32_t* is_count,
+                              const double* is_dist, const int64_t* n_is, int64_t is_cap, int32_t max_reflections,
+                              int64_t n_rays, int32_t n_rcv, const float* alpha, const float* beta, float c, float fs,
+                              int64_t L, const float* fir, int32_t K, float* band_energy, float* hist, float* band_ir,
+                              float* ir, void* stream) {
+    int rc = check_is_args(scene, is_key, is_count, is_dist, n_is, is_cap, max_reflections, n_rays, n_rcv, alpha,
+                           beta, c, fs, L);
+    if (rc) {
+        set_error("rt_assemble_ir: %s", rt_last_error());
+        return rc;
+    }
+    RT_CHECK(fir && K >= 1 && (K & 1) == 1 && K <= 16383, RT_EINVAL, "rt_assemble_ir: K must be odd in [1, 16383]");
+    RT_CHECK(band_energy && hist && band_ir && ir, RT_EINVAL, "rt_assemble_ir: null output");
+    RT_CHECK((int64_t)n_rcv * L * 8 < ((int64_t)1 << 62), RT_EINVAL, "rt_assemble_ir: output too large");
+    hipStream_t st = (hipStream_t)stream;
+    rt_scene* s = const_cast<rt_scene*>(scene);
+    Workspace& ws = s->ws;
+    const int64_t cap = is_cap > 0 ? is_cap : 1;
+    if (ws.asm_energy.ensure(sizeof(double) * 8 * cap) || ws.sort_keys[0].ensure(8 * cap) ||
+        ws.sort_keys[1].ensure(8 * cap) || ws.sort_vals[0].ensure(4 * cap) || ws.sort_vals[1].ensure(4 * cap))
+        return RT_ENOMEM;
+    IsArgs a = make_is_args(scene, is_key, is_count, is_dist, n_is, is_cap, max_reflections, n_rays, n_rcv, alpha,
+                            beta, c, fs, L);
+    double* E = ws.asm_energy.as<double>();
+    uint64_t* k0 = ws.sort_keys[0].as<uint64_t>();
+    uint64_t* k1 = ws.sort_keys[1].as<uint64_t>();
+    uint32_t* v0 = ws.sort_vals[0].as<uint32_t>();
+    uint32_t* v1 = ws.sort_vals[1].as<uint32_t>();
+    hipLaunchKernelGGL(k_is_energy, dim3(nblk(cap)), dim3(256), 0, st, a, E, k0);
+    // sort by (receiver, bin); the invalid key n_rcv * L lands last
+    int bits = 8;
+    while (bits < 64 && (a.invalid >> bits) != 0) bits += 8;
+    int which = 0;
+    rc = radix_sort_pairs(ws, k0, v0, k1, v1, cap, n_is, 0, bits, st, &which, true);
+    if (rc) return rc;
+    const int64_t hn = (int64_t)n_rcv * 8 * L;
+    hipLaunchKernelGGL(k_fill_f32, dim3(nblk(hn)), dim3(256), 0, st, hist, hn, 0.f);
+    hipLaunchKernelGGL(k_bin_sum, dim3(nblk(cap)), dim3(256), 0, st, a, which ? k1 : k0, which ? v1 : v0, E, hist);
+    hipLaunchKernelGGL(k_band_energy, dim3(n_rcv * 8), dim3(256), 0, st, hist, L, band_energy);
+    const int Kpad = K + 112;
+    const int Smax = (K + 15 + 15 + 3) / 4;
+    const int W = kFirOut + 4 * Smax + 16;
+    const size_t shm = sizeof(float) * ((size_t)Kpad + (size_t)((W >> 4) + 2) * 20);
+    RT_CHECK(shm <= 160 * 1024, RT_EINVAL, "rt_assemble_ir: FIR taps too long for LDS");
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipFuncSetAttribute((const void*)k_fir_mfma, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        attr_set = true;
+    }
+    dim3 grid((unsigned)((L + kFirOut - 1) / kFirOut), (unsigned)(n_rcv * 8));
+    hipLaunchKernelGGL(k_fir_mfma, grid, dim3(256), shm, st, hist, fir, K, L, band_ir);
+    hipLaunchKernelGGL(k_sum_bands, dim3(nblk((int64_t)n_rcv * L)), dim3(256), 0, st, band_ir, L, n_rcv, ir);
+    RT_HIP(hipGetLastError());
+    return RT_OK;
+}
+
+extern "C" int rt_band_energy_adjoint(const rt_scene* scene, const int32_t* is_key, const int32_t* is_count,
+                                      const double* is_dist, const int64_t* n_is, int64_t is_cap,
+                                      int32_t max_reflections, int64_t n_rays, int32_t n_rcv, const float* alpha,
+                                      int32_t n_mat, const float* beta, float c, float fs, int64_t L,
+                                      const float* grad_band_energy, float* grad_alpha, void* stream) {
+    int rc = check_is_args(scene, is_key, is_count, is_dist, n_is, is_cap, max_reflections, n_rays, n_rcv, alpha,
+                           beta, c, fs, L);
+    if (rc) {
+        set_error("rt_band_energy_adjoint: %s", rt_last_error());
+        return rc;
+    }
+    RT_CHECK(grad_band_energy && grad_alpha, RT_EINVAL, "rt_band_energy_adjoint: null gradient buffer");
+    RT_CHECK(n_mat >= scene->n_mat && n_mat <= 4096, RT_EINVAL,
+             "rt_band_energy_adjoint: n_mat must cover the scene's materials (%d)", scene->n_mat);
+    hipStream_t st = (hipStream_t)stream;
+    rt_scene* s = const_cast<rt_scene*>(scene);
+    const int64_t cap = is_cap > 0 ? is_cap : 1;
+    const int nb = (int)nblk(cap, kAdjThreads);
+    if (s->ws.asm_partial.ensure(sizeof(double) * (size_t)nb * n_mat * 8)) return RT_ENOMEM;
+    IsArgs a = make_is_args(scene, is_key, is_count, is_dist, n_is, is_cap, max_reflections, n_rays, n_rcv, alpha,
+                            beta, c, fs, L);
+    double* part = s->ws.asm_partial.as<double>();
+    hipLaunchKernelGGL(k_adjoint_partial, dim3(nb), dim3(kAdjThreads), 0, st, a, n_mat, grad_band_energy, part);
+    hipLaunchKernelGGL(k_adjoint_final, dim3(nblk(n_mat * 8)), dim3(256), 0, st, part, nb, n_mat, n_is, is_cap,
+                       grad_alpha);
+    RT_HIP(hipGetLastError());
+    return RT_OK;
+}

@@ -1,0 +1,555 @@
+// Scene ingest and acceleration tree (rt_build_tree).
+//
+// The paper builds its tree once per mesh: a mother box holding every
+// element is split into two daughter boxes, recursively, down to one element
+// per leaf (section "Tree-base acceleration").  Here the splits come from the
+// Morton order of the triangle centroids: a binary radix tree (one leaf per
+// triangle, every inner node separating one Morton prefix) built in one
+// parallel pass, boxes refitted bottom-up, then every other level folded so
+// that traversal sees a 4-wide tree with 128-byte nodes (one cache line per
+// node on gfx950).  Subtrees of at most `leaf_size` triangles become leaves.
+//
+// Everything per triangle that traversal and shading need is re-laid out in
+// tree order (48 B per triangle) so a leaf is a contiguous range.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "common.h"
+
+namespace rtac {
+
+namespace {
+
+enum : uint32_t {
+    kErrIndex = 1u,
+    kErrNonFinite = 2u,
+    kErrZeroArea = 4u,
+    kErrPlaneRange = 8u,
+    kErrMaterial = 16u,
+    kErrNotCoplanar = 32u,
+    kErrMixedMaterial = 64u,
+};
+
+__device__ inline uint32_t ford(float f) {
+    uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__host__ __device__ inline float funord(uint32_t u) {
+    uint32_t b = (u & 0x80000000u) ? (u & 0x7FFFFFFFu) : ~u;
+    return __builtin_bit_cast(float, b);
+}
+
+// bounds[0..5] = vertex box (min xyz ordered, max xyz ordered),
+// bounds[6..11] = centroid box; info[0] = error bits, info[1] = max material.
+__global__ void k_tri_prep(const float* __restrict__ vtx, int64_t nv, const int3* __restrict__ tri, int64_t nt,
+                           const int32_t* __restrict__ material, const int32_t* __restrict__ plane_id,
+                           float* __restrict__ tri_box, float* __restrict__ centroid, uint32_t* __restrict__ bounds,
+                           uint32_t* __restrict__ info, int32_t* __restrict__ prep) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nt) return;
+    const int3 t = tri[i];
+    uint32_t err = 0;
+    if (t.x < 0 || t.y < 0 || t.z < 0 || t.x >= nv || t.y >= nv || t.z >= nv) err |= kErrIndex;
+    const int32_t p = plane_id ? plane_id[i] : (int32_t)i;
+    if (p < 0 || p >= nt) err |= kErrPlaneRange;
+    const int32_t m = material[i];
+    if (m < 0) err |= kErrMaterial;
+    if (err) {
+        atomicOr(&info[0], err);
+        return;
+    }
+    float v[3][3];
+    const int idx[3] = {t.x, t.y, t.z};
+    bool finite = true;
+    for (int a = 0; a < 3; a++)
+        for (int c = 0; c < 3; c++) {
+            v[a][c] = vtx[3 * (int64_t)idx[a] + c];
+            finite &= isfinite(v[a][c]);
+        }
+    if (!finite) {
+        atomicOr(&info[0], kErrNonFinite);
+        return;
+    }
+    double e1[3], e2[3];
+    for (int c = 0; c < 3; c++) {
+        e1[c] = (double)v[1][c] - (double)v[0][c];
+        e2[c] = (double)v[2][c] - (double)v[0][c];
+    }
+    const double cx = e1[1] * e2[2] - e1[2] * e2[1];
+    const double cy = e1[2] * e2[0] - e1[0] * e2[2];
+    const double cz = e1[0] * e2[1] - e1[1] * e2[0];
+    if (cx == 0.0 && cy == 0.0 && cz == 0.0) atomicOr(&info[0], kErrZeroArea);
+    atomicMax(&info[1], (uint32_t)m);
+    atomicMin(&prep[p], (int32_t)i);
+    for (int c = 0; c < 3; c++) {
+        const float lo = fminf(v[0][c], fminf(v[1][c], v[2][c]));
+        const float hi = fmaxf(v[0][c], fmaxf(v[1][c], v[2][c]));
+        tri_box[6 * i + c] = lo;
+        tri_box[6 * i + 3 + c] = hi;
+        const float cen = (v[0][c] + v[1][c] + v[2][c]) * (1.0f / 3.0f);
+        centroid[3 * i + c] = cen;
+        atomicMin(&bounds[c], ford(lo));
+        atomicMax(&bounds[3 + c], ford(hi));
+        atomicMin(&bounds[6 + c], ford(cen));
+        atomicMax(&bounds[9 + c], ford(cen));
+    }
+}
+
+// Plane table (FP64) from each plane id's representative (lowest index).
+__global__ void k_plane_table(const float* __restrict__ vtx, const int3* __restrict__ tri, int64_t nt,
+                              const int32_t* __restrict__ material, const int32_t* __restrict__ prep,
+                              double* __restrict__ pn, double* __restrict__ pp, int32_t* __restrict__ pmat) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nt) return;
+    const int32_t r = prep[p];
+    if (r == INT32_MAX) {
+        for (int c = 0; c < 3; c++) pn[3 * p + c] = pp[3 * p + c] = __longlong_as_double(0x7FF8000000000000ll);
+        pmat[p] = -1;
+        return;
+    }
+    const int3 t = tri[r];
+    double a[3], b[3], cc[3];
+    for (int c = 0; c < 3; c++) {
+        a[c] = vtx[3 * (int64_t)t.x + c];
+        b[c] = vtx[3 * (int64_t)t.y + c];
+        cc[c] = vtx[3 * (int64_t)t.z + c];
+    }
+    const double e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+    const double e2[3] = {cc[0] - a[0], cc[1] - a[1], cc[2] - a[2]};
+    double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+    const double len = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    for (int c = 0; c < 3; c++) {
+        pn[3 * p + c] = n[c] / len;
+        pp[3 * p + c] = a[c];
+    }
+    pmat[p] = material[r];
+}
+
+// Members of a plane group lie in the representative's plane (1e-9 D) and
+// share its material.  Also records the plane id of every triangle.
+__global__ void k_coplanar(const float* __restrict__ vtx, const int3* __restrict__ tri, int64_t nt,
+                           const int32_t* __restrict__ material, const int32_t* __restrict__ plane_id,
+                           const double* __restrict__ pn, const double* __restrict__ pp,
+                           const int32_t* __restrict__ pmat, double tol, int32_t* __restrict__ tri_plane,
+                           uint32_t* __restrict__ info) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nt) return;
+    const int32_t p = plane_id ? plane_id[i] : (int32_t)i;
+    tri_plane[i] = p;
+    if (material[i] != pmat[p]) atomicOr(&info[0], kErrMixedMaterial);
+    const int3 t = tri[i];
+    const int idx[3] = {t.x, t.y, t.z};
+    for (int a = 0; a < 3; a++) {
+        double d = 0;
+        for (int c = 0; c < 3; c++) d += ((double)vtx[3 * (int64_t)idx[a] + c] - pp[3 * p + c]) * pn[3 * p + c];
+        if (!(fabs(d) <= tol)) atomicOr(&info[0], kErrNotCoplanar);
+    }
+}
+
+__device__ inline uint64_t spread21(uint64_t x) {
+    x &= 0x1FFFFFull;
+    x = (x | (x << 32)) & 0x1F00000000FFFFull;
+    x = (x | (x << 16)) & 0x1F0000FF0000FFull;
+    x = (x | (x << 8)) & 0x100F00F00F00F00Full;
+    x = (x | (x << 4)) & 0x10C30C30C30C30C3ull;
+    x = (x | (x << 2)) & 0x1249249249249249ull;
+    return x;
+}
+
+// 63-bit Morton code of the centroid, quantised on a cube spanning the
+// centroid box (equal cells on every axis).
+__global__ void k_morton(const float* __restrict__ centroid, int64_t nt, const uint32_t* __restrict__ bounds,
+                         uint64_t* __restrict__ code) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nt) return;
+    float lo[3], ext = 0.f;
+    for (int c = 0; c < 3; c++) {
+        lo[c] = funord(bounds[6 + c]);
+        ext = fmaxf(ext, funord(bounds[9 + c]) - lo[c]);
+    }
+    const float scale = ext > 0.f ? 2097151.0f / ext : 0.f;
+    uint64_t q[3];
+    for (int c = 0; c < 3; c++) {
+        float f = (centroid[3 * i + c] - lo[c]) * scale;
+        f = fminf(fmaxf(f, 0.f), 2097151.0f);
+        q[c] = (uint64_t)f;
+    }
+    code[i] = (spread21(q[0]) << 2) | (spread21(q[1]) << 1) | spread21(q[2]);
+}
+
+__device__ inline int prefix_len(const uint64_t* __restrict__ k, int64_t n, int64_t i, int64_t j) {
+    if (j < 0 || j >= n) return -1;
+    const uint64_t a = k[i], b = k[j];
+    if (a == b) return 64 + __clz((uint32_t)(i ^ j));
+    return __clzll(a ^ b);
+}
+
+// Binary radix tree over sorted codes (one inner node per adjacent pair):
+// node i covers [first, last]; its split is where the common prefix ends.
+// Children: >= 0 inner node, < 0 leaf ~j.  parent arrays: -1 for the root.
+__global__ void k_radix_tree(const uint64_t* __restrict__ k, int64_t n, int32_t* __restrict__ left,
+                             int32_t* __restrict__ right, int32_t* __restrict__ first, int32_t* __restrict__ last,
+                             int32_t* __restrict__ parent_in, int32_t* __restrict__ parent_leaf) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n - 1) return;
+    const int d = (prefix_len(k, n, i, i + 1) - prefix_len(k, n, i, i - 1)) >= 0 ? 1 : -1;
+    const int dmin = prefix_len(k, n, i, i - d);
+    int64_t lmax = 2;
+    while (prefix_len(k, n, i, i + lmax * d) > dmin) lmax <<= 1;
+    int64_t l = 0;
+    for (int64_t t = lmax >> 1; t >= 1; t >>= 1)
+        if (prefix_len(k, n, i, i + (l + t) * d) > dmin) l += t;
+    const int64_t j = i + l * d;
+    const int dnode = prefix_len(k, n, i, j);
+    int64_t s = 0, t = l;
+    do {
+        t = (t + 1) >> 1;
+        if (prefix_len(k, n, i, i + (s + t) * d) > dnode) s += t;
+    } while (t > 1);
+    const int64_t g = i + s * d + (d < 0 ? -1 : 0);
+    const int64_t lo = i < j ? i : j, hi = i < j ? j : i;
+    int32_t lc, rc;
+    if (lo == g) {
+        lc = ~(int32_t)g;
+        parent_leaf[g] = (int32_t)i;
+    } else {
+        lc = (int32_t)g;
+        parent_in[g] = (int32_t)i;
+    }
+    if (hi == g + 1) {
+        rc = ~(int32_t)(g + 1);
+        parent_leaf[g + 1] = (int32_t)i;
+    } else {
+        rc = (int32_t)(g + 1);
+        parent_in[g + 1] = (int32_t)i;
+    }
+    left[i] = lc;
+    right[i] = rc;
+    first[i] = (int32_t)lo;
+    last[i] = (int32_t)hi;
+    if (i == 0) parent_in[0] = -1;
+}
+
+// Bottom-up boxes: the second child to arrive at a node computes its box.
+__global__ void k_refit(int64_t n, const uint32_t* __restrict__ order, const float* __restrict__ tri_box,
+                        const int32_t* __restrict__ left, const int32_t* __restrict__ right,
+                        const int32_t* __restrict__ parent_in, const int32_t* __restrict__ parent_leaf,
+                        float* box_in, uint32_t* __restrict__ arrive) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    int32_t p = parent_leaf[j];
+    while (p >= 0) {
+        __threadfence();
+        if (atomicAdd(&arrive[p], 1u) == 0) return;
+        __threadfence();
+        float b[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+        const int32_t ch[2] = {left[p], right[p]};
+        for (int c2 = 0; c2 < 2; c2++) {
+            const int32_t c = ch[c2];
+            float cb[6];
+            if (c < 0) {
+                const uint32_t t = order[~c];
+                for (int a = 0; a < 6; a++) cb[a] = tri_box[6 * (int64_t)t + a];
+            } else {
+                const volatile float* src = box_in + 6 * (int64_t)c;
+                for (int a = 0; a < 6; a++) cb[a] = src[a];
+            }
+            for (int a = 0; a < 3; a++) {
+                b[a] = fminf(b[a], cb[a]);
+                b[3 + a] = fmaxf(b[3 + a], cb[3 + a]);
+            }
+        }
+        volatile float* dst = box_in + 6 * (int64_t)p;
+        for (int a = 0; a < 6; a++) dst[a] = b[a];
+        p = parent_in[p];
+    }
+}
+
+__device__ inline int32_t node_size(const int32_t* first, const int32_t* last, int32_t c) {
+    return c < 0 ? 1 : last[c] - first[c] + 1;
+}
+
+// Inner nodes above the leaf-cluster level at even depth become 4-wide nodes.
+__global__ void k_flag4(int64_t n_in, const int32_t* __restrict__ first, const int32_t* __restrict__ last,
+                        const int32_t* __restrict__ parent_in, int32_t leaf_size, uint32_t* __restrict__ flag,
+                        int32_t* __restrict__ depth_out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_in) return;
+    int depth = 0;
+    for (int32_t p = parent_in[i]; p >= 0 && depth < 4096; p = parent_in[p]) depth++;
+    depth_out[i] = depth;
+    const int32_t size = last[i] - first[i] + 1;
+    flag[i] = (size > leaf_size && (depth & 1) == 0) ? 1u : 0u;
+}
+
+__global__ void k_emit4(int64_t n_in, const int32_t* __restrict__ left, const int32_t* __restrict__ right,
+                        const int32_t* __restrict__ first, const int32_t* __restrict__ last,
+                        const uint32_t* __restrict__ flag, const uint32_t* __restrict__ index,
+                        const int32_t* __restrict__ depth_in, const float* __restrict__ box_in,
+                        const float* __restrict__ tri_box, const uint32_t* __restrict__ order, int32_t leaf_size,
+                        Node4* __restrict__ nodes, uint32_t* __restrict__ info) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_in || !flag[i]) return;
+    int32_t slot_ref[4];
+    float slot_box[4][6];
+    int ns = 0;
+    auto add = [&](int32_t c) {
+        float* b = slot_box[ns];
+        if (c < 0) {
+            const uint32_t t = order[~c];
+            for (int a = 0; a < 6; a++) b[a] = tri_box[6 * (int64_t)t + a];
+            slot_ref[ns] = leaf_ref(~c, 1);
+        } else {
+            for (int a = 0; a < 6; a++) b[a] = box_in[6 * (int64_t)c + a];
+            const int32_t sz = last[c] - first[c] + 1;
+            slot_ref[ns] = sz <= leaf_size ? leaf_ref(first[c], sz) : (int32_t)index[c];
+        }
+        ns++;
+    };
+    const int32_t ch[2] = {left[i], right[i]};
+    for (int q = 0; q < 2; q++) {
+        const int32_t c = ch[q];
+        if (c < 0 || node_size(first, last, c) <= leaf_size) {
+            add(c);
+        } else {
+            add(left[c]);
+            add(right[c]);
+        }
+    }
+    Node4 nd;
+    for (int s = 0; s < 4; s++) {
+        if (s < ns) {
+            nd.lox[s] = slot_box[s][0];
+            nd.loy[s] = slot_box[s][1];
+            nd.loz[s] = slot_box[s][2];
+            nd.hix[s] = slot_box[s][3];
+            nd.hiy[s] = slot_box[s][4];
+            nd.hiz[s] = slot_box[s][5];
+            nd.child[s] = slot_ref[s];
+        } else {
+            nd.lox[s] = nd.loy[s] = nd.loz[s] = INFINITY;
+            nd.hix[s] = nd.hiy[s] = nd.hiz[s] = -INFINITY;
+            nd.child[s] = kEmpty;
+        }
+        nd.pad[s] = 0;
+    }
+    nodes[index[i]] = nd;
+    atomicMax(&info[2], (uint32_t)(depth_in[i] / 2 + 1));
+}
+
+// Root made of a single leaf (the whole mesh fits one leaf).
+__global__ void k_single_leaf_root(const uint32_t* __restrict__ bounds, int32_t count, Node4* __restrict__ nodes) {
+    Node4 nd;
+    for (int s = 0; s < 4; s++) {
+        nd.lox[s] = nd.loy[s] = nd.loz[s] = INFINITY;
+        nd.hix[s] = nd.hiy[s] = nd.hiz[s] = -INFINITY;
+        nd.child[s] = kEmpty;
+        nd.pad[s] = 0;
+    }
+    nd.lox[0] = funord(bounds[0]);
+    nd.loy[0] = funord(bounds[1]);
+    nd.loz[0] = funord(bounds[2]);
+    nd.hix[0] = funord(bounds[3]);
+    nd.hiy[0] = funord(bounds[4]);
+    nd.hiz[0] = funord(bounds[5]);
+    nd.child[0] = leaf_ref(0, count);
+    nodes[0] = nd;
+}
+
+__global__ void k_tri_records(const float* __restrict__ vtx, const int3* __restrict__ tri, int64_t nt,
+                              const int32_t* __restrict__ material, const int32_t* __restrict__ tri_plane,
+                              const uint32_t* __restrict__ order, float4* __restrict__ rec) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nt) return;
+    const uint32_t t = order[j];
+    const int3 v = tri[t];
+    const int idx[3] = {v.x, v.y, v.z};
+    const int32_t w[3] = {tri_plane[t], (int32_t)t, material[t]};
+    for (int a = 0; a < 3; a++) {
+        const float* p = vtx + 3 * (int64_t)idx[a];
+        rec[3 * j + a] = make_float4(p[0], p[1], p[2], __int_as_float(w[a]));
+    }
+}
+
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_init_bounds(uint32_t* b, uint32_t* info) {
+    const int t = threadIdx.x;
+    if (t < 12) b[t] = (t % 6) < 3 ? 0xFFFFFFFFu : 0u;
+    if (t < 4) info[t] = 0;
+}
+
+inline int blocks(int64_t n, int t = 256) { return (int)((n + t - 1) / t); }
+
+const char* err_text(uint32_t e) {
+    if (e & kErrIndex) return "vertex index out of range";
+    if (e & kErrPlaneRange) return "plane id out of range [0, n_tri)";
+    if (e & kErrMaterial) return "negative material index";
+    if (e & kErrNonFinite) return "non-finite vertex coordinate";
+    if (e & kErrZeroArea) return "zero-area triangle";
+    if (e & kErrNotCoplanar) return "plane group member not in its representative's plane";
+    if (e & kErrMixedMaterial) return "plane group members with different materials";
+    return "invalid mesh";
+}
+
+struct TmpBufs {
+    std::vector<void*> ptrs;
+    ~TmpBufs() {
+        for (void* p : ptrs) (void)hipFree(p);
+    }
+    template <class T>
+    T* get(size_t count) {
+        void* p = nullptr;
+        if (hipMalloc(&p, sizeof(T) * (count ? count : 1)) != hipSuccess) return nullptr;
+        ptrs.push_back(p);
+        return reinterpret_cast<T*>(p);
+    }
+};
+
+}  // namespace
+
+}  // namespace rtac
+
+using namespace rtac;
+
+extern "C" int rt_build_tree(const float* vtx, int64_t n_vtx, const int32_t* tri, int64_t n_tri,
+                             const int32_t* material, const int32_t* plane_id, const rt_build_params* params,
+                             void* stream, rt_scene** out_scene) {
+    RT_CHECK(out_scene != nullptr, RT_EINVAL, "rt_build_tree: out_scene is NULL");
+    *out_scene = nullptr;
+    RT_CHECK(vtx && tri && material, RT_EINVAL, "rt_build_tree: null input array");
+    RT_CHECK(n_tri >= 1 && n_vtx >= 3, RT_EINVAL, "rt_build_tree: need n_tri >= 1 and n_vtx >= 3");
+    RT_CHECK(n_tri < kMaxTris, RT_EINVAL, "rt_build_tree: n_tri must be < 2^27");
+    int leaf = params ? params->leaf_size : 1;
+    RT_CHECK(leaf >= 1 && leaf <= kMaxLeaf, RT_EINVAL, "rt_build_tree: leaf_size must be in [1, %d]", kMaxLeaf);
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t nt = n_tri;
+    TmpBufs tmp;
+    float* tri_box = tmp.get<float>(6 * nt);
+    float* cen = tmp.get<float>(3 * nt);
+    uint32_t* bounds = tmp.get<uint32_t>(12);
+    uint32_t* info = tmp.get<uint32_t>(4);
+    int32_t* prep = tmp.get<int32_t>(nt);
+    RT_CHECK(tri_box && cen && bounds && info && prep, RT_ENOMEM, "rt_build_tree: out of device memory");
+    hipLaunchKernelGGL(k_init_bounds, dim3(1), dim3(64), 0, st, bounds, info);
+    hipLaunchKernelGGL(k_fill_i32, dim3(blocks(nt)), dim3(256), 0, st, prep, nt, INT32_MAX);
+    hipLaunchKernelGGL(k_tri_prep, dim3(blocks(nt)), dim3(256), 0, st, vtx, n_vtx, (const int3*)tri, nt, material,
+                       plane_id, tri_box, cen, bounds, info, prep);
+    RT_HIP(hipGetLastError());
+    uint32_t h_info[4], h_bounds[12];
+    RT_HIP(hipMemcpyAsync(h_info, info, sizeof(h_info), hipMemcpyDeviceToHost, st));
+    RT_HIP(hipMemcpyAsync(h_bounds, bounds, sizeof(h_bounds), hipMemcpyDeviceToHost, st));
+    RT_HIP(hipStreamSynchronize(st));
+    if (h_info[0]) {
+        set_error("rt_build_tree: %s", err_text(h_info[0]));
+        return (h_info[0] & (kErrNonFinite | kErrZeroArea)) && !(h_info[0] & (kErrIndex | kErrPlaneRange | kErrMaterial))
+                   ? RT_EDEGENERATE
+                   : RT_EINVAL;
+    }
+    rt_scene* s = new rt_scene();
+    RT_HIP(hipGetDevice(&s->device));
+    s->n_tri = nt;
+    s->n_vtx = n_vtx;
+    s->n_mat = (int32_t)h_info[1] + 1;
+    s->leaf_size = leaf;
+    double d2 = 0;
+    for (int c = 0; c < 3; c++) {
+        s->bounds[c] = funord(h_bounds[c]);
+        s->bounds[3 + c] = funord(h_bounds[3 + c]);
+        const double e = (double)s->bounds[3 + c] - (double)s->bounds[c];
+        d2 += e * e;
+    }
+    s->diag = std::sqrt(d2);
+    auto fail = [&](int code) {
+        rt_scene_destroy(s);
+        return code;
+    };
+    if (hipMalloc(&s->plane_n, sizeof(double) * 3 * nt) != hipSuccess ||
+        hipMalloc(&s->plane_p, sizeof(double) * 3 * nt) != hipSuccess ||
+        hipMalloc(&s->plane_mat, sizeof(int32_t) * nt) != hipSuccess ||
+        hipMalloc(&s->tri_plane, sizeof(int32_t) * nt) != hipSuccess ||
+        hipMalloc(&s->tri_rec, sizeof(float4) * 3 * nt) != hipSuccess) {
+        set_error("rt_build_tree: out of device memory");
+        return fail(RT_ENOMEM);
+    }
+    hipLaunchKernelGGL(k_plane_table, dim3(blocks(nt)), dim3(256), 0, st, vtx, (const int3*)tri, nt, material, prep,
+                       s->plane_n, s->plane_p, s->plane_mat);
+    hipLaunchKernelGGL(k_coplanar, dim3(blocks(nt)), dim3(256), 0, st, vtx, (const int3*)tri, nt, material, plane_id,
+                       s->plane_n, s->plane_p, s->plane_mat, 1e-9 * s->diag, s->tri_plane, info);
+    // Morton order
+    uint64_t* codes0 = tmp.get<uint64_t>(nt);
+    uint64_t* codes1 = tmp.get<uint64_t>(nt);
+    uint32_t* ord0 = tmp.get<uint32_t>(nt);
+    uint32_t* ord1 = tmp.get<uint32_t>(nt);
+    if (!codes0 || !codes1 || !ord0 || !ord1) {
+        set_error("rt_build_tree: out of device memory");
+        return fail(RT_ENOMEM);
+    }
+    hipLaunchKernelGGL(k_morton, dim3(blocks(nt)), dim3(256), 0, st, cen, nt, bounds, codes0);
+    int which = 0;
+    int rc = radix_sort_pairs(s->ws, codes0, ord0, codes1, ord1, nt, nullptr, 0, 64, st, &which, true);
+    if (rc) return fail(rc);
+    uint64_t* codes = which ? codes1 : codes0;
+    uint32_t* order = which ? ord1 : ord0;
+    const int64_t n_in = nt - 1;
+    uint32_t h_info2[4] = {0, 0, 0, 0};
+    if (n_in == 0 || nt <= leaf) {
+        RT_HIP(hipMalloc(&s->nodes, sizeof(Node4)));
+        hipLaunchKernelGGL(k_single_leaf_root, dim3(1), dim3(1), 0, st, bounds, (int32_t)nt, s->nodes);
+        s->n_nodes = 1;
+        h_info2[2] = 1;
+    } else {
+        int32_t* left = tmp.get<int32_t>(n_in);
+        int32_t* right = tmp.get<int32_t>(n_in);
+        int32_t* first = tmp.get<int32_t>(n_in);
+        int32_t* last = tmp.get<int32_t>(n_in);
+        int32_t* par_in = tmp.get<int32_t>(n_in);
+        int32_t* par_leaf = tmp.get<int32_t>(nt);
+        int32_t* depth = tmp.get<int32_t>(n_in);
+        float* box_in = tmp.get<float>(6 * n_in);
+        uint32_t* arrive = tmp.get<uint32_t>(n_in);
+        uint32_t* flag = tmp.get<uint32_t>(n_in);
+        uint32_t* index = tmp.get<uint32_t>(n_in + 1);
+        if (!left || !right || !first || !last || !par_in || !par_leaf || !depth || !box_in || !arrive || !flag ||
+            !index) {
+            set_error("rt_build_tree: out of device memory");
+            return fail(RT_ENOMEM);
+        }
+        RT_HIP(hipMemsetAsync(arrive, 0, sizeof(uint32_t) * n_in, st));
+        hipLaunchKernelGGL(k_radix_tree, dim3(blocks(n_in)), dim3(256), 0, st, codes, nt, left, right, first, last,
+                           par_in, par_leaf);
+        hipLaunchKernelGGL(k_refit, dim3(blocks(nt)), dim3(256), 0, st, nt, order, tri_box, left, right, par_in,
+                           par_leaf, box_in, arrive);
+        hipLaunchKernelGGL(k_flag4, dim3(blocks(n_in)), dim3(256), 0, st, n_in, first, last, par_in, leaf, flag,
+                           depth);
+        rc = exclusive_scan_u32(s->ws, flag, index, n_in, nullptr, st);
+        if (rc) return fail(rc);
+        uint32_t n4 = 0;
+        RT_HIP(hipMemcpyAsync(&n4, index + n_in, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        RT_HIP(hipStreamSynchronize(st));
+        RT_CHECK(n4 >= 1, RT_EHIP, "rt_build_tree: empty tree");
+        if (hipMalloc(&s->nodes, sizeof(Node4) * n4) != hipSuccess) {
+            set_error("rt_build_tree: out of device memory");
+            return fail(RT_ENOMEM);
+        }
+        s->n_nodes = (int32_t)n4;
+        hipLaunchKernelGGL(k_emit4, dim3(blocks(n_in)), dim3(256), 0, st, n_in, left, right, first, last, flag,
+                           index, depth, box_in, tri_box, order, leaf, s->nodes, info);
+    }
+    hipLaunchKernelGGL(k_tri_records, dim3(blocks(nt)), dim3(256), 0, st, vtx, (const int3*)tri, nt, material,
+                       s->tri_plane, order, s->tri_rec);
+    RT_HIP(hipGetLastError());
+    RT_HIP(hipMemcpyAsync(h_info, info, sizeof(h_info), hipMemcpyDeviceToHost, st));
+    RT_HIP(hipStreamSynchronize(st));
+    if (h_info[0]) {
+        set_error("rt_build_tree: %s", err_text(h_info[0]));
+        return fail(RT_EINVAL);
+    }
+    s->depth = (int32_t)(h_info2[2] ? h_info2[2] : h_info[2]);
+    *out_scene = s;
+    return RT_OK;
+}

@@ -1,0 +1,119 @@
+// Internal declarations shared by the librtac translation units (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/rtac.h"
+
+namespace rtac {
+
+void set_error(const char* fmt, ...);
+
+#define RT_HIP(call)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess) {                                                           \
+            ::rtac::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),      \
+                              __FILE__, __LINE__);                                        \
+            return RT_EHIP;                                                               \
+        }                                                                                 \
+    } while (0)
+
+#define RT_CHECK(cond, code, ...)             \
+    do {                                      \
+        if (!(cond)) {                        \
+            ::rtac::set_error(__VA_ARGS__);   \
+            return (code);                    \
+        }                                     \
+    } while (0)
+
+constexpr int kWave = 64;
+constexpr int kMaxRcv = 32;
+constexpr int kMaxLeaf = 8;
+
+// 4-wide tree node: child boxes as SoA (96 B) + child references (32 B).
+// child[i] >= 0: inner node index; child[i] < 0: leaf, see leaf_ref();
+// cnt unused slot: child = kEmpty and an inverted (empty) box.
+struct __attribute__((aligned(128))) Node4 {
+    float lox[4], hix[4], loy[4], hiy[4], loz[4], hiz[4];
+    int32_t child[4];
+    int32_t pad[4];
+};
+static_assert(sizeof(Node4) == 128, "node size");
+
+constexpr int32_t kEmpty = (int32_t)0x80000000u;   // count field 0 => empty slot
+__host__ __device__ inline int32_t leaf_ref(int32_t first, int32_t count) {
+    return (int32_t)(0x80000000u | ((uint32_t)count << 27) | (uint32_t)first);
+}
+__host__ __device__ inline int32_t leaf_first(int32_t ref) { return (int32_t)((uint32_t)ref & 0x07FFFFFFu); }
+__host__ __device__ inline int32_t leaf_count(int32_t ref) { return (int32_t)(((uint32_t)ref >> 27) & 0xFu); }
+constexpr int64_t kMaxTris = (int64_t)1 << 27;
+
+// Growable device scratch owned by a scene.
+struct Buf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    int ensure(size_t n);
+    void release();
+    template <class T>
+    T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+struct Workspace {
+    Buf sort_keys[2], sort_vals[2], sort_hist, scan_tmp;
+    Buf stack_spill, trace_pool;
+    Buf is_hash, is_idx, is_flags, is_group, coll_err;
+    Buf asm_key, asm_idx, asm_energy, asm_partial, asm_pressure;
+    Buf generic[4];
+    void release_all();
+};
+
+}  // namespace rtac
+
+struct rt_scene {
+    int device = 0;
+    int64_t n_tri = 0;
+    int64_t n_vtx = 0;
+    int32_t n_mat = 0;
+    int32_t leaf_size = 1;
+    int32_t n_nodes = 0;
+    int32_t depth = 0;          // 4-wide tree depth (levels of inner nodes)
+    double diag = 0.0;
+    float bounds[6] = {0, 0, 0, 0, 0, 0};
+    // device arrays
+    rtac::Node4* nodes = nullptr;   // [n_nodes]
+    float4* tri_rec = nullptr;      // [n_tri * 3] in tree (Morton) order:
+                                    // (v0, plane id) (v1, triangle id) (v2, material) as int bits in w
+    double* plane_n = nullptr;      // [n_tri * 3] unit normal per plane id (representative)
+    double* plane_p = nullptr;      // [n_tri * 3] first vertex of the representative
+    int32_t* plane_mat = nullptr;   // [n_tri] material of each plane id (-1 unused)
+    int32_t* tri_plane = nullptr;   // [n_tri] plane id per original triangle id
+    rtac::Workspace ws;
+};
+
+namespace rtac {
+
+// ---------------------------------------------------------------------------
+// sorting and scanning primitives (sort.hip)
+// ---------------------------------------------------------------------------
+
+// Stable LSD radix sort of (uint64 key, uint32 value) pairs over bits
+// [begin_bit, end_bit).  n_dev (device) overrides n when non-null (the
+// count is read on the device, buffers are sized for `cap`).  Result ends in
+// keys[out]/vals[out] where out is returned (0 or 1).  iota_values: the
+// input values are taken to be 0, 1, 2, ... (vals0 is then only scratch).
+int radix_sort_pairs(Workspace& ws, uint64_t* keys0, uint32_t* vals0, uint64_t* keys1, uint32_t* vals1,
+                     int64_t cap, const int64_t* n_dev, int begin_bit, int end_bit, hipStream_t st,
+                     int* out_index, bool iota_values = false);
+
+// Exclusive scan of uint32 flags[0..cap) into out[0..cap]; out[n] = total.
+int exclusive_scan_u32(Workspace& ws, const uint32_t* in, uint32_t* out, int64_t cap, const int64_t* n_dev,
+                       hipStream_t st);
+
+int device_sm_count();
+
+}  // namespace rtac

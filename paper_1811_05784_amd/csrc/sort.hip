@@ -1,0 +1,226 @@
+// Stable LSD radix sort of (uint64 key, uint32 value) pairs and an exclusive
+// scan, both able to read the element count from device memory so that a
+// producer kernel's count never has to come back to the host.
+//
+// Radix sort: 8-bit digits; per pass (1) per-tile digit histograms, (2) one
+// workgroup scans the digit-major histogram table, (3) each tile ranks its
+// keys stably (wave ballots on the 8 digit bits give each lane its peers,
+// per-wave counts are combined in LDS in wave order) and scatters.
+#include "common.h"
+
+namespace rtac {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kItems = 16;
+constexpr int kTile = kThreads * kItems;   // 4096 keys per workgroup
+constexpr int kWaves = kThreads / kWave;
+
+__device__ inline int64_t count_of(const int64_t* n_dev, int64_t cap) {
+    if (!n_dev) return cap;
+    int64_t n = *n_dev;
+    return n < 0 ? 0 : (n > cap ? cap : n);
+}
+
+__global__ void __launch_bounds__(kThreads) k_digit_hist(const uint64_t* __restrict__ keys, int64_t cap,
+                                                          const int64_t* n_dev, int shift,
+                                                          uint32_t* __restrict__ hist, int nblocks) {
+    __shared__ uint32_t h[256];
+    const int tid = threadIdx.x;
+    h[tid] = 0;
+    __syncthreads();
+    const int64_t n = count_of(n_dev, cap);
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    if (base < n) {
+#pragma unroll 4
+        for (int i = 0; i < kItems; i++) {
+            int64_t idx = base + (int64_t)i * kThreads + tid;
+            if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & 255u], 1u);
+        }
+    }
+    __syncthreads();
+    hist[(int64_t)tid * nblocks + blockIdx.x] = h[tid];
+}
+
+// In-place exclusive scan of a[0..len) by one workgroup of 1024 threads.
+__global__ void __launch_bounds__(1024) k_scan_single(uint32_t* __restrict__ a, int64_t len,
+                                                       uint32_t* __restrict__ total) {
+    __shared__ uint32_t sums[1024];
+    const int tid = threadIdx.x;
+    const int64_t per = (len + 1023) / 1024;
+    const int64_t b = tid * per;
+    const int64_t e = b + per < len ? b + per : len;
+    uint32_t s = 0;
+    for (int64_t i = b; i < e; i++) s += a[i];
+    sums[tid] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        uint32_t v = tid >= off ? sums[tid - off] : 0u;
+        __syncthreads();
+        sums[tid] += v;
+        __syncthreads();
+    }
+    uint32_t run = tid ? sums[tid - 1] : 0u;
+    for (int64_t i = b; i < e; i++) {
+        uint32_t v = a[i];
+        a[i] = run;
+        run += v;
+    }
+    if (total && tid == 1023) *total = sums[1023];
+}
+
+__global__ void __launch_bounds__(kThreads) k_rank_scatter(const uint64_t* __restrict__ kin,
+                                                            const uint32_t* __restrict__ vin,
+                                                            uint64_t* __restrict__ kout,
+                                                            uint32_t* __restrict__ vout, int64_t cap,
+                                                            const int64_t* n_dev, int shift,
+                                                            const uint32_t* __restrict__ offs, int nblocks) {
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t wcnt[kWaves][256];
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wave = tid / kWave;
+    const int64_t n = count_of(n_dev, cap);
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    if (base >= n) return;   // whole workgroup leaves together
+    run[tid] = offs[(int64_t)tid * nblocks + blockIdx.x];
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int i = 0; i < kItems; i++) {
+        const int64_t idx = base + (int64_t)i * kThreads + tid;
+        const bool valid = idx < n;
+        uint64_t key = valid ? kin[idx] : 0ull;
+        uint32_t val = valid ? (vin ? vin[idx] : (uint32_t)idx) : 0u;
+        uint32_t d = (uint32_t)(key >> shift) & 255u;
+#pragma unroll
+        for (int w = 0; w < kWaves; w++) wcnt[w][tid] = 0;
+        __syncthreads();
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; bit++) {
+            const bool on = (d >> bit) & 1u;
+            const uint64_t bal = __ballot(on);
+            peers &= on ? bal : ~bal;
+        }
+        const uint32_t rank = (uint32_t)__popcll(peers & lt);
+        if (valid && rank == 0) wcnt[wave][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        {
+            uint32_t r = run[tid];
+#pragma unroll
+            for (int w = 0; w < kWaves; w++) {
+                uint32_t c = wcnt[w][tid];
+                wcnt[w][tid] = r;
+                r += c;
+            }
+            run[tid] = r;
+        }
+        __syncthreads();
+        if (valid) {
+            const uint32_t dst = wcnt[wave][d] + rank;
+            kout[dst] = key;
+            vout[dst] = val;
+        }
+        __syncthreads();
+    }
+}
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+__global__ void __launch_bounds__(kScanThreads) k_block_sums(const uint32_t* __restrict__ in, int64_t cap,
+                                                              const int64_t* n_dev, uint32_t* __restrict__ sums) {
+    __shared__ uint32_t red[kScanThreads];
+    const int64_t n = count_of(n_dev, cap);
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    uint32_t s = 0;
+    for (int i = 0; i < kScanItems; i++)
+        if (base + i < n) s += in[base + i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = kScanThreads / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sums[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_block_scan(const uint32_t* __restrict__ in, int64_t cap,
+                                                              const int64_t* n_dev,
+                                                              const uint32_t* __restrict__ block_offs,
+                                                              const uint32_t* __restrict__ total,
+                                                              uint32_t* __restrict__ out) {
+    __shared__ uint32_t sc[kScanThreads];
+    const int64_t n = count_of(n_dev, cap);
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t s = 0;
+    for (int i = 0; i < kScanItems; i++) {
+        v[i] = base + i < n ? in[base + i] : 0u;
+        s += v[i];
+    }
+    sc[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+        uint32_t t = (int)threadIdx.x >= off ? sc[threadIdx.x - off] : 0u;
+        __syncthreads();
+        sc[threadIdx.x] += t;
+        __syncthreads();
+    }
+    uint32_t r = block_offs[blockIdx.x] + (threadIdx.x ? sc[threadIdx.x - 1] : 0u);
+    for (int i = 0; i < kScanItems; i++) {
+        if (base + i < n) out[base + i] = r;
+        r += v[i];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = *total;
+}
+
+}  // namespace
+
+int radix_sort_pairs(Workspace& ws, uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int64_t cap,
+                     const int64_t* n_dev, int begin_bit, int end_bit, hipStream_t st, int* out_index,
+                     bool iota_values) {
+    *out_index = 0;
+    if (cap <= 0) return RT_OK;
+    const int nblocks = (int)((cap + kTile - 1) / kTile);
+    const int64_t hlen = (int64_t)256 * nblocks;
+    if (ws.sort_hist.ensure(sizeof(uint32_t) * (size_t)hlen)) return RT_ENOMEM;
+    uint32_t* hist = ws.sort_hist.as<uint32_t>();
+    uint64_t* kin = k0;
+    uint32_t* vin = v0;
+    uint64_t* kout = k1;
+    uint32_t* vout = v1;
+    int cur = 0;
+    bool first = true;
+    for (int shift = begin_bit; shift < end_bit; shift += 8) {
+        hipLaunchKernelGGL(k_digit_hist, dim3(nblocks), dim3(kThreads), 0, st, kin, cap, n_dev, shift, hist,
+                           nblocks);
+        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, st, hist, hlen, (uint32_t*)nullptr);
+        hipLaunchKernelGGL(k_rank_scatter, dim3(nblocks), dim3(kThreads), 0, st, kin,
+                           first && iota_values ? (const uint32_t*)nullptr : vin, kout, vout, cap, n_dev,
+                           shift, hist, nblocks);
+        first = false;
+        std::swap(kin, kout);
+        std::swap(vin, vout);
+        cur ^= 1;
+    }
+    RT_HIP(hipGetLastError());
+    *out_index = cur;
+    return RT_OK;
+}
+
+int exclusive_scan_u32(Workspace& ws, const uint32_t* in, uint32_t* out, int64_t cap, const int64_t* n_dev,
+                       hipStream_t st) {
+    const int nblocks = (int)((cap + kScanTile - 1) / kScanTile);
+    const int nb = nblocks > 0 ? nblocks : 1;
+    if (ws.scan_tmp.ensure(sizeof(uint32_t) * (size_t)(nb + 1))) return RT_ENOMEM;
+    uint32_t* sums = ws.scan_tmp.as<uint32_t>();
+    hipLaunchKernelGGL(k_block_sums, dim3(nb), dim3(kScanThreads), 0, st, in, cap, n_dev, sums);
+    hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, st, sums, (int64_t)nb, sums + nb);
+    hipLaunchKernelGGL(k_block_scan, dim3(nb), dim3(kScanThreads), 0, st, in, cap, n_dev, sums, sums + nb, out);
+    RT_HIP(hipGetLastError());
+    return RT_OK;
+}
+
+}  // namespace rtac

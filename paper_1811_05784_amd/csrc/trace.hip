@@ -1,0 +1,575 @@
+// Ray generation and specular ray propagation (rt_fibonacci_directions,
+// rt_trace_rays).
+//
+// One persistent kernel runs every segment of every ray.  Each lane of a
+// 64-wide wavefront owns one ray and keeps its whole state in registers:
+// after a reflection it starts the next segment's nearest-hit query at once,
+// and when its ray stops it takes a new ray from a global pool (one atomic
+// per wavefront for all idle lanes).  Nothing round-trips to the host between
+// bounces and the ray state never goes back to HBM.
+//
+// Nearest hit (section "Standard algorithm": 0 <= lambda, mu, lambda + mu <= 1,
+// delta > 0 minimal) walks the 4-wide tree with an ordered short stack (16
+// entries per lane in LDS, spilling to a per-lane global area), a
+// conservative slab test for the child boxes (Williams et al.'s test, which
+// the paper uses to sort rays into daughter boxes) and the watertight FP32
+// ray/triangle test of Woop, Benthin and Wald (2013): shared edges are never
+// missed, exact ties go to the lowest triangle id.  Lanes whose query is
+// finished wait until enough of the wavefront is finished, then shade
+// together: the chosen triangle's plane crossing, receiver tests and the
+// reflection are evaluated in FP64 and rounded once to FP32.
+#include "common.h"
+
+namespace rtac {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kRing = 16;                 // LDS stack entries per lane
+constexpr int kSpillChunk = 8;
+
+enum : int { kIdle = 0, kQuery = 1, kDone = 2 };
+
+enum : unsigned long long { kErrStack = 1ull, kErrNode = 2ull, kErrSteps = 4ull };
+
+struct TraceArgs {
+    const Node4* nodes;
+    const float4* tri;
+    const double* plane_n;
+    int32_t n_nodes;
+    int32_t n_tri;
+    float src[3];
+    const float* origins;
+    const float* dirs;
+    const int32_t* start_plane;
+    const float* start_len;
+    int64_t n_rays;
+    const float* rcv;
+    int32_t n_rcv;
+    int32_t R;
+    float max_len;
+    int32_t record;
+    int32_t* hit_seq;
+    int32_t* det;
+    int64_t det_cap;
+    unsigned long long* counters;   // [0] n_det [1] queries [2] escapes [3] error
+    unsigned long long* pool;       // [0] next ray
+    float* states;
+    int32_t* spill;
+    int32_t spill_per_lane;
+    int32_t fetch_thr;
+    int32_t shade_thr;
+    int64_t max_steps;
+};
+
+__global__ void k_trace_reset(unsigned long long* counters, unsigned long long* pool) {
+    if (threadIdx.x < 4) counters[threadIdx.x] = 0ull;
+    if (threadIdx.x == 0) pool[0] = 0ull;
+}
+
+struct Ray {
+    float ox, oy, oz, ux, uy, uz;
+    float ix, iy, iz;      // reciprocal direction for the slab test
+    float sx, sy, sz;      // shear constants of the watertight test
+    int kx, ky, kz;
+};
+
+__device__ inline float pick(float a, float b, float c, int k) { return k == 0 ? a : (k == 1 ? b : c); }
+
+__device__ inline void setup_ray(Ray& r) {
+    const float ax = fabsf(r.ux), ay = fabsf(r.uy), az = fabsf(r.uz);
+    int kz = ax >= ay ? (ax >= az ? 0 : 2) : (ay >= az ? 1 : 2);
+    int kx = kz == 2 ? 0 : kz + 1;
+    int ky = kx == 2 ? 0 : kx + 1;
+    const float dz = pick(r.ux, r.uy, r.uz, kz);
+    if (dz < 0.f) {
+        int t = kx;
+        kx = ky;
+        ky = t;
+    }
+    r.kx = kx;
+    r.ky = ky;
+    r.kz = kz;
+    r.sx = pick(r.ux, r.uy, r.uz, kx) / dz;
+    r.sy = pick(r.ux, r.uy, r.uz, ky) / dz;
+    r.sz = 1.0f / dz;
+    const float tiny = 1e-20f;
+    r.ix = 1.0f / (fabsf(r.ux) > tiny ? r.ux : copysignf(tiny, r.ux));
+    r.iy = 1.0f / (fabsf(r.uy) > tiny ? r.uy : copysignf(tiny, r.uy));
+    r.iz = 1.0f / (fabsf(r.uz) > tiny ? r.uz : copysignf(tiny, r.uz));
+}
+
+// Watertight ray/triangle test.  Edge functions are evaluated without
+// contraction so that a shared edge gives exactly opposite values for the
+// two triangles that share it; zero values are re-evaluated in FP64.
+// Returns t > 0 on a hit, else -1.
+__device__ inline float watertight(const Ray& r, float4 v0, float4 v1, float4 v2) {
+#pragma clang fp contract(off)
+    const float a0 = v0.x - r.ox, a1 = v0.y - r.oy, a2 = v0.z - r.oz;
+    const float b0 = v1.x - r.ox, b1 = v1.y - r.oy, b2 = v1.z - r.oz;
+    const float c0 = v2.x - r.ox, c1 = v2.y - r.oy, c2 = v2.z - r.oz;
+    const float Akx = pick(a0, a1, a2, r.kx), Aky = pick(a0, a1, a2, r.ky), Akz = pick(a0, a1, a2, r.kz);
+    const float Bkx = pick(b0, b1, b2, r.kx), Bky = pick(b0, b1, b2, r.ky), Bkz = pick(b0, b1, b2, r.kz);
+    const float Ckx = pick(c0, c1, c2, r.kx), Cky = pick(c0, c1, c2, r.ky), Ckz = pick(c0, c1, c2, r.kz);
+    const float Ax = Akx - r.sx * Akz, Ay = Aky - r.sy * Akz;
+    const float Bx = Bkx - r.sx * Bkz, By = Bky - r.sy * Bkz;
+    const float Cx = Ckx - r.sx * Ckz, Cy = Cky - r.sy * Ckz;
+    float U = Cx * By - Cy * Bx;
+    float V = Ax * Cy - Ay * Cx;
+    float W = Bx * Ay - By * Ax;
+    if (U == 0.f || V == 0.f || W == 0.f) {
+        U = (float)((double)Cx * (double)By - (double)Cy * (double)Bx);
+        V = (float)((double)Ax * (double)Cy - (double)Ay * (double)Cx);
+        W = (float)((double)Bx * (double)Ay - (double)By * (double)Ax);
+    }
+    if ((U < 0.f || V < 0.f || W < 0.f) && (U > 0.f || V > 0.f || W > 0.f)) return -1.f;
+    float det = U + V + W;
+    if (det == 0.f) return -1.f;
+    const float Az = r.sz * Akz, Bz = r.sz * Bkz, Cz = r.sz * Ckz;
+    float T = U * Az + V * Bz + W * Cz;
+    if (det < 0.f) {
+        det = -det;
+        T = -T;
+    }
+    if (!(T > 0.f)) return -1.f;
+    return T / det;
+}
+
+struct Stack {
+    int base, cnt, gsp;
+};
+
+__device__ inline bool stack_push(Stack& s, int32_t* lds, int32_t* spill, int spill_n, int tid, int32_t item) {
+    if (s.cnt == kRing) {
+        if (s.gsp + kSpillChunk > spill_n) return false;
+        for (int i = 0; i < kSpillChunk; i++) spill[s.gsp + i] = lds[((s.base + i) & (kRing - 1)) * kBlock + tid];
+        s.gsp += kSpillChunk;
+        s.base = (s.base + kSpillChunk) & (kRing - 1);
+        s.cnt -= kSpillChunk;
+    }
+    lds[((s.base + s.cnt) & (kRing - 1)) * kBlock + tid] = item;
+    s.cnt++;
+    return true;
+}
+
+// Returns false when the stack is empty.
+__device__ inline bool stack_pop(Stack& s, int32_t* lds, const int32_t* spill, int tid, int32_t& item) {
+    if (s.cnt == 0) {
+        if (s.gsp == 0) return false;
+        const int h = s.gsp < kSpillChunk ? s.gsp : kSpillChunk;
+        s.gsp -= h;
+        s.base = (s.base - h) & (kRing - 1);
+        for (int i = 0; i < h; i++) lds[((s.base + i) & (kRing - 1)) * kBlock + tid] = spill[s.gsp + i];
+        s.cnt = h;
+    }
+    s.cnt--;
+    item = lds[((s.base + s.cnt) & (kRing - 1)) * kBlock + tid];
+    return true;
+}
+
+__device__ inline void cswap(float& ta, int32_t& ra, float& tb, int32_t& rb) {
+    if (tb < ta) {
+        float t = ta;
+        ta = tb;
+        tb = t;
+        int32_t q = ra;
+        ra = rb;
+        rb = q;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_trace(TraceArgs a) {
+    __shared__ int32_t lds_stack[kRing * kBlock];
+    __shared__ double rcv_s[kMaxRcv][4];
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    if (tid < a.n_rcv * 4) rcv_s[tid >> 2][tid & 3] = (double)a.rcv[tid];
+    __syncthreads();
+
+    int32_t* spill = a.spill + ((int64_t)blockIdx.x * kBlock + tid) * a.spill_per_lane;
+    const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
+    const int R1 = a.R + 1;
+
+    int status = kIdle;
+    int64_t ray = 0;
+    int k = 0;
+    float L = 0.f;
+    int32_t last_plane = -1;
+    Ray r;
+    r.ox = r.oy = r.oz = r.ux = r.uy = r.uz = 0.f;
+    setup_ray(r);
+    int32_t cur = 0;
+    Stack st{0, 0, 0};
+    float best_t = INFINITY;
+    int32_t best_j = -1, best_id = 0x7FFFFFFF;
+    int64_t steps = 0;
+    unsigned long long n_query = 0, n_escape = 0;
+    bool pool_empty = false;
+
+    for (;;) {
+        // ---- refill idle lanes from the ray pool -----------------------------
+        const uint64_t idle = __ballot(status == kIdle);
+        const int n_idle = __popcll(idle);
+        if (!pool_empty && n_idle > 0 && (n_idle >= a.fetch_thr || n_idle == kWave)) {
+            const int leader = __ffsll((long long)idle) - 1;
+            unsigned long long base = 0;
+            if (lane == leader) base = atomicAdd(a.pool, (unsigned long long)n_idle);
+            base = __shfl(base, leader);
+            if (base + (unsigned long long)n_idle >= (unsigned long long)a.n_rays) pool_empty = true;
+            if (status == kIdle) {
+                const unsigned long long my = base + (unsigned long long)__popcll(idle & lt_mask);
+                if (my < (unsigned long long)a.n_rays) {
+                    ray = (int64_t)my;
+                    if (a.origins) {
+                        r.ox = a.origins[3 * ray];
+                        r.oy = a.origins[3 * ray + 1];
+                        r.oz = a.origins[3 * ray + 2];
+                    } else {
+                        r.ox = a.src[0];
+                        r.oy = a.src[1];
+                        r.oz = a.src[2];
+                    }
+                    r.ux = a.dirs[3 * ray];
+                    r.uy = a.dirs[3 * ray + 1];
+                    r.uz = a.dirs[3 * ray + 2];
+                    L = a.start_len ? a.start_len[ray] : 0.f;
+                    last_plane = a.start_plane ? a.start_plane[ray] : -1;
+                    k = 0;
+                    setup_ray(r);
+                    cur = 0;
+                    st = Stack{0, 0, 0};
+                    best_t = INFINITY;
+                    best_j = -1;
+                    best_id = 0x7FFFFFFF;
+                    steps = 0;
+                    status = kQuery;
+                    if (r.ux == 0.f && r.uy == 0.f && r.uz == 0.f) status = kDone;   // degenerate: escapes
+                }
+            }
+        }
+        if (__ballot(status != kIdle) == 0ull) {
+            if (pool_empty) break;
+            continue;
+        }
+
+        // ---- traverse until enough lanes have finished their query -----------
+        for (;;) {
+            const uint64_t q = __ballot(status == kQuery);
+            if (q == 0ull) break;
+            if (__popcll(__ballot(status == kDone)) >= a.shade_thr) break;
+            if (status != kQuery) continue;
+            bool have = true;
+            if (++steps > a.max_steps) {
+                atomicOr(&a.counters[3], kErrSteps);
+                best_j = -1;
+                status = kDone;
+                continue;
+            }
+            if (cur >= 0) {
+                if (cur >= a.n_nodes) {
+                    atomicOr(&a.counters[3], kErrNode);
+                    best_j = -1;
+                    status = kDone;
+                    continue;
+                }
+                const float4* np = reinterpret_cast<const float4*>(a.nodes + cur);
+                const float4 lx = np[0], hx = np[1], ly = np[2], hy = np[3], lz = np[4], hz = np[5];
+                const int4 ch = reinterpret_cast<const int4*>(np)[6];
+                const float tlim = best_t;
+                float tn[4];
+                int32_t rf[4];
+#define RT_SLAB(S, LX, HX, LY, HY, LZ, HZ, CH)                                          \
+    {                                                                                    \
+        const float t0x = (LX - r.ox) * r.ix, t1x = (HX - r.ox) * r.ix;                  \
+        const float t0y = (LY - r.oy) * r.iy, t1y = (HY - r.oy) * r.iy;                  \
+        const float t0z = (LZ - r.oz) * r.iz, t1z = (HZ - r.oz) * r.iz;                  \
+        const float tmin = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)),               \
+                                 fmaxf(fminf(t0z, t1z), 0.f));                           \
+        float tmax = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z));    \
+        tmax *= 1.00000036f;                                                             \
+        const bool h = (CH != kEmpty) && tmin <= tmax && tmin <= tlim;                   \
+        tn[S] = h ? tmin : INFINITY;                                                     \
+        rf[S] = CH;                                                                      \
+    }
+                RT_SLAB(0, lx.x, hx.x, ly.x, hy.x, lz.x, hz.x, ch.x)
+                RT_SLAB(1, lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, ch.y)
+                RT_SLAB(2, lx.z, hx.z, ly.z, hy.z, lz.z, hz.z, ch.z)
+                RT_SLAB(3, lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, ch.w)
+#undef RT_SLAB
+                cswap(tn[0], rf[0], tn[1], rf[1]);
+                cswap(tn[2], rf[2], tn[3], rf[3]);
+                cswap(tn[0], rf[0], tn[2], rf[2]);
+                cswap(tn[1], rf[1], tn[3], rf[3]);
+                cswap(tn[1], rf[1], tn[2], rf[2]);
+                const int nh = (tn[0] < INFINITY) + (tn[1] < INFINITY) + (tn[2] < INFINITY) + (tn[3] < INFINITY);
+                bool ok = true;
+                if (nh > 3) ok &= stack_push(st, lds_stack, spill, a.spill_per_lane, tid, rf[3]);
+                if (nh > 2) ok &= stack_push(st, lds_stack, spill, a.spill_per_lane, tid, rf[2]);
+                if (nh > 1) ok &= stack_push(st, lds_stack, spill, a.spill_per_lane, tid, rf[1]);
+                if (!ok) {
+                    atomicOr(&a.counters[3], kErrStack);
+                    best_j = -1;
+                    status = kDone;
+                    continue;
+                }
+                if (nh > 0)
+                    cur = rf[0];
+                else
+                    have = stack_pop(st, lds_stack, spill, tid, cur);
+            } else {
+                const int32_t first = leaf_first(cur), cnt = leaf_count(cur);
+                if (first + cnt > a.n_tri) {
+                    atomicOr(&a.counters[3], kErrNode);
+                    best_j = -1;
+                    status = kDone;
+                    continue;
+                }
+                for (int i = 0; i < cnt; i++) {
+                    const int32_t j = first + i;
+                    const float4 v0 = a.tri[3 * j], v1 = a.tri[3 * j + 1], v2 = a.tri[3 * j + 2];
+                    if (__float_as_int(v0.w) == last_plane) continue;
+                    const float t = watertight(r, v0, v1, v2);
+                    const int32_t id = __float_as_int(v1.w);
+                    if (t > 0.f && (t < best_t || (t == best_t && id < best_id))) {
+                        best_t = t;
+                        best_j = j;
+                        best_id = id;
+                    }
+                }
+                have = stack_pop(st, lds_stack, spill, tid, cur);
+            }
+            if (!have) status = kDone;
+        }
+
+        // ---- shade the finished queries (FP64), record, reflect ---------------
+        const bool shading = status == kDone;
+        uint32_t dm = 0;
+        double dl = INFINITY;
+        int32_t hit_id = -1, hit_plane = -1;
+        const double ox = r.ox, oy = r.oy, oz = r.oz, ux = r.ux, uy = r.uy, uz = r.uz;
+        const double uu = ux * ux + uy * uy + uz * uz;
+        if (shading) {
+            if (best_j >= 0) {
+                const float4 v0 = a.tri[3 * best_j], v1 = a.tri[3 * best_j + 1], v2 = a.tri[3 * best_j + 2];
+                hit_plane = __float_as_int(v0.w);
+                hit_id = __float_as_int(v1.w);
+                const double e1x = (double)v1.x - v0.x, e1y = (double)v1.y - v0.y, e1z = (double)v1.z - v0.z;
+                const double e2x = (double)v2.x - v0.x, e2y = (double)v2.y - v0.y, e2z = (double)v2.z - v0.z;
+                const double nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
+                const double num = ((double)v0.x - ox) * nx + ((double)v0.y - oy) * ny + ((double)v0.z - oz) * nz;
+                const double den = ux * nx + uy * ny + uz * nz;
+                dl = num / den;
+                if (!(dl > 0.0)) dl = 0.0;
+            }
+            if (uu > 0.0) {
+                for (int m = 0; m < a.n_rcv; m++) {
+                    const double wx = rcv_s[m][0] - ox, wy = rcv_s[m][1] - oy, wz = rcv_s[m][2] - oz;
+                    double ts = (wx * ux + wy * uy + wz * uz) / uu;
+                    if (ts < 0.0) ts = 0.0;
+                    if (ts > dl) ts = dl;
+                    const double qx = ox + ts * ux - rcv_s[m][0];
+                    const double qy = oy + ts * uy - rcv_s[m][1];
+                    const double qz = oz + ts * uz - rcv_s[m][2];
+                    if (qx * qx + qy * qy + qz * qz <= rcv_s[m][3] * rcv_s[m][3]) dm |= 1u << m;
+                }
+            }
+        }
+        // wave-wide append of detections: one atomic per wavefront
+        {
+            const int c = __popc(dm);
+            int incl = c;
+#pragma unroll
+            for (int off = 1; off < kWave; off <<= 1) {
+                const int t = __shfl_up(incl, off);
+                if (lane >= off) incl += t;
+            }
+            const int total = __shfl(incl, kWave - 1);
+            if (total > 0) {
+                unsigned long long base = 0;
+                if (lane == 0) base = atomicAdd(&a.counters[0], (unsigned long long)total);
+                base = __shfl(base, 0);
+                unsigned long long pos = base + (unsigned long long)(incl - c);
+                uint32_t bits = dm;
+                while (bits) {
+                    const int m = __ffs(bits) - 1;
+                    bits &= bits - 1;
+                    if (pos < (unsigned long long)a.det_cap) {
+                        int32_t* d = a.det + 3 * pos;
+                        d[0] = (int32_t)ray;
+                        d[1] = k;
+                        d[2] = m;
+                    }
+                    pos++;
+                }
+            }
+        }
+        if (shading) {
+            n_query++;
+            int32_t* hs = a.hit_seq + ray * R1;
+            hs[k] = hit_id;
+            if (a.record) {
+                float* sp = a.states + (ray * (R1 + 1) + k) * 8;
+                sp[0] = r.ox;
+                sp[1] = r.oy;
+                sp[2] = r.oz;
+                sp[3] = r.ux;
+                sp[4] = r.uy;
+                sp[5] = r.uz;
+                sp[6] = L;
+                sp[7] = __int_as_float(last_plane);
+            }
+            bool stop = true;
+            if (hit_id < 0) {
+                n_escape++;
+            } else {
+                const double nx = a.plane_n[3 * (int64_t)hit_plane], ny = a.plane_n[3 * (int64_t)hit_plane + 1],
+                             nz = a.plane_n[3 * (int64_t)hit_plane + 2];
+                const double udn = ux * nx + uy * ny + uz * nz;
+                const double Ln = (double)L + dl * sqrt(uu);
+                r.ox = (float)(ox + dl * ux);
+                r.oy = (float)(oy + dl * uy);
+                r.oz = (float)(oz + dl * uz);
+                r.ux = (float)(ux - 2.0 * udn * nx);
+                r.uy = (float)(uy - 2.0 * udn * ny);
+                r.uz = (float)(uz - 2.0 * udn * nz);
+                L = (float)Ln;
+                last_plane = hit_plane;
+                stop = (k == a.R) || (a.max_len > 0.f && Ln >= (double)a.max_len);
+                if (a.record) {
+                    float* sp = a.states + (ray * (R1 + 1) + k + 1) * 8;
+                    sp[0] = r.ox;
+                    sp[1] = r.oy;
+                    sp[2] = r.oz;
+                    sp[3] = r.ux;
+                    sp[4] = r.uy;
+                    sp[5] = r.uz;
+                    sp[6] = L;
+                    sp[7] = __int_as_float(last_plane);
+                }
+            }
+            if (stop) {
+                for (int kk = k + 1; kk < R1; kk++) hs[kk] = -1;
+                status = kIdle;
+            } else {
+                k++;
+                setup_ray(r);
+                cur = 0;
+                st = Stack{0, 0, 0};
+                best_t = INFINITY;
+                best_j = -1;
+                best_id = 0x7FFFFFFF;
+                steps = 0;
+                status = kQuery;
+            }
+        }
+    }
+    // per-wave totals
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        n_query += __shfl_down(n_query, off);
+        n_escape += __shfl_down(n_escape, off);
+    }
+    if (lane == 0) {
+        if (n_query) atomicAdd(&a.counters[1], n_query);
+        if (n_escape) atomicAdd(&a.counters[2], n_escape);
+    }
+}
+
+// Fibonacci sphere: z_i = 1 - (2i+1)/n, phi_i = i pi (3 - sqrt5) mod 2 pi.
+__global__ void k_fibonacci(int64_t n, float* __restrict__ out) {
+#pragma clang fp contract(off)
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double pi = 3.14159265358979323846;
+    const double golden = pi * (3.0 - sqrt(5.0));
+    const double two_pi = 2.0 * pi;
+    const double z = 1.0 - (double)(2 * i + 1) / (double)n;
+    const double phi = fmod((double)i * golden, two_pi);
+    const double zz = z * z;
+    const double rho = sqrt(1.0 - zz);
+    const double x = rho * cos(phi);
+    const double y = rho * sin(phi);
+    out[3 * i + 0] = (float)x;
+    out[3 * i + 1] = (float)y;
+    out[3 * i + 2] = (float)z;
+}
+
+}  // namespace
+
+}  // namespace rtac
+
+using namespace rtac;
+
+extern "C" int rt_fibonacci_directions(int64_t n, float* dirs, void* stream) {
+    RT_CHECK(n >= 0, RT_EINVAL, "rt_fibonacci_directions: n < 0");
+    if (n == 0) return RT_OK;
+    RT_CHECK(dirs != nullptr, RT_EINVAL, "rt_fibonacci_directions: dirs is NULL");
+    hipLaunchKernelGGL(k_fibonacci, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, n, dirs);
+    RT_HIP(hipGetLastError());
+    return RT_OK;
+}
+
+extern "C" int rt_trace_rays(const rt_scene* scene, const float* src_host, const float* origins, const float* dirs,
+                             const int32_t* start_plane, const float* start_len, int64_t n_rays, const float* rcv,
+                             int32_t n_rcv, const rt_trace_params* p, int32_t* hit_seq, int32_t* det, int64_t det_cap,
+                             int64_t* counters, float* states, void* stream) {
+    RT_CHECK(scene && p, RT_EINVAL, "rt_trace_rays: null scene or params");
+    RT_CHECK(n_rays >= 0 && n_rays < ((int64_t)1 << 31), RT_EINVAL, "rt_trace_rays: n_rays out of range");
+    RT_CHECK(p->max_reflections >= 0 && p->max_reflections < 4096, RT_EINVAL,
+             "rt_trace_rays: max_reflections must be in [0, 4096)");
+    RT_CHECK(n_rcv >= 0 && n_rcv <= kMaxRcv, RT_EINVAL, "rt_trace_rays: n_rcv must be in [0, %d]", kMaxRcv);
+    RT_CHECK(n_rcv == 0 || rcv, RT_EINVAL, "rt_trace_rays: rcv is NULL");
+    RT_CHECK(counters, RT_EINVAL, "rt_trace_rays: counters is NULL");
+    RT_CHECK(det_cap >= 0 && (det_cap == 0 || det), RT_EINVAL, "rt_trace_rays: det is NULL");
+    RT_CHECK(!p->record_states || states, RT_EINVAL, "rt_trace_rays: record_states needs states");
+    RT_CHECK(origins || src_host, RT_EINVAL, "rt_trace_rays: need src_host or origins");
+    RT_CHECK(n_rays == 0 || (dirs && hit_seq), RT_EINVAL, "rt_trace_rays: dirs/hit_seq is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    rt_scene* s = const_cast<rt_scene*>(scene);
+    if (s->ws.trace_pool.ensure(64)) return RT_ENOMEM;
+    unsigned long long* pool = s->ws.trace_pool.as<unsigned long long>();
+    hipLaunchKernelGGL(k_trace_reset, dim3(1), dim3(64), 0, st, (unsigned long long*)counters, pool);
+    if (n_rays == 0) {
+        RT_HIP(hipGetLastError());
+        return RT_OK;
+    }
+    const int bpc = p->blocks_per_cu > 0 ? p->blocks_per_cu : 4;
+    int64_t nblk = (int64_t)device_sm_count() * bpc;
+    const int64_t need = (n_rays + kBlock - 1) / kBlock;
+    if (nblk > need) nblk = need;
+    if (nblk < 1) nblk = 1;
+    const int spill_n = ((3 * (s->depth + 1) + 2 * kSpillChunk) / kSpillChunk + 1) * kSpillChunk;
+    if (s->ws.stack_spill.ensure(sizeof(int32_t) * (size_t)nblk * kBlock * spill_n)) return RT_ENOMEM;
+    TraceArgs a;
+    a.nodes = s->nodes;
+    a.tri = s->tri_rec;
+    a.plane_n = s->plane_n;
+    a.n_nodes = s->n_nodes;
+    a.n_tri = (int32_t)s->n_tri;
+    a.src[0] = src_host ? src_host[0] : 0.f;
+    a.src[1] = src_host ? src_host[1] : 0.f;
+    a.src[2] = src_host ? src_host[2] : 0.f;
+    a.origins = origins;
+    a.dirs = dirs;
+    a.start_plane = start_plane;
+    a.start_len = start_len;
+    a.n_rays = n_rays;
+    a.rcv = rcv;
+    a.n_rcv = n_rcv;
+    a.R = p->max_reflections;
+    a.max_len = p->max_path_length;
+    a.record = p->record_states ? 1 : 0;
+    a.hit_seq = hit_seq;
+    a.det = det;
+    a.det_cap = det_cap;
+    a.counters = (unsigned long long*)counters;
+    a.pool = pool;
+    a.states = states;
+    a.spill = s->ws.stack_spill.as<int32_t>();
+    a.spill_per_lane = spill_n;
+    a.fetch_thr = p->fetch_threshold > 0 ? p->fetch_threshold : 16;
+    a.shade_thr = p->shade_threshold > 0 ? p->shade_threshold : 16;
+    a.max_steps = 8 * ((int64_t)s->n_nodes + s->n_tri) + 4096;
+    hipLaunchKernelGGL(k_trace, dim3((unsigned)nblk), dim3(kBlock), 0, st, a);
+    RT_HIP(hipGetLastError());
+    return RT_OK;
+}

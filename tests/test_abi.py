@@ -1,0 +1,64 @@
+"""Boundary checks that need no GPU: the library loads, exports every entry
+point the public header declares, and rejects bad arguments before touching
+the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "rtac.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rt_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_1811_05784_amd as rt
+    return rt.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_1811_05784_amd import _lib
+    names = _declared()
+    assert "rt_trace_rays" in names and "rt_build_tree" in names and len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in _lib.SIGNATURES, n
+    assert set(_lib.SIGNATURES) == set(names)
+
+
+def test_version_and_error_strings(lib):
+    assert b"gfx950" in lib.rt_version()
+
+
+def test_argument_validation_without_device(lib):
+    P = ctypes.c_void_p
+    out = P()
+    assert lib.rt_build_tree(None, 0, None, 0, None, None, None, None, ctypes.byref(out)) == -1
+    assert b"null" in lib.rt_last_error().lower()
+    assert lib.rt_fibonacci_directions(-1, None, None) == -1
+    assert lib.rt_fibonacci_directions(0, None, None) == 0
+    assert lib.rt_trace_rays(None, None, None, None, None, None, 0, None, 0, None, None, None, 0, None, None,
+                             None) == -1
+    assert lib.rt_collect_image_sources(None, None, None, 0, None, 0, 0, None, 0, None, None, None, None, None, 0,
+                                        None, None) == -1
+    assert lib.rt_assemble_ir(None, None, None, None, None, 0, 0, 0, 0, None, None, 343.0, 48000.0, 10, None, 1,
+                              None, None, None, None, None) == -1
+    assert lib.rt_band_energy_adjoint(None, None, None, None, None, 0, 0, 0, 0, None, 0, None, 343.0, 48000.0, 10,
+                                      None, None, None) == -1
+    assert lib.rt_debug_set_hash_bits(0) == -1
+    assert lib.rt_debug_set_hash_bits(64) == 0
+    assert lib.rt_scene_destroy(None) == 0
+
+
+def test_product_path_fails_loudly_without_library(tmp_path, monkeypatch):
+    from paper_1811_05784_amd import _lib
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(ImportError):
+        _lib.load()

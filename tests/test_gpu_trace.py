@@ -1,0 +1,215 @@
+"""GPU parity of ray generation and ray propagation against the FP64 oracle.
+
+* Fibonacci directions: FP64 on both sides, rounded once; the two libms may
+  differ by one FP64 ulp in cos/sin, so FP32 results agree to <= 1 ulp.
+* One-segment queries from seeded states (on-surface origins excluding their
+  own plane, interior origins): the nearest-hit triangle and the detections
+  must equal the oracle's unless the oracle flags the query; the next state
+  (o', u', L') is FP64 rounded once on the GPU, so it is within 1 FP32 ulp of
+  the oracle's FP64 value (plus the FP32 rounding of sub-ulp differences in
+  delta: a tolerance of 2 ulp of the coordinate magnitude, relative 1e-9 of
+  the step for values near zero).
+* Full trajectories on the 12-triangle shoebox from the same FP32 directions:
+  every ray's hit sequence equals the oracle's, or first differs at a query
+  the oracle flags.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from tests._util import ulp_diff
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rt():
+    import paper_1811_05784_amd as m
+    m.load()
+    return m
+
+
+@pytest.fixture(scope="module")
+def scenes(rt):
+    out = {}
+    for name, mk in [("c1", synth.shoebox_c1), ("c2", lambda: synth.tessellated_box_c2(jitter=True)),
+                     ("c2flat", lambda: synth.tessellated_box_c2(jitter=False)), ("c3", synth.theater_c3)]:
+        s = mk()
+        out[name] = (s, rt.Scene.from_synth(s, device="cuda:0"))
+    return out
+
+
+@pytest.mark.parametrize("n", [1, 7, 1000, 65_537, 1_000_000])
+def test_fibonacci_matches_oracle(rt, oracle_lib, n):
+    _say("fibonacci n=%d" % n)
+    g = rt.fibonacci_directions(n, device="cuda:0").cpu().numpy()
+    o = oracle_lib.fibonacci(n)
+    d = ulp_diff(g, o)
+    assert d.max() <= 1
+    assert (d == 0).mean() > 0.9999
+
+
+def test_build_tree_reports(rt, scenes):
+    for name, (s, sc) in scenes.items():
+        _say("scene", name, sc.n_tri, sc.n_nodes, sc.depth, sc.n_mat)
+        assert sc.n_tri == s.n_tri and sc.n_mat == s.n_mat
+        assert abs(sc.diag - s.diag()) < 1e-5 * s.diag()
+        assert 1 <= sc.n_nodes <= s.n_tri and 1 <= sc.depth <= 64
+
+
+def test_build_tree_rejects_bad_meshes(rt):
+    s = synth.shoebox_c1()
+    bad_idx = s.tri.copy()
+    bad_idx[3, 1] = 99
+    with pytest.raises(rt.RtError, match="index"):
+        rt.Scene(s.vtx, bad_idx, s.material, s.plane_id)
+    degenerate = s.vtx.copy()
+    t = s.tri[0]
+    degenerate[t[1]] = degenerate[t[0]]
+    with pytest.raises(rt.RtError):
+        rt.Scene(degenerate, s.tri, s.material, s.plane_id)
+    plane = s.plane_id.copy()
+    plane[plane == plane[2]] = plane[0]          # two walls claimed coplanar
+    with pytest.raises(rt.RtError, match="plane"):
+        rt.Scene(s.vtx, s.tri, s.material, plane)
+    mat = s.material.copy()
+    mat[1] = (mat[0] + 1) % 6                    # same wall, two materials
+    with pytest.raises(rt.RtError, match="material"):
+        rt.Scene(s.vtx, s.tri, mat, s.plane_id)
+    nan = s.vtx.copy()
+    nan[0, 0] = np.nan
+    with pytest.raises(rt.RtError):
+        rt.Scene(nan, s.tri, s.material, s.plane_id)
+
+
+def _query_parity(rt, oracle_lib, s, sc, o, u, lp, L, tag):
+    n = len(o)
+    tr = rt.trace_rays(sc, u, s.rcv, 1, origins=o, start_plane=lp, start_len=L, record_states=True)
+    hit = tr.hit_seq[:, 0].cpu().numpy()
+    det = tr.detections().cpu().numpy()
+    gdet = np.zeros(n, np.uint32)
+    d0 = det[det[:, 1] == 0]
+    np.bitwise_or.at(gdet, d0[:, 0], (np.uint32(1) << d0[:, 2].astype(np.uint32)))
+    nxt = tr.states[:, 1, :7].cpu().numpy()
+    osc = oracle_lib.OracleScene.of(s)
+    ref = oracle_lib.query_batch(osc, o, u, lp, L, s.rcv)
+    flagged = ref["flags"] != 0
+    bad_hit = (hit != ref["hit"]) & ~flagged
+    bad_det = (gdet != ref["det"]) & ~flagged
+    both = (hit == ref["hit"]) & (hit >= 0)
+    on = ref["next"][both]
+    gn = nxt[both]
+    mag = np.maximum(np.abs(on[:, :3]), np.abs(o[both]).astype(np.float64)).max(1, keepdims=True)
+    ulp_o = np.spacing(mag.astype(np.float32)).astype(np.float64)
+    err_o = np.abs(gn[:, :3] - on[:, :3])
+    err_u = ulp_diff(gn[:, 3:6], on[:, 3:6].astype(np.float32))
+    err_L = np.abs(gn[:, 6] - on[:, 6]) / np.spacing(np.abs(on[:, 6]).astype(np.float32))
+    _say("%s: n=%d flagged=%d hit-mismatch(flagged)=%d unflagged hit=%d det=%d escapes=%d max|do|/ulp=%.2f "
+         "max du ulp=%d max dL ulp=%.2f" % (tag, n, flagged.sum(), ((hit != ref["hit"]) & flagged).sum(),
+                                          bad_hit.sum(), bad_det.sum(), (hit < 0).sum(),
+                                          (err_o / ulp_o).max() if len(gn) else 0,
+                                          err_u.max() if len(gn) else 0, err_L.max() if len(gn) else 0))
+    assert bad_hit.sum() == 0
+    assert bad_det.sum() == 0
+    assert np.all(err_o <= 2 * ulp_o)
+    assert err_u.max() <= 2
+    assert np.all(err_L <= 2)
+    assert int(tr.counters[3]) == 0
+    return flagged.mean()
+
+
+@pytest.mark.parametrize("name,n", [("c1", 20_000), ("c2", 30_000), ("c2flat", 20_000), ("c3", 8_000)])
+def test_surface_query_parity(rt, oracle_lib, scenes, name, n):
+    s, sc = scenes[name]
+    toward = (5.0, 3.5, 1.5) if name.startswith("c") and name != "c3" else None
+    o, u, lp, L = synth.surface_query_states(s, n, seed=100 + n, toward=toward)
+    frac = _query_parity(rt, oracle_lib, s, sc, o, u, lp, L, "surface " + name)
+    assert frac < 0.02
+
+
+@pytest.mark.parametrize("name,n", [("c2", 20_000), ("c3", 8_000)])
+def test_interior_query_parity(rt, oracle_lib, scenes, name, n):
+    s, sc = scenes[name]
+    o, u, lp, L = synth.interior_query_states(s, n, seed=7 + n)
+    _query_parity(rt, oracle_lib, s, sc, o, u, lp, L, "interior " + name)
+
+
+def test_c1_trajectory_parity(rt, oracle_lib, scenes):
+    s, sc = scenes["c1"]
+    dirs = oracle_lib.fibonacci(s.n_rays)
+    tr = rt.trace_rays(sc, dirs, s.rcv, s.max_reflections, src=s.src, max_path_length=s.max_path_length)
+    hs = tr.hit_seq.cpu().numpy()
+    osc = oracle_lib.OracleScene.of(s)
+    ref = oracle_lib.trace(osc, s.src, dirs, s.rcv, s.max_reflections, max_len=s.max_path_length)
+    diff = (hs != ref["hit_seq"]).any(axis=1)
+    unflagged = 0
+    for i in np.nonzero(diff)[0]:
+        k = int(np.argmax(hs[i] != ref["hit_seq"][i]))
+        if not ref["flags"][i, : k + 1].any():
+            unflagged += 1
+    # detections of rays whose whole sequence agrees and is unflagged
+    good = ~diff & ~ref["flags"].any(axis=1)
+    det = tr.detections().cpu().numpy()
+    gbits = np.zeros_like(ref["det"])
+    np.bitwise_or.at(gbits, (det[:, 0], det[:, 1]), (np.uint32(1) << det[:, 2].astype(np.uint32)))
+    det_bad = (gbits[good] != ref["det"][good]).any(axis=1).sum()
+    _say("c1 trajectories: rays=%d differing=%d unflagged-first-divergence=%d flagged-rays=%d det-bad=%d "
+         "queries=%d" % (len(hs), diff.sum(), unflagged, ref["flags"].any(axis=1).sum(), det_bad,
+                         int(tr.counters[1])))
+    assert unflagged == 0
+    assert det_bad == 0
+    # closed room: nothing escapes, every ray ends by the path-length stop or R
+    assert int(tr.counters[2]) == 0
+    assert int(tr.counters[1]) == int((hs >= 0).sum())
+
+
+def test_determinism_and_batch_invariance(rt, scenes):
+    s, sc = scenes["c2"]
+    dirs = rt.fibonacci_directions(50_000, device="cuda:0")
+    a = rt.trace_rays(sc, dirs, s.rcv, 20, src=s.src)
+    b = rt.trace_rays(sc, dirs, s.rcv, 20, src=s.src, shade_threshold=1, fetch_threshold=1, blocks_per_cu=1)
+    assert torch.equal(a.hit_seq, b.hit_seq)
+    sub = torch.arange(123, 50_000, 977, device="cuda:0")
+    c = rt.trace_rays(sc, dirs[sub], s.rcv, 20, src=s.src)
+    assert torch.equal(c.hit_seq, a.hit_seq[sub])
+    da = a.detections().cpu().numpy()
+    db = b.detections().cpu().numpy()
+    sa = da[np.lexsort(da.T[::-1])]
+    sb = db[np.lexsort(db.T[::-1])]
+    assert np.array_equal(sa, sb)
+
+
+def test_edge_cases(rt, scenes):
+    s, sc = scenes["c1"]
+    # no rays
+    tr = rt.trace_rays(sc, np.zeros((0, 3), np.float32), s.rcv, 3, src=s.src)
+    assert tr.hit_seq.shape == (0, 4) and int(tr.counters[1]) == 0
+    # R = 0: one segment each; a zero direction escapes without detections
+    d = np.array([[1, 0, 0], [0, 0, 0], [0, 0.6, 0.8]], np.float32)
+    tr = rt.trace_rays(sc, d, s.rcv, 0, src=s.src)
+    hs = tr.hit_seq.cpu().numpy()
+    assert hs.shape == (3, 1) and hs[0, 0] >= 0 and hs[1, 0] == -1 and hs[2, 0] >= 0
+    assert int(tr.counters[1]) == 3 and int(tr.counters[2]) == 1
+    # single-triangle open scene: rays miss and escape
+    one = rt.Scene(np.array([[0, 0, 5], [1, 0, 5], [0, 1, 5]], np.float32), np.array([[0, 1, 2]], np.int32),
+                   np.zeros(1, np.int32))
+    d = np.array([[0.04, 0.04, 1.0], [0, 0, -1.0], [0.02, 0.1, 1.0]], np.float32)
+    tr = rt.trace_rays(one, d, np.array([[0, 0, -3, 0.8]], np.float32), 4, src=np.zeros(3))
+    hs = tr.hit_seq.cpu().numpy()
+    assert hs[0, 0] == 0 and hs[0, 1] == -1 and hs[1, 0] == -1 and hs[2, 0] == 0
+    assert int(tr.counters[0]) == 2           # ray 0 after its reflection, ray 1 directly
+    # detection capacity overflow: reported and retried by the wrapper
+    dirs = rt.fibonacci_directions(20_000, device="cuda:0")
+    small = rt.trace_rays(sc, dirs, s.rcv, 20, src=s.src, det_cap=16, check_capacity=False)
+    need = int(small.counters[0])
+    assert need > 16
+    full = rt.trace_rays(sc, dirs, s.rcv, 20, src=s.src, det_cap=16)
+    assert full.n_det() == need and full.det.shape[0] >= need
