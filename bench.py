@@ -44,6 +44,8 @@ def main():
     ap.add_argument("--shade", type=int, default=0)
     ap.add_argument("--fetch", type=int, default=0)
     ap.add_argument("--bpc", type=int, default=0)
+    ap.add_argument("--keep-order", action="store_true")
+    ap.add_argument("--stats", action="store_true", help="count traversal work (extra pass, not timed)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (the ray set would be split "
@@ -92,7 +94,7 @@ def main():
         mark("trace", 0)
         tr = rt.trace_rays(sc, dirs, rcv, R, src=s.src, max_path_length=s.max_path_length, det_cap=det_cap,
                            check_capacity=False, out=state.get("tr"), shade_threshold=args.shade,
-                           fetch_threshold=args.fetch, blocks_per_cu=args.bpc)
+                           fetch_threshold=args.fetch, blocks_per_cu=args.bpc, keep_order=args.keep_order)
         mark("trace", 1)
         state["tr"] = tr
         mark("collect", 0)
@@ -156,6 +158,15 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_trace", "bytes_per_query": B},
     }
+    if args.stats:
+        st = torch.zeros(4, dtype=torch.int64, device=dev)
+        sc = state["scene"]
+        rt.trace_rays(sc, rt.fibonacci_directions(args.rays, device=dev), rcv, R, src=s.src,
+                      max_path_length=s.max_path_length, det_cap=det_cap, stats=st, keep_order=args.keep_order)
+        st = st.cpu().tolist()
+        out["traversal_per_query"] = {"inner_nodes": st[0] / queries, "leaves": st[1] / queries,
+                                      "triangles": st[2] / queries, "spills": st[3] / queries,
+                                      "tree_nodes": sc.n_nodes, "tree_depth": sc.depth}
     # IR band error vs the oracle on a seeded image-source table of this shape
     try:
         out["ir_band_error"] = band_error(rt, state["scene"], s, taps)

@@ -106,6 +106,10 @@ typedef struct {
     int32_t fetch_threshold;   /* 0 = default; lanes idle before a wave fetches new rays       */
     int32_t shade_threshold;   /* 0 = default; finished queries before a wave shades them      */
     int32_t blocks_per_cu;     /* 0 = default; persistent workgroups per compute unit          */
+    int32_t keep_order;        /* 0: rays are handed to wavefronts sorted by a Morton key of
+                                  their direction (and origin) for coherence; 1: in index order */
+    int64_t* stats;            /* NULL or device int64[4], overwritten: inner nodes visited,
+                                  leaves visited, triangle tests, stack spills                  */
 } rt_trace_params;
 
 /*

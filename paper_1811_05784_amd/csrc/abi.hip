@@ -1,6 +1,8 @@
 // Error reporting, scratch buffers, scene lifetime and small host queries.
 #include <cstdarg>
 #include <cstring>
+#include <map>
+#include <mutex>
 
 #include "common.h"
 
@@ -15,23 +17,82 @@ void set_error(const char* fmt, ...) {
     va_end(ap);
 }
 
+namespace {
+struct Cache {
+    std::mutex mu;
+    std::map<void*, std::pair<int, size_t>> live;          // ptr -> (device, bytes)
+    std::multimap<std::pair<int, size_t>, void*> free_;    // (device, bytes) -> ptr
+};
+Cache& cache() {
+    static Cache* c = new Cache();   // never destroyed: freed blocks live until exit
+    return *c;
+}
+}  // namespace
+
+void* dcache_alloc(size_t bytes) {
+    if (bytes == 0) bytes = 1;
+    bytes = (bytes + 255) & ~(size_t)255;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    Cache& c = cache();
+    {
+        std::lock_guard<std::mutex> g(c.mu);
+        auto it = c.free_.lower_bound({dev, bytes});
+        if (it != c.free_.end() && it->first.first == dev && it->first.second <= 2 * bytes) {
+            void* p = it->second;
+            c.live[p] = it->first;
+            c.free_.erase(it);
+            return p;
+        }
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        // give cached blocks back to the runtime and retry once
+        std::lock_guard<std::mutex> g(c.mu);
+        for (auto it = c.free_.begin(); it != c.free_.end();) {
+            if (it->first.first == dev) {
+                (void)hipFree(it->second);
+                it = c.free_.erase(it);
+            } else {
+                ++it;
+            }
+        }
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("hipMalloc of %zu bytes failed", bytes);
+            return nullptr;
+        }
+    }
+    std::lock_guard<std::mutex> g(c.mu);
+    c.live[p] = {dev, bytes};
+    return p;
+}
+
+void dcache_free(void* p) {
+    if (!p) return;
+    Cache& c = cache();
+    std::lock_guard<std::mutex> g(c.mu);
+    auto it = c.live.find(p);
+    if (it == c.live.end()) return;
+    c.free_.insert({it->second, p});
+    c.live.erase(it);
+}
+
 int Buf::ensure(size_t n) {
     if (n <= bytes && p) return 0;
-    if (p) (void)hipFree(p);
+    dcache_free(p);
     p = nullptr;
     bytes = 0;
     size_t want = n < 256 ? 256 : n;
-    if (hipMalloc(&p, want) != hipSuccess) {
-        p = nullptr;
-        set_error("hipMalloc of %zu bytes failed", want);
-        return 1;
-    }
+    p = dcache_alloc(want);
+    if (!p) return 1;
     bytes = want;
     return 0;
 }
 
 void Buf::release() {
-    if (p) (void)hipFree(p);
+    dcache_free(p);
     p = nullptr;
     bytes = 0;
 }
@@ -66,12 +127,12 @@ extern "C" const char* rt_version(void) { return "librtac 0.1 (gfx950)"; }
 extern "C" int rt_scene_destroy(rt_scene* s) {
     if (!s) return RT_OK;
     (void)hipDeviceSynchronize();
-    (void)hipFree(s->nodes);
-    (void)hipFree(s->tri_rec);
-    (void)hipFree(s->plane_n);
-    (void)hipFree(s->plane_p);
-    (void)hipFree(s->plane_mat);
-    (void)hipFree(s->tri_plane);
+    rtac::dcache_free(s->nodes);
+    rtac::dcache_free(s->tri_rec);
+    rtac::dcache_free(s->plane_n);
+    rtac::dcache_free(s->plane_p);
+    rtac::dcache_free(s->plane_mat);
+    rtac::dcache_free(s->tri_plane);
     s->ws.release_all();
     delete s;
     return RT_OK;

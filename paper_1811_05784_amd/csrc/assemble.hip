@@ -47,29 +47,30 @@ __device__ inline int64_t is_count_of(const IsArgs& a) {
 
 // Energy per band and (receiver, bin) sort key; invalid / late -> a.invalid.
 __global__ void k_is_energy(IsArgs a, double* __restrict__ E, uint64_t* __restrict__ skey) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= is_count_of(a)) return;
-    const int32_t* row = a.key + i * (int64_t)(a.R1 + 1);
-    const int32_t m = row[0], k = row[1];
-    const double d = a.dist[i];
-    double e[8];
-    const double base = (double)a.count[i] / (double)a.n_rays;
-    for (int b = 0; b < 8; b++) e[b] = base * exp(-(double)a.beta[b] * d);
-    bool ok = m >= 0 && m < a.n_rcv && k >= 0 && k < a.R1;
-    for (int j = 0; ok && j < k; j++) {
-        const int32_t p = row[2 + j];
-        if (p < 0 || p >= a.n_tri) {
-            ok = false;
-            break;
+    const int64_t n = is_count_of(a);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t* row = a.key + i * (int64_t)(a.R1 + 1);
+        const int32_t m = row[0], k = row[1];
+        const double d = a.dist[i];
+        double e[8];
+        const double base = (double)a.count[i] / (double)a.n_rays;
+        for (int b = 0; b < 8; b++) e[b] = base * exp(-(double)a.beta[b] * d);
+        bool ok = m >= 0 && m < a.n_rcv && k >= 0 && k < a.R1;
+        for (int j = 0; ok && j < k; j++) {
+            const int32_t p = row[2 + j];
+            if (p < 0 || p >= a.n_tri) {
+                ok = false;
+                break;
+            }
+            const int32_t mat = a.plane_mat[p];
+            for (int b = 0; b < 8; b++) e[b] *= 1.0 - (double)a.alpha[8 * mat + b];
         }
-        const int32_t mat = a.plane_mat[p];
-        for (int b = 0; b < 8; b++) e[b] *= 1.0 - (double)a.alpha[8 * mat + b];
+        for (int b = 0; b < 8; b++) E[8 * i + b] = e[b];
+        const double sb = floor(d * a.fs / a.c);
+        uint64_t key = a.invalid;
+        if (ok && sb >= 0.0 && sb < (double)a.L) key = (uint64_t)m * (uint64_t)a.L + (uint64_t)sb;
+        skey[i] = key;
     }
-    for (int b = 0; b < 8; b++) E[8 * i + b] = e[b];
-    const double sb = floor(d * a.fs / a.c);
-    uint64_t key = a.invalid;
-    if (ok && sb >= 0.0 && sb < (double)a.L) key = (uint64_t)m * (uint64_t)a.L + (uint64_t)sb;
-    skey[i] = key;
 }
 
 __global__ void k_fill_f32(float* p, int64_t n, float v) {
@@ -80,31 +81,31 @@ __global__ void k_fill_f32(float* p, int64_t n, float v) {
 // One thread per run of equal (receiver, bin): sum in sorted order (FP64).
 __global__ void k_bin_sum(IsArgs a, const uint64_t* __restrict__ skey, const uint32_t* __restrict__ idx,
                           const double* __restrict__ E, float* __restrict__ hist) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t n = is_count_of(a);
-    if (i >= n) return;
-    const uint64_t key = skey[i];
-    if (key == a.invalid) return;
-    if (i > 0 && skey[i - 1] == key) return;
-    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int64_t j = i; j < n && skey[j] == key; j++) {
-        const uint32_t q = idx[j];
-        for (int b = 0; b < 8; b++) s[b] += E[8 * (int64_t)q + b];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t key = skey[i];
+        if (key == a.invalid) continue;
+        if (i > 0 && skey[i - 1] == key) continue;
+        double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int64_t j = i; j < n && skey[j] == key; j++) {
+            const uint32_t q = idx[j];
+            for (int b = 0; b < 8; b++) s[b] += E[8 * (int64_t)q + b];
+        }
+        const int64_t m = (int64_t)(key / (uint64_t)a.L), bin = (int64_t)(key % (uint64_t)a.L);
+        for (int b = 0; b < 8; b++) hist[(m * 8 + b) * a.L + bin] = (float)s[b];
     }
-    const int64_t m = (int64_t)(key / (uint64_t)a.L), bin = (int64_t)(key % (uint64_t)a.L);
-    for (int b = 0; b < 8; b++) hist[(m * 8 + b) * a.L + bin] = (float)s[b];
 }
 
 // band_energy[r, b] = sum over bins (FP64 tree reduction, fixed order).
-__global__ void __launch_bounds__(256) k_band_energy(const float* __restrict__ hist, int64_t L,
-                                                     float* __restrict__ out) {
-    __shared__ double red[256];
+__global__ void __launch_bounds__(1024) k_band_energy(const float* __restrict__ hist, int64_t L,
+                                                      float* __restrict__ out) {
+    __shared__ double red[1024];
     const float* h = hist + (int64_t)blockIdx.x * L;
     double s = 0.0;
-    for (int64_t i = threadIdx.x; i < L; i += 256) s += (double)h[i];
+    for (int64_t i = threadIdx.x; i < L; i += 1024) s += (double)h[i];
     red[threadIdx.x] = s;
     __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
+    for (int off = 512; off > 0; off >>= 1) {
         if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
         __syncthreads();
     }
@@ -258,6 +259,13 @@ __global__ void k_adjoint_final(const double* __restrict__ partial, int nblocks,
 }
 
 inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t > 0 ? (n + t - 1) / t : 1); }
+// grid-stride kernels: enough workgroups to fill the chip, no more
+inline unsigned nblk_gs(int64_t n) {
+    int64_t b = (n + 255) / 256;
+    const int64_t cap = (int64_t)device_sm_count() * 8;
+    if (b > cap) b = cap;
+    return (unsigned)(b > 0 ? b : 1);
+}
 
 int check_is_args(const rt_scene* s, const int32_t* is_key, const int32_t* is_count, const double* is_dist,
                   const int64_t* n_is, int64_t is_cap, int32_t R, int64_t n_rays, int32_t n_rcv, const float* alpha,
@@ -330,7 +338,7 @@ extern "C" int rt_assemble_ir(const rt_scene* scene, const int32_t* is_key, cons
     uint64_t* k1 = ws.sort_keys[1].as<uint64_t>();
     uint32_t* v0 = ws.sort_vals[0].as<uint32_t>();
     uint32_t* v1 = ws.sort_vals[1].as<uint32_t>();
-    hipLaunchKernelGGL(k_is_energy, dim3(nblk(cap)), dim3(256), 0, st, a, E, k0);
+    hipLaunchKernelGGL(k_is_energy, dim3(nblk_gs(cap)), dim3(256), 0, st, a, E, k0);
     // sort by (receiver, bin); the invalid key n_rcv * L lands last
     int bits = 8;
     while (bits < 64 && (a.invalid >> bits) != 0) bits += 8;
@@ -339,8 +347,8 @@ extern "C" int rt_assemble_ir(const rt_scene* scene, const int32_t* is_key, cons
     if (rc) return rc;
     const int64_t hn = (int64_t)n_rcv * 8 * L;
     hipLaunchKernelGGL(k_fill_f32, dim3(nblk(hn)), dim3(256), 0, st, hist, hn, 0.f);
-    hipLaunchKernelGGL(k_bin_sum, dim3(nblk(cap)), dim3(256), 0, st, a, which ? k1 : k0, which ? v1 : v0, E, hist);
-    hipLaunchKernelGGL(k_band_energy, dim3(n_rcv * 8), dim3(256), 0, st, hist, L, band_energy);
+    hipLaunchKernelGGL(k_bin_sum, dim3(nblk_gs(cap)), dim3(256), 0, st, a, which ? k1 : k0, which ? v1 : v0, E, hist);
+    hipLaunchKernelGGL(k_band_energy, dim3(n_rcv * 8), dim3(1024), 0, st, hist, L, band_energy);
     const int Kpad = K + 112;
     const int Smax = (K + 15 + 15 + 3) / 4;
     const int W = kFirOut + 4 * Smax + 16;

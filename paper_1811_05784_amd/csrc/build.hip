@@ -42,57 +42,83 @@ __host__ __device__ inline float funord(uint32_t u) {
 
 // bounds[0..5] = vertex box (min xyz ordered, max xyz ordered),
 // bounds[6..11] = centroid box; info[0] = error bits, info[1] = max material.
-__global__ void k_tri_prep(const float* __restrict__ vtx, int64_t nv, const int3* __restrict__ tri, int64_t nt,
-                           const int32_t* __restrict__ material, const int32_t* __restrict__ plane_id,
-                           float* __restrict__ tri_box, float* __restrict__ centroid, uint32_t* __restrict__ bounds,
-                           uint32_t* __restrict__ info, int32_t* __restrict__ prep) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nt) return;
-    const int3 t = tri[i];
-    uint32_t err = 0;
-    if (t.x < 0 || t.y < 0 || t.z < 0 || t.x >= nv || t.y >= nv || t.z >= nv) err |= kErrIndex;
-    const int32_t p = plane_id ? plane_id[i] : (int32_t)i;
-    if (p < 0 || p >= nt) err |= kErrPlaneRange;
-    const int32_t m = material[i];
-    if (m < 0) err |= kErrMaterial;
-    if (err) {
-        atomicOr(&info[0], err);
-        return;
+// Bounds are reduced in LDS first: one atomic per workgroup and bound.
+__global__ void __launch_bounds__(256) k_tri_prep(const float* __restrict__ vtx, int64_t nv,
+                                                  const int3* __restrict__ tri, int64_t nt,
+                                                  const int32_t* __restrict__ material,
+                                                  const int32_t* __restrict__ plane_id, float* __restrict__ tri_box,
+                                                  float* __restrict__ centroid, uint32_t* __restrict__ bounds,
+                                                  uint32_t* __restrict__ info, int32_t* __restrict__ prep) {
+    __shared__ uint32_t sb[12];
+    __shared__ uint32_t s_err, s_mat;
+    const int tid = threadIdx.x;
+    if (tid < 12) sb[tid] = (tid % 6) < 3 ? 0xFFFFFFFFu : 0u;
+    if (tid == 0) {
+        s_err = 0;
+        s_mat = 0;
     }
-    float v[3][3];
-    const int idx[3] = {t.x, t.y, t.z};
-    bool finite = true;
-    for (int a = 0; a < 3; a++)
-        for (int c = 0; c < 3; c++) {
-            v[a][c] = vtx[3 * (int64_t)idx[a] + c];
-            finite &= isfinite(v[a][c]);
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + tid;
+    if (i < nt) {
+        const int3 t = tri[i];
+        uint32_t err = 0;
+        if (t.x < 0 || t.y < 0 || t.z < 0 || t.x >= nv || t.y >= nv || t.z >= nv) err |= kErrIndex;
+        const int32_t p = plane_id ? plane_id[i] : (int32_t)i;
+        if (p < 0 || p >= nt) err |= kErrPlaneRange;
+        const int32_t m = material[i];
+        if (m < 0) err |= kErrMaterial;
+        float v[3][3];
+        if (!err) {
+            const int idx[3] = {t.x, t.y, t.z};
+            bool finite = true;
+            for (int a = 0; a < 3; a++)
+                for (int c = 0; c < 3; c++) {
+                    v[a][c] = vtx[3 * (int64_t)idx[a] + c];
+                    finite &= isfinite(v[a][c]);
+                }
+            if (!finite) err |= kErrNonFinite;
         }
-    if (!finite) {
-        atomicOr(&info[0], kErrNonFinite);
-        return;
+        if (!err) {
+            double e1[3], e2[3];
+            for (int c = 0; c < 3; c++) {
+                e1[c] = (double)v[1][c] - (double)v[0][c];
+                e2[c] = (double)v[2][c] - (double)v[0][c];
+            }
+            const double cx = e1[1] * e2[2] - e1[2] * e2[1];
+            const double cy = e1[2] * e2[0] - e1[0] * e2[2];
+            const double cz = e1[0] * e2[1] - e1[1] * e2[0];
+            if (cx == 0.0 && cy == 0.0 && cz == 0.0) err |= kErrZeroArea;
+            atomicMax(&s_mat, (uint32_t)m);
+            atomicMin(&prep[p], (int32_t)i);
+            for (int c = 0; c < 3; c++) {
+                const float lo = fminf(v[0][c], fminf(v[1][c], v[2][c]));
+                const float hi = fmaxf(v[0][c], fmaxf(v[1][c], v[2][c]));
+                tri_box[6 * i + c] = lo;
+                tri_box[6 * i + 3 + c] = hi;
+                const float cen = (v[0][c] + v[1][c] + v[2][c]) * (1.0f / 3.0f);
+                centroid[3 * i + c] = cen;
+                atomicMin(&sb[c], ford(lo));
+                atomicMax(&sb[3 + c], ford(hi));
+                atomicMin(&sb[6 + c], ford(cen));
+                atomicMax(&sb[9 + c], ford(cen));
+            }
+        } else {
+            for (int c = 0; c < 3; c++) {
+                tri_box[6 * i + c] = 0.f;
+                tri_box[6 * i + 3 + c] = 0.f;
+                centroid[3 * i + c] = 0.f;
+            }
+        }
+        if (err) atomicOr(&s_err, err);
     }
-    double e1[3], e2[3];
-    for (int c = 0; c < 3; c++) {
-        e1[c] = (double)v[1][c] - (double)v[0][c];
-        e2[c] = (double)v[2][c] - (double)v[0][c];
+    __syncthreads();
+    if (tid < 12) {
+        if ((tid % 6) < 3) atomicMin(&bounds[tid], sb[tid]);
+        else atomicMax(&bounds[tid], sb[tid]);
     }
-    const double cx = e1[1] * e2[2] - e1[2] * e2[1];
-    const double cy = e1[2] * e2[0] - e1[0] * e2[2];
-    const double cz = e1[0] * e2[1] - e1[1] * e2[0];
-    if (cx == 0.0 && cy == 0.0 && cz == 0.0) atomicOr(&info[0], kErrZeroArea);
-    atomicMax(&info[1], (uint32_t)m);
-    atomicMin(&prep[p], (int32_t)i);
-    for (int c = 0; c < 3; c++) {
-        const float lo = fminf(v[0][c], fminf(v[1][c], v[2][c]));
-        const float hi = fmaxf(v[0][c], fmaxf(v[1][c], v[2][c]));
-        tri_box[6 * i + c] = lo;
-        tri_box[6 * i + 3 + c] = hi;
-        const float cen = (v[0][c] + v[1][c] + v[2][c]) * (1.0f / 3.0f);
-        centroid[3 * i + c] = cen;
-        atomicMin(&bounds[c], ford(lo));
-        atomicMax(&bounds[3 + c], ford(hi));
-        atomicMin(&bounds[6 + c], ford(cen));
-        atomicMax(&bounds[9 + c], ford(cen));
+    if (tid == 0) {
+        if (s_err) atomicOr(&info[0], s_err);
+        atomicMax(&info[1], s_mat);
     }
 }
 
@@ -108,7 +134,7 @@ __global__ void k_plane_table(const float* __restrict__ vtx, const int3* __restr
         pmat[p] = -1;
         return;
     }
-    const int3 t = tri[r];
+    const int3 t = tri[r];   // r passed validation in k_tri_prep
     double a[3], b[3], cc[3];
     for (int c = 0; c < 3; c++) {
         a[c] = vtx[3 * (int64_t)t.x + c];
@@ -126,19 +152,28 @@ __global__ void k_plane_table(const float* __restrict__ vtx, const int3* __restr
     pmat[p] = material[r];
 }
 
-// Members of a plane group lie in the representative's plane (1e-9 D) and
-// share its material.  Also records the plane id of every triangle.
-__global__ void k_coplanar(const float* __restrict__ vtx, const int3* __restrict__ tri, int64_t nt,
+// Members of a plane group lie in the representative's plane (1e-9 D, D the
+// bounding-box diagonal) and share its material.  Also records the plane id
+// of every triangle.  Triangles that failed validation are skipped.
+__global__ void k_coplanar(const float* __restrict__ vtx, int64_t nv, const int3* __restrict__ tri, int64_t nt,
                            const int32_t* __restrict__ material, const int32_t* __restrict__ plane_id,
                            const double* __restrict__ pn, const double* __restrict__ pp,
-                           const int32_t* __restrict__ pmat, double tol, int32_t* __restrict__ tri_plane,
-                           uint32_t* __restrict__ info) {
+                           const int32_t* __restrict__ pmat, const uint32_t* __restrict__ bounds,
+                           int32_t* __restrict__ tri_plane, uint32_t* __restrict__ info) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nt) return;
     const int32_t p = plane_id ? plane_id[i] : (int32_t)i;
-    tri_plane[i] = p;
-    if (material[i] != pmat[p]) atomicOr(&info[0], kErrMixedMaterial);
     const int3 t = tri[i];
+    const bool ok = p >= 0 && p < nt && t.x >= 0 && t.y >= 0 && t.z >= 0 && t.x < nv && t.y < nv && t.z < nv;
+    tri_plane[i] = ok ? p : 0;
+    if (!ok) return;
+    double d2 = 0.0;
+    for (int c = 0; c < 3; c++) {
+        const double e = (double)funord(bounds[3 + c]) - (double)funord(bounds[c]);
+        d2 += e * e;
+    }
+    const double tol = 1e-9 * sqrt(d2);
+    if (material[i] != pmat[p]) atomicOr(&info[0], kErrMixedMaterial);
     const int idx[3] = {t.x, t.y, t.z};
     for (int a = 0; a < 3; a++) {
         double d = 0;
@@ -232,6 +267,17 @@ __global__ void k_radix_tree(const uint64_t* __restrict__ k, int64_t n, int32_t*
 }
 
 // Bottom-up boxes: the second child to arrive at a node computes its box.
+// Boxes written by other threads are read with relaxed device-scope atomic
+// loads (no L1 staleness, and independent loads stay in flight together).
+__device__ inline float load_coherent(const float* p) {
+    return __uint_as_float(__hip_atomic_load(reinterpret_cast<const uint32_t*>(p), __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT));
+}
+__device__ inline void store_coherent(float* p, float v) {
+    __hip_atomic_store(reinterpret_cast<uint32_t*>(p), __float_as_uint(v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __global__ void k_refit(int64_t n, const uint32_t* __restrict__ order, const float* __restrict__ tri_box,
                         const int32_t* __restrict__ left, const int32_t* __restrict__ right,
                         const int32_t* __restrict__ parent_in, const int32_t* __restrict__ parent_leaf,
@@ -240,28 +286,24 @@ __global__ void k_refit(int64_t n, const uint32_t* __restrict__ order, const flo
     if (j >= n) return;
     int32_t p = parent_leaf[j];
     while (p >= 0) {
-        __threadfence();
-        if (atomicAdd(&arrive[p], 1u) == 0) return;
-        __threadfence();
+        if (__hip_atomic_fetch_add(&arrive[p], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == 0) return;
         float b[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
         const int32_t ch[2] = {left[p], right[p]};
+        float cb[2][6];
         for (int c2 = 0; c2 < 2; c2++) {
             const int32_t c = ch[c2];
-            float cb[6];
             if (c < 0) {
                 const uint32_t t = order[~c];
-                for (int a = 0; a < 6; a++) cb[a] = tri_box[6 * (int64_t)t + a];
+                for (int a = 0; a < 6; a++) cb[c2][a] = tri_box[6 * (int64_t)t + a];
             } else {
-                const volatile float* src = box_in + 6 * (int64_t)c;
-                for (int a = 0; a < 6; a++) cb[a] = src[a];
-            }
-            for (int a = 0; a < 3; a++) {
-                b[a] = fminf(b[a], cb[a]);
-                b[3 + a] = fmaxf(b[3 + a], cb[3 + a]);
+                for (int a = 0; a < 6; a++) cb[c2][a] = load_coherent(box_in + 6 * (int64_t)c + a);
             }
         }
-        volatile float* dst = box_in + 6 * (int64_t)p;
-        for (int a = 0; a < 6; a++) dst[a] = b[a];
+        for (int a = 0; a < 3; a++) {
+            b[a] = fminf(cb[0][a], cb[1][a]);
+            b[3 + a] = fmaxf(cb[0][3 + a], cb[1][3 + a]);
+        }
+        for (int a = 0; a < 6; a++) store_coherent(box_in + 6 * (int64_t)p + a, b[a]);
         p = parent_in[p];
     }
 }
@@ -357,13 +399,14 @@ __global__ void k_single_leaf_root(const uint32_t* __restrict__ bounds, int32_t 
     nodes[0] = nd;
 }
 
-__global__ void k_tri_records(const float* __restrict__ vtx, const int3* __restrict__ tri, int64_t nt,
+__global__ void k_tri_records(const float* __restrict__ vtx, int64_t nv, const int3* __restrict__ tri, int64_t nt,
                               const int32_t* __restrict__ material, const int32_t* __restrict__ tri_plane,
                               const uint32_t* __restrict__ order, float4* __restrict__ rec) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= nt) return;
     const uint32_t t = order[j];
     const int3 v = tri[t];
+    if (v.x < 0 || v.y < 0 || v.z < 0 || v.x >= nv || v.y >= nv || v.z >= nv) return;   // reported already
     const int idx[3] = {v.x, v.y, v.z};
     const int32_t w[3] = {tri_plane[t], (int32_t)t, material[t]};
     for (int a = 0; a < 3; a++) {
@@ -371,6 +414,8 @@ __global__ void k_tri_records(const float* __restrict__ vtx, const int3* __restr
         rec[3 * j + a] = make_float4(p[0], p[1], p[2], __int_as_float(w[a]));
     }
 }
+
+__global__ void k_copy_u32(const uint32_t* src, uint32_t* dst) { *dst = *src; }
 
 __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -399,13 +444,12 @@ const char* err_text(uint32_t e) {
 struct TmpBufs {
     std::vector<void*> ptrs;
     ~TmpBufs() {
-        for (void* p : ptrs) (void)hipFree(p);
+        for (void* p : ptrs) dcache_free(p);
     }
     template <class T>
     T* get(size_t count) {
-        void* p = nullptr;
-        if (hipMalloc(&p, sizeof(T) * (count ? count : 1)) != hipSuccess) return nullptr;
-        ptrs.push_back(p);
+        void* p = dcache_alloc(sizeof(T) * (count ? count : 1));
+        if (p) ptrs.push_back(p);
         return reinterpret_cast<T*>(p);
     }
 };
@@ -428,80 +472,57 @@ extern "C" int rt_build_tree(const float* vtx, int64_t n_vtx, const int32_t* tri
     RT_CHECK(leaf >= 1 && leaf <= kMaxLeaf, RT_EINVAL, "rt_build_tree: leaf_size must be in [1, %d]", kMaxLeaf);
     hipStream_t st = (hipStream_t)stream;
     const int64_t nt = n_tri;
+    const int64_t n_in = nt - 1;
+    const bool single = n_in == 0 || nt <= leaf;
     TmpBufs tmp;
+    rt_scene* s = new rt_scene();
+    auto fail = [&](int code) {
+        rt_scene_destroy(s);
+        return code;
+    };
+    if (hipGetDevice(&s->device) != hipSuccess) return fail(RT_EHIP);
+    s->n_tri = nt;
+    s->n_vtx = n_vtx;
+    s->leaf_size = leaf;
+    // upper bound of 4-wide nodes: inner binary nodes (one per adjacent pair)
+    const int64_t node_cap = single ? 1 : n_in;
+    s->plane_n = (double*)dcache_alloc(sizeof(double) * 3 * nt);
+    s->plane_p = (double*)dcache_alloc(sizeof(double) * 3 * nt);
+    s->plane_mat = (int32_t*)dcache_alloc(sizeof(int32_t) * nt);
+    s->tri_plane = (int32_t*)dcache_alloc(sizeof(int32_t) * nt);
+    s->tri_rec = (float4*)dcache_alloc(sizeof(float4) * 3 * nt);
+    s->nodes = (Node4*)dcache_alloc(sizeof(Node4) * node_cap);
     float* tri_box = tmp.get<float>(6 * nt);
     float* cen = tmp.get<float>(3 * nt);
     uint32_t* bounds = tmp.get<uint32_t>(12);
     uint32_t* info = tmp.get<uint32_t>(4);
     int32_t* prep = tmp.get<int32_t>(nt);
-    RT_CHECK(tri_box && cen && bounds && info && prep, RT_ENOMEM, "rt_build_tree: out of device memory");
-    hipLaunchKernelGGL(k_init_bounds, dim3(1), dim3(64), 0, st, bounds, info);
-    hipLaunchKernelGGL(k_fill_i32, dim3(blocks(nt)), dim3(256), 0, st, prep, nt, INT32_MAX);
-    hipLaunchKernelGGL(k_tri_prep, dim3(blocks(nt)), dim3(256), 0, st, vtx, n_vtx, (const int3*)tri, nt, material,
-                       plane_id, tri_box, cen, bounds, info, prep);
-    RT_HIP(hipGetLastError());
-    uint32_t h_info[4], h_bounds[12];
-    RT_HIP(hipMemcpyAsync(h_info, info, sizeof(h_info), hipMemcpyDeviceToHost, st));
-    RT_HIP(hipMemcpyAsync(h_bounds, bounds, sizeof(h_bounds), hipMemcpyDeviceToHost, st));
-    RT_HIP(hipStreamSynchronize(st));
-    if (h_info[0]) {
-        set_error("rt_build_tree: %s", err_text(h_info[0]));
-        return (h_info[0] & (kErrNonFinite | kErrZeroArea)) && !(h_info[0] & (kErrIndex | kErrPlaneRange | kErrMaterial))
-                   ? RT_EDEGENERATE
-                   : RT_EINVAL;
-    }
-    rt_scene* s = new rt_scene();
-    RT_HIP(hipGetDevice(&s->device));
-    s->n_tri = nt;
-    s->n_vtx = n_vtx;
-    s->n_mat = (int32_t)h_info[1] + 1;
-    s->leaf_size = leaf;
-    double d2 = 0;
-    for (int c = 0; c < 3; c++) {
-        s->bounds[c] = funord(h_bounds[c]);
-        s->bounds[3 + c] = funord(h_bounds[3 + c]);
-        const double e = (double)s->bounds[3 + c] - (double)s->bounds[c];
-        d2 += e * e;
-    }
-    s->diag = std::sqrt(d2);
-    auto fail = [&](int code) {
-        rt_scene_destroy(s);
-        return code;
-    };
-    if (hipMalloc(&s->plane_n, sizeof(double) * 3 * nt) != hipSuccess ||
-        hipMalloc(&s->plane_p, sizeof(double) * 3 * nt) != hipSuccess ||
-        hipMalloc(&s->plane_mat, sizeof(int32_t) * nt) != hipSuccess ||
-        hipMalloc(&s->tri_plane, sizeof(int32_t) * nt) != hipSuccess ||
-        hipMalloc(&s->tri_rec, sizeof(float4) * 3 * nt) != hipSuccess) {
-        set_error("rt_build_tree: out of device memory");
-        return fail(RT_ENOMEM);
-    }
-    hipLaunchKernelGGL(k_plane_table, dim3(blocks(nt)), dim3(256), 0, st, vtx, (const int3*)tri, nt, material, prep,
-                       s->plane_n, s->plane_p, s->plane_mat);
-    hipLaunchKernelGGL(k_coplanar, dim3(blocks(nt)), dim3(256), 0, st, vtx, (const int3*)tri, nt, material, plane_id,
-                       s->plane_n, s->plane_p, s->plane_mat, 1e-9 * s->diag, s->tri_plane, info);
-    // Morton order
     uint64_t* codes0 = tmp.get<uint64_t>(nt);
     uint64_t* codes1 = tmp.get<uint64_t>(nt);
     uint32_t* ord0 = tmp.get<uint32_t>(nt);
     uint32_t* ord1 = tmp.get<uint32_t>(nt);
-    if (!codes0 || !codes1 || !ord0 || !ord1) {
+    if (!s->plane_n || !s->plane_p || !s->plane_mat || !s->tri_plane || !s->tri_rec || !s->nodes || !tri_box ||
+        !cen || !bounds || !info || !prep || !codes0 || !codes1 || !ord0 || !ord1) {
         set_error("rt_build_tree: out of device memory");
         return fail(RT_ENOMEM);
     }
+    hipLaunchKernelGGL(k_init_bounds, dim3(1), dim3(64), 0, st, bounds, info);
+    hipLaunchKernelGGL(k_fill_i32, dim3(blocks(nt)), dim3(256), 0, st, prep, nt, INT32_MAX);
+    hipLaunchKernelGGL(k_tri_prep, dim3(blocks(nt)), dim3(256), 0, st, vtx, n_vtx, (const int3*)tri, nt, material,
+                       plane_id, tri_box, cen, bounds, info, prep);
+    hipLaunchKernelGGL(k_plane_table, dim3(blocks(nt)), dim3(256), 0, st, vtx, (const int3*)tri, nt, material, prep,
+                       s->plane_n, s->plane_p, s->plane_mat);
+    hipLaunchKernelGGL(k_coplanar, dim3(blocks(nt)), dim3(256), 0, st, vtx, n_vtx, (const int3*)tri, nt, material,
+                       plane_id, s->plane_n, s->plane_p, s->plane_mat, bounds, s->tri_plane, info);
     hipLaunchKernelGGL(k_morton, dim3(blocks(nt)), dim3(256), 0, st, cen, nt, bounds, codes0);
     int which = 0;
     int rc = radix_sort_pairs(s->ws, codes0, ord0, codes1, ord1, nt, nullptr, 0, 64, st, &which, true);
     if (rc) return fail(rc);
     uint64_t* codes = which ? codes1 : codes0;
     uint32_t* order = which ? ord1 : ord0;
-    const int64_t n_in = nt - 1;
-    uint32_t h_info2[4] = {0, 0, 0, 0};
-    if (n_in == 0 || nt <= leaf) {
-        RT_HIP(hipMalloc(&s->nodes, sizeof(Node4)));
+    uint32_t* n4_dev = info + 3;
+    if (single) {
         hipLaunchKernelGGL(k_single_leaf_root, dim3(1), dim3(1), 0, st, bounds, (int32_t)nt, s->nodes);
-        s->n_nodes = 1;
-        h_info2[2] = 1;
     } else {
         int32_t* left = tmp.get<int32_t>(n_in);
         int32_t* right = tmp.get<int32_t>(n_in);
@@ -519,7 +540,7 @@ extern "C" int rt_build_tree(const float* vtx, int64_t n_vtx, const int32_t* tri
             set_error("rt_build_tree: out of device memory");
             return fail(RT_ENOMEM);
         }
-        RT_HIP(hipMemsetAsync(arrive, 0, sizeof(uint32_t) * n_in, st));
+        hipLaunchKernelGGL(k_fill_i32, dim3(blocks(n_in)), dim3(256), 0, st, (int32_t*)arrive, n_in, 0);
         hipLaunchKernelGGL(k_radix_tree, dim3(blocks(n_in)), dim3(256), 0, st, codes, nt, left, right, first, last,
                            par_in, par_leaf);
         hipLaunchKernelGGL(k_refit, dim3(blocks(nt)), dim3(256), 0, st, nt, order, tri_box, left, right, par_in,
@@ -528,28 +549,35 @@ extern "C" int rt_build_tree(const float* vtx, int64_t n_vtx, const int32_t* tri
                            depth);
         rc = exclusive_scan_u32(s->ws, flag, index, n_in, nullptr, st);
         if (rc) return fail(rc);
-        uint32_t n4 = 0;
-        RT_HIP(hipMemcpyAsync(&n4, index + n_in, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-        RT_HIP(hipStreamSynchronize(st));
-        RT_CHECK(n4 >= 1, RT_EHIP, "rt_build_tree: empty tree");
-        if (hipMalloc(&s->nodes, sizeof(Node4) * n4) != hipSuccess) {
-            set_error("rt_build_tree: out of device memory");
-            return fail(RT_ENOMEM);
-        }
-        s->n_nodes = (int32_t)n4;
         hipLaunchKernelGGL(k_emit4, dim3(blocks(n_in)), dim3(256), 0, st, n_in, left, right, first, last, flag,
                            index, depth, box_in, tri_box, order, leaf, s->nodes, info);
+        hipLaunchKernelGGL(k_copy_u32, dim3(1), dim3(1), 0, st, index + n_in, n4_dev);
     }
-    hipLaunchKernelGGL(k_tri_records, dim3(blocks(nt)), dim3(256), 0, st, vtx, (const int3*)tri, nt, material,
+    hipLaunchKernelGGL(k_tri_records, dim3(blocks(nt)), dim3(256), 0, st, vtx, n_vtx, (const int3*)tri, nt, material,
                        s->tri_plane, order, s->tri_rec);
     RT_HIP(hipGetLastError());
+    uint32_t h_info[4], h_bounds[12];
     RT_HIP(hipMemcpyAsync(h_info, info, sizeof(h_info), hipMemcpyDeviceToHost, st));
+    RT_HIP(hipMemcpyAsync(h_bounds, bounds, sizeof(h_bounds), hipMemcpyDeviceToHost, st));
     RT_HIP(hipStreamSynchronize(st));
     if (h_info[0]) {
         set_error("rt_build_tree: %s", err_text(h_info[0]));
-        return fail(RT_EINVAL);
+        const bool degen = (h_info[0] & (kErrNonFinite | kErrZeroArea)) &&
+                           !(h_info[0] & (kErrIndex | kErrPlaneRange | kErrMaterial));
+        return fail(degen ? RT_EDEGENERATE : RT_EINVAL);
     }
-    s->depth = (int32_t)(h_info2[2] ? h_info2[2] : h_info[2]);
+    s->n_mat = (int32_t)h_info[1] + 1;
+    double d2 = 0;
+    for (int c = 0; c < 3; c++) {
+        s->bounds[c] = funord(h_bounds[c]);
+        s->bounds[3 + c] = funord(h_bounds[3 + c]);
+        const double e = (double)s->bounds[3 + c] - (double)s->bounds[c];
+        d2 += e * e;
+    }
+    s->diag = std::sqrt(d2);
+    s->n_nodes = single ? 1 : (int32_t)h_info[3];
+    s->depth = single ? 1 : (int32_t)h_info[2];
+    RT_CHECK(s->n_nodes >= 1 && s->n_nodes <= node_cap, RT_EHIP, "rt_build_tree: inconsistent tree");
     *out_scene = s;
     return RT_OK;
 }

@@ -58,21 +58,22 @@ __device__ inline int32_t plane_at(const CollectArgs& a, int32_t ray, int32_t j)
 }
 
 __global__ void k_hash(CollectArgs a, uint64_t mask, uint64_t* __restrict__ hash, uint32_t* __restrict__ err) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= det_count(a)) return;
-    int32_t ray, k, m;
-    if (!det_row(a, i, ray, k, m)) {
-        atomicOr(err, 1u);
-        hash[i] = mask;   // invalid rows sort together at the end
-        return;
+    const int64_t n = det_count(a);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        int32_t ray, k, m;
+        if (!det_row(a, i, ray, k, m)) {
+            atomicOr(err, 1u);
+            hash[i] = mask;   // invalid rows sort together at the end
+            continue;
+        }
+        uint64_t h = mix64(0x9E3779B97F4A7C15ull ^ ((uint64_t)(uint32_t)m << 32 | (uint32_t)k));
+        for (int j = 0; j < k; j++) {
+            const int32_t p = plane_at(a, ray, j);
+            if (p < 0) atomicOr(err, 2u);
+            h = mix64(h + 0x632BE59BD9B4E019ull * (uint64_t)(uint32_t)(p + 1));
+        }
+        hash[i] = h & mask;
     }
-    uint64_t h = mix64(0x9E3779B97F4A7C15ull ^ ((uint64_t)(uint32_t)m << 32 | (uint32_t)k));
-    for (int j = 0; j < k; j++) {
-        const int32_t p = plane_at(a, ray, j);
-        if (p < 0) atomicOr(err, 2u);
-        h = mix64(h + 0x632BE59BD9B4E019ull * (uint64_t)(uint32_t)(p + 1));
-    }
-    hash[i] = h & mask;
 }
 
 // Lexicographic comparison of two detections' keys: <0, 0, >0.
@@ -91,25 +92,32 @@ __device__ inline int key_cmp(const CollectArgs& a, uint32_t x, uint32_t y) {
 
 __global__ void k_heads(CollectArgs a, const uint64_t* __restrict__ hash, const uint32_t* __restrict__ idx,
                         uint32_t* __restrict__ head, uint32_t* __restrict__ flags) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t n = det_count(a);
-    if (i >= n) return;
-    uint32_t h = 1;
-    if (i > 0 && hash[i] == hash[i - 1]) {
-        h = key_cmp(a, idx[i], idx[i - 1]) != 0;
-        if (h) atomicOr(flags, 4u);   // equal hashes, different keys
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t h = 1;
+        if (i > 0 && hash[i] == hash[i - 1]) {
+            h = key_cmp(a, idx[i], idx[i - 1]) != 0;
+            if (h) atomicOr(flags, 4u);   // equal hashes, different keys
+        }
+        head[i] = h;
     }
-    head[i] = h;
 }
+
+__device__ void fix_run(const CollectArgs& a, const uint64_t* hash, uint32_t* idx, uint32_t* head, int64_t n,
+                        int64_t i);
 
 // Runs of equal hash holding different keys: sort the run by full key and
 // recompute its group heads.  Does nothing unless a collision was seen.
 __global__ void k_fix_collisions(CollectArgs a, const uint64_t* __restrict__ hash, uint32_t* __restrict__ idx,
                                  uint32_t* __restrict__ head, const uint32_t* __restrict__ flags) {
     if (!(*flags & 4u)) return;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t n = det_count(a);
-    if (i >= n) return;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        fix_run(a, hash, idx, head, n, i);
+}
+
+__device__ void fix_run(const CollectArgs& a, const uint64_t* hash, uint32_t* idx, uint32_t* head, int64_t n,
+                        int64_t i) {
     if (i > 0 && hash[i] == hash[i - 1]) return;   // not a run start
     int64_t e = i + 1;
     while (e < n && hash[e] == hash[i]) e++;
@@ -131,14 +139,14 @@ __global__ void k_fix_collisions(CollectArgs a, const uint64_t* __restrict__ has
 
 __global__ void k_head_pos(CollectArgs a, const uint32_t* __restrict__ head, const uint32_t* __restrict__ group,
                            uint32_t* __restrict__ hpos, int64_t* __restrict__ n_is) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t n = det_count(a);
-    if (i == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
         const int64_t total = n > 0 ? (int64_t)group[n] : 0;
         *n_is = total;
         hpos[total] = (uint32_t)n;
     }
-    if (i < n && head[i]) hpos[group[i]] = (uint32_t)i;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        if (head[i]) hpos[group[i]] = (uint32_t)i;
 }
 
 struct EmitArgs {
@@ -153,11 +161,18 @@ struct EmitArgs {
     int64_t is_cap;
 };
 
+__device__ void emit_one(const CollectArgs& a, const EmitArgs& e, const uint32_t* __restrict__ idx,
+                         const uint32_t* __restrict__ hpos, int64_t g);
+
 __global__ void k_emit(CollectArgs a, EmitArgs e, const uint32_t* __restrict__ idx, const uint32_t* __restrict__ hpos,
                        const int64_t* __restrict__ n_is) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t ng = *n_is;
-    if (g >= ng || g >= e.is_cap) return;
+    const int64_t ng = *n_is < e.is_cap ? *n_is : e.is_cap;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ng; g += (int64_t)gridDim.x * blockDim.x)
+        emit_one(a, e, idx, hpos, g);
+}
+
+__device__ void emit_one(const CollectArgs& a, const EmitArgs& e, const uint32_t* __restrict__ idx,
+                         const uint32_t* __restrict__ hpos, int64_t g) {
     const uint32_t p0 = hpos[g], p1 = hpos[g + 1];
     const uint32_t d = idx[p0];
     int32_t ray, k, m;
@@ -196,7 +211,13 @@ __global__ void k_zero_u32(uint32_t* p, int n) {
     if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
 }
 
-inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256 > 0 ? (n + 255) / 256 : 1); }
+// grid-stride kernels: enough workgroups to fill the chip, no more
+inline unsigned nblk(int64_t n) {
+    int64_t b = (n + 255) / 256;
+    const int64_t cap = (int64_t)device_sm_count() * 8;
+    if (b > cap) b = cap;
+    return (unsigned)(b > 0 ? b : 1);
+}
 
 }  // namespace
 

@@ -116,4 +116,11 @@ int exclusive_scan_u32(Workspace& ws, const uint32_t* in, uint32_t* out, int64_t
 
 int device_sm_count();
 
+// Process-wide caching device allocator (per device, best fit within 2x):
+// repeated scene builds and scratch growth reuse freed blocks instead of
+// calling hipMalloc/hipFree again.  Blocks are only returned to the cache
+// once no queued kernel uses them (after a synchronisation).
+void* dcache_alloc(size_t bytes);
+void dcache_free(void* p);
+
 }  // namespace rtac

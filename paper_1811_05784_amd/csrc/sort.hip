@@ -23,51 +23,65 @@ __device__ inline int64_t count_of(const int64_t* n_dev, int64_t cap) {
     return n < 0 ? 0 : (n > cap ? cap : n);
 }
 
+// Tiles holding at least one of the n keys; tables are laid out digit-major
+// over these tiles only: hist[d * used + tile].
+__device__ inline int used_tiles(int64_t n) { return (int)((n + kTile - 1) / kTile); }
+
 __global__ void __launch_bounds__(kThreads) k_digit_hist(const uint64_t* __restrict__ keys, int64_t cap,
                                                           const int64_t* n_dev, int shift,
-                                                          uint32_t* __restrict__ hist, int nblocks) {
+                                                          uint32_t* __restrict__ hist) {
     __shared__ uint32_t h[256];
     const int tid = threadIdx.x;
+    const int64_t n = count_of(n_dev, cap);
+    const int used = used_tiles(n);
+    if ((int)blockIdx.x >= used) return;
     h[tid] = 0;
     __syncthreads();
-    const int64_t n = count_of(n_dev, cap);
     const int64_t base = (int64_t)blockIdx.x * kTile;
-    if (base < n) {
 #pragma unroll 4
-        for (int i = 0; i < kItems; i++) {
-            int64_t idx = base + (int64_t)i * kThreads + tid;
-            if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & 255u], 1u);
-        }
+    for (int i = 0; i < kItems; i++) {
+        int64_t idx = base + (int64_t)i * kThreads + tid;
+        if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & 255u], 1u);
     }
     __syncthreads();
-    hist[(int64_t)tid * nblocks + blockIdx.x] = h[tid];
+    hist[(int64_t)tid * used + blockIdx.x] = h[tid];
 }
 
-// In-place exclusive scan of a[0..len) by one workgroup of 1024 threads.
-__global__ void __launch_bounds__(1024) k_scan_single(uint32_t* __restrict__ a, int64_t len,
+// In-place exclusive scan of a[0..len) by one workgroup of 1024 threads,
+// 4096 elements per round (coalesced uint4 loads, LDS scan of thread sums).
+// len = len_mul * used_tiles(n) when n_dev is given, else len_fixed.
+__global__ void __launch_bounds__(1024) k_scan_single(uint32_t* __restrict__ a, int64_t len_fixed,
+                                                       const int64_t* n_dev, int64_t cap, int len_mul,
                                                        uint32_t* __restrict__ total) {
     __shared__ uint32_t sums[1024];
+    __shared__ uint32_t carry_s;
     const int tid = threadIdx.x;
-    const int64_t per = (len + 1023) / 1024;
-    const int64_t b = tid * per;
-    const int64_t e = b + per < len ? b + per : len;
-    uint32_t s = 0;
-    for (int64_t i = b; i < e; i++) s += a[i];
-    sums[tid] = s;
+    const int64_t len = n_dev ? (int64_t)len_mul * used_tiles(count_of(n_dev, cap)) : len_fixed;
+    if (tid == 0) carry_s = 0;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        uint32_t v = tid >= off ? sums[tid - off] : 0u;
+    for (int64_t base = 0; base < len; base += 4096) {
+        const int64_t i0 = base + 4 * (int64_t)tid;
+        uint32_t v[4];
+        for (int j = 0; j < 4; j++) v[j] = i0 + j < len ? a[i0 + j] : 0u;
+        const uint32_t t = v[0] + v[1] + v[2] + v[3];
+        sums[tid] = t;
         __syncthreads();
-        sums[tid] += v;
+        for (int off = 1; off < 1024; off <<= 1) {
+            const uint32_t x = tid >= off ? sums[tid - off] : 0u;
+            __syncthreads();
+            sums[tid] += x;
+            __syncthreads();
+        }
+        uint32_t run = carry_s + sums[tid] - t;
+        for (int j = 0; j < 4; j++) {
+            if (i0 + j < len) a[i0 + j] = run;
+            run += v[j];
+        }
+        __syncthreads();
+        if (tid == 1023) carry_s += sums[1023];
         __syncthreads();
     }
-    uint32_t run = tid ? sums[tid - 1] : 0u;
-    for (int64_t i = b; i < e; i++) {
-        uint32_t v = a[i];
-        a[i] = run;
-        run += v;
-    }
-    if (total && tid == 1023) *total = sums[1023];
+    if (total && tid == 0) *total = carry_s;
 }
 
 __global__ void __launch_bounds__(kThreads) k_rank_scatter(const uint64_t* __restrict__ kin,
@@ -75,7 +89,7 @@ __global__ void __launch_bounds__(kThreads) k_rank_scatter(const uint64_t* __res
                                                             uint64_t* __restrict__ kout,
                                                             uint32_t* __restrict__ vout, int64_t cap,
                                                             const int64_t* n_dev, int shift,
-                                                            const uint32_t* __restrict__ offs, int nblocks) {
+                                                            const uint32_t* __restrict__ offs) {
     __shared__ uint32_t run[256];
     __shared__ uint32_t wcnt[kWaves][256];
     const int tid = threadIdx.x;
@@ -84,7 +98,7 @@ __global__ void __launch_bounds__(kThreads) k_rank_scatter(const uint64_t* __res
     const int64_t n = count_of(n_dev, cap);
     const int64_t base = (int64_t)blockIdx.x * kTile;
     if (base >= n) return;   // whole workgroup leaves together
-    run[tid] = offs[(int64_t)tid * nblocks + blockIdx.x];
+    run[tid] = offs[(int64_t)tid * used_tiles(n) + blockIdx.x];
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int i = 0; i < kItems; i++) {
         const int64_t idx = base + (int64_t)i * kThreads + tid;
@@ -194,12 +208,12 @@ int radix_sort_pairs(Workspace& ws, uint64_t* k0, uint32_t* v0, uint64_t* k1, ui
     int cur = 0;
     bool first = true;
     for (int shift = begin_bit; shift < end_bit; shift += 8) {
-        hipLaunchKernelGGL(k_digit_hist, dim3(nblocks), dim3(kThreads), 0, st, kin, cap, n_dev, shift, hist,
-                           nblocks);
-        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, st, hist, hlen, (uint32_t*)nullptr);
+        hipLaunchKernelGGL(k_digit_hist, dim3(nblocks), dim3(kThreads), 0, st, kin, cap, n_dev, shift, hist);
+        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, st, hist, hlen, n_dev, cap, 256,
+                           (uint32_t*)nullptr);
         hipLaunchKernelGGL(k_rank_scatter, dim3(nblocks), dim3(kThreads), 0, st, kin,
                            first && iota_values ? (const uint32_t*)nullptr : vin, kout, vout, cap, n_dev,
-                           shift, hist, nblocks);
+                           shift, hist);
         first = false;
         std::swap(kin, kout);
         std::swap(vin, vout);
@@ -217,7 +231,8 @@ int exclusive_scan_u32(Workspace& ws, const uint32_t* in, uint32_t* out, int64_t
     if (ws.scan_tmp.ensure(sizeof(uint32_t) * (size_t)(nb + 1))) return RT_ENOMEM;
     uint32_t* sums = ws.scan_tmp.as<uint32_t>();
     hipLaunchKernelGGL(k_block_sums, dim3(nb), dim3(kScanThreads), 0, st, in, cap, n_dev, sums);
-    hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, st, sums, (int64_t)nb, sums + nb);
+    hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, st, sums, (int64_t)nb, (const int64_t*)nullptr,
+                       (int64_t)0, 0, sums + nb);
     hipLaunchKernelGGL(k_block_scan, dim3(nb), dim3(kScanThreads), 0, st, in, cap, n_dev, sums, sums + nb, out);
     RT_HIP(hipGetLastError());
     return RT_OK;

@@ -60,10 +60,13 @@ struct TraceArgs {
     int32_t fetch_thr;
     int32_t shade_thr;
     int64_t max_steps;
+    const uint32_t* order;          // pool index -> ray id (NULL: identity)
+    unsigned long long* stats;      // NULL or [4]
 };
 
-__global__ void k_trace_reset(unsigned long long* counters, unsigned long long* pool) {
+__global__ void k_trace_reset(unsigned long long* counters, unsigned long long* pool, unsigned long long* stats) {
     if (threadIdx.x < 4) counters[threadIdx.x] = 0ull;
+    if (stats && threadIdx.x < 4) stats[threadIdx.x] = 0ull;
     if (threadIdx.x == 0) pool[0] = 0ull;
 }
 
@@ -204,6 +207,8 @@ __global__ void __launch_bounds__(kBlock) k_trace(TraceArgs a) {
     int32_t best_j = -1, best_id = 0x7FFFFFFF;
     int64_t steps = 0;
     unsigned long long n_query = 0, n_escape = 0;
+    unsigned long long st_nodes = 0, st_leaves = 0, st_tris = 0, st_spill = 0;
+    const bool want_stats = a.stats != nullptr;
     bool pool_empty = false;
 
     for (;;) {
@@ -219,7 +224,7 @@ __global__ void __launch_bounds__(kBlock) k_trace(TraceArgs a) {
             if (status == kIdle) {
                 const unsigned long long my = base + (unsigned long long)__popcll(idle & lt_mask);
                 if (my < (unsigned long long)a.n_rays) {
-                    ray = (int64_t)my;
+                    ray = a.order ? (int64_t)a.order[my] : (int64_t)my;
                     if (a.origins) {
                         r.ox = a.origins[3 * ray];
                         r.oy = a.origins[3 * ray + 1];
@@ -266,6 +271,7 @@ __global__ void __launch_bounds__(kBlock) k_trace(TraceArgs a) {
                 continue;
             }
             if (cur >= 0) {
+                if (want_stats) st_nodes++;
                 if (cur >= a.n_nodes) {
                     atomicOr(&a.counters[3], kErrNode);
                     best_j = -1;
@@ -303,6 +309,7 @@ __global__ void __launch_bounds__(kBlock) k_trace(TraceArgs a) {
                 cswap(tn[1], rf[1], tn[2], rf[2]);
                 const int nh = (tn[0] < INFINITY) + (tn[1] < INFINITY) + (tn[2] < INFINITY) + (tn[3] < INFINITY);
                 bool ok = true;
+                if (want_stats && st.cnt + nh - 1 > kRing) st_spill++;
                 if (nh > 3) ok &= stack_push(st, lds_stack, spill, a.spill_per_lane, tid, rf[3]);
                 if (nh > 2) ok &= stack_push(st, lds_stack, spill, a.spill_per_lane, tid, rf[2]);
                 if (nh > 1) ok &= stack_push(st, lds_stack, spill, a.spill_per_lane, tid, rf[1]);
@@ -318,6 +325,10 @@ __global__ void __launch_bounds__(kBlock) k_trace(TraceArgs a) {
                     have = stack_pop(st, lds_stack, spill, tid, cur);
             } else {
                 const int32_t first = leaf_first(cur), cnt = leaf_count(cur);
+                if (want_stats) {
+                    st_leaves++;
+                    st_tris += (unsigned long long)cnt;
+                }
                 if (first + cnt > a.n_tri) {
                     atomicOr(&a.counters[3], kErrNode);
                     best_j = -1;
@@ -448,8 +459,7 @@ __global__ void __launch_bounds__(kBlock) k_trace(TraceArgs a) {
                 }
             }
             if (stop) {
-                for (int kk = k + 1; kk < R1; kk++) hs[kk] = -1;
-                status = kIdle;
+                status = kIdle;   // rest of the row keeps the -1 written by k_fill_rows
             } else {
                 k++;
                 setup_ray(r);
@@ -467,11 +477,91 @@ __global__ void __launch_bounds__(kBlock) k_trace(TraceArgs a) {
     for (int off = kWave / 2; off > 0; off >>= 1) {
         n_query += __shfl_down(n_query, off);
         n_escape += __shfl_down(n_escape, off);
+        if (want_stats) {
+            st_nodes += __shfl_down(st_nodes, off);
+            st_leaves += __shfl_down(st_leaves, off);
+            st_tris += __shfl_down(st_tris, off);
+            st_spill += __shfl_down(st_spill, off);
+        }
     }
     if (lane == 0) {
         if (n_query) atomicAdd(&a.counters[1], n_query);
         if (n_escape) atomicAdd(&a.counters[2], n_escape);
+        if (want_stats) {
+            atomicAdd(&a.stats[0], st_nodes);
+            atomicAdd(&a.stats[1], st_leaves);
+            atomicAdd(&a.stats[2], st_tris);
+            atomicAdd(&a.stats[3], st_spill);
+        }
     }
+}
+
+// Sort key of a ray: Morton code of its direction's octahedral map (16 bits
+// per axis) in the low 32 bits and, for per-ray origins, the Morton code of
+// the origin in the scene box (10 bits per axis) above it.
+__device__ inline uint32_t spread16(uint32_t x) {
+    x &= 0xFFFFu;
+    x = (x | (x << 8)) & 0x00FF00FFu;
+    x = (x | (x << 4)) & 0x0F0F0F0Fu;
+    x = (x | (x << 2)) & 0x33333333u;
+    x = (x | (x << 1)) & 0x55555555u;
+    return x;
+}
+__device__ inline uint64_t spread10(uint64_t x) {
+    x &= 0x3FFull;
+    x = (x | (x << 16)) & 0x30000FFull;
+    x = (x | (x << 8)) & 0x300F00Full;
+    x = (x | (x << 4)) & 0x30C30C3ull;
+    x = (x | (x << 2)) & 0x9249249ull;
+    return x;
+}
+
+__global__ void k_ray_keys(const float* __restrict__ dirs, const float* __restrict__ origins, int64_t n,
+                           float bx0, float by0, float bz0, float inv_ext, uint64_t* __restrict__ key) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float x = dirs[3 * i], y = dirs[3 * i + 1], z = dirs[3 * i + 2];
+    const float s = fabsf(x) + fabsf(y) + fabsf(z);
+    float u = 0.f, v = 0.f;
+    if (s > 0.f) {
+        x /= s;
+        y /= s;
+        z /= s;
+        if (z < 0.f) {
+            const float ox = (1.f - fabsf(y)) * (x >= 0.f ? 1.f : -1.f);
+            const float oy = (1.f - fabsf(x)) * (y >= 0.f ? 1.f : -1.f);
+            x = ox;
+            y = oy;
+        }
+        u = fminf(fmaxf((x + 1.f) * 0.5f, 0.f), 1.f);
+        v = fminf(fmaxf((y + 1.f) * 0.5f, 0.f), 1.f);
+    }
+    const uint32_t qu = (uint32_t)(u * 65535.f), qv = (uint32_t)(v * 65535.f);
+    uint64_t k = (uint64_t)(spread16(qu) | (spread16(qv) << 1));
+    if (origins) {
+        const float ox = fminf(fmaxf((origins[3 * i] - bx0) * inv_ext, 0.f), 1.f);
+        const float oy = fminf(fmaxf((origins[3 * i + 1] - by0) * inv_ext, 0.f), 1.f);
+        const float oz = fminf(fmaxf((origins[3 * i + 2] - bz0) * inv_ext, 0.f), 1.f);
+        const uint64_t m = (spread10((uint64_t)(ox * 1023.f)) << 2) | (spread10((uint64_t)(oy * 1023.f)) << 1) |
+                           spread10((uint64_t)(oz * 1023.f));
+        k |= m << 32;
+    }
+    key[i] = k;
+}
+
+// hit_seq <- -1 with 16-byte stores (rows are then written only where hit).
+__global__ void k_fill_rows(int32_t* __restrict__ p, int64_t n) {
+    const int64_t n4 = n >> 2;
+    int4* q = reinterpret_cast<int4*>(p);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride)
+        q[i] = make_int4(-1, -1, -1, -1);
+    for (int64_t i = 4 * n4 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = -1;
+}
+
+__global__ void k_fill_rows_scalar(int32_t* __restrict__ p, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = -1;
 }
 
 // Fibonacci sphere: z_i = 1 - (2i+1)/n, phi_i = i pi (3 - sqrt5) mod 2 pi.
@@ -527,7 +617,8 @@ extern "C" int rt_trace_rays(const rt_scene* scene, const float* src_host, const
     rt_scene* s = const_cast<rt_scene*>(scene);
     if (s->ws.trace_pool.ensure(64)) return RT_ENOMEM;
     unsigned long long* pool = s->ws.trace_pool.as<unsigned long long>();
-    hipLaunchKernelGGL(k_trace_reset, dim3(1), dim3(64), 0, st, (unsigned long long*)counters, pool);
+    hipLaunchKernelGGL(k_trace_reset, dim3(1), dim3(64), 0, st, (unsigned long long*)counters, pool,
+                       (unsigned long long*)p->stats);
     if (n_rays == 0) {
         RT_HIP(hipGetLastError());
         return RT_OK;
@@ -569,6 +660,37 @@ extern "C" int rt_trace_rays(const rt_scene* scene, const float* src_host, const
     a.fetch_thr = p->fetch_threshold > 0 ? p->fetch_threshold : 16;
     a.shade_thr = p->shade_threshold > 0 ? p->shade_threshold : 16;
     a.max_steps = 8 * ((int64_t)s->n_nodes + s->n_tri) + 4096;
+    a.order = nullptr;
+    a.stats = (unsigned long long*)p->stats;
+    if (!p->keep_order && n_rays > 1) {
+        Workspace& ws = s->ws;
+        if (ws.sort_keys[0].ensure(8 * n_rays) || ws.sort_keys[1].ensure(8 * n_rays) ||
+            ws.sort_vals[0].ensure(4 * n_rays) || ws.sort_vals[1].ensure(4 * n_rays))
+            return RT_ENOMEM;
+        float ext = 0.f;
+        for (int c = 0; c < 3; c++) ext = fmaxf(ext, s->bounds[3 + c] - s->bounds[c]);
+        hipLaunchKernelGGL(k_ray_keys, dim3((unsigned)((n_rays + 255) / 256)), dim3(256), 0, st, dirs, origins,
+                           n_rays, s->bounds[0], s->bounds[1], s->bounds[2], ext > 0.f ? 1.f / ext : 0.f,
+                           ws.sort_keys[0].as<uint64_t>());
+        int which = 0;
+        int rc = radix_sort_pairs(ws, ws.sort_keys[0].as<uint64_t>(), ws.sort_vals[0].as<uint32_t>(),
+                                  ws.sort_keys[1].as<uint64_t>(), ws.sort_vals[1].as<uint32_t>(), n_rays, nullptr, 0,
+                                  origins ? 64 : 32, st, &which, true);
+        if (rc) return rc;
+        a.order = which ? ws.sort_vals[1].as<uint32_t>() : ws.sort_vals[0].as<uint32_t>();
+    }
+    {
+        const int64_t cells = n_rays * (int64_t)(p->max_reflections + 1);
+        int64_t fb = (cells / 4 + 255) / 256;
+        const int64_t fcap = (int64_t)device_sm_count() * 16;
+        if (fb > fcap) fb = fcap;
+        if (fb < 1) fb = 1;
+        if (((uintptr_t)hit_seq & 15u) == 0) {
+            hipLaunchKernelGGL(k_fill_rows, dim3((unsigned)fb), dim3(256), 0, st, hit_seq, cells);
+        } else {
+            hipLaunchKernelGGL(k_fill_rows_scalar, dim3((unsigned)fb), dim3(256), 0, st, hit_seq, cells);
+        }
+    }
     hipLaunchKernelGGL(k_trace, dim3((unsigned)nblk), dim3(kBlock), 0, st, a);
     RT_HIP(hipGetLastError());
     return RT_OK;

@@ -43,7 +43,7 @@ def synthetic_is_table(scene, n_is, max_reflections, n_rcv, seed, L, c, fs, n_ra
         seq = tuple(int(p) for p in rng.choice(planes, size=k))
         keys.append((r, k) + seq)
         counts.append(int(rng.integers(1, 50)))
-        dists.append(float(rng.uniform(0.5, 1.05 * c * tmax)))
+        dists.append(float(rng.uniform(0.0, max(1.05 * c * tmax, 1e-3))))
     # merge duplicates (keys must be unique)
     d = {}
     for k, n, x in zip(keys, counts, dists):
