@@ -45,7 +45,11 @@ def main():
     ap.add_argument("--fetch", type=int, default=0)
     ap.add_argument("--bpc", type=int, default=0)
     ap.add_argument("--keep-order", action="store_true")
+    ap.add_argument("--rounds", type=int, default=0)
+    ap.add_argument("--spill", type=int, default=0)
     ap.add_argument("--stats", action="store_true", help="count traversal work (extra pass, not timed)")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (the ray set would be split "
@@ -94,7 +98,8 @@ def main():
         mark("trace", 0)
         tr = rt.trace_rays(sc, dirs, rcv, R, src=s.src, max_path_length=s.max_path_length, det_cap=det_cap,
                            check_capacity=False, out=state.get("tr"), shade_threshold=args.shade,
-                           fetch_threshold=args.fetch, blocks_per_cu=args.bpc, keep_order=args.keep_order)
+                           fetch_threshold=args.fetch, blocks_per_cu=args.bpc, keep_order=args.keep_order,
+                           rounds=args.rounds, spill_threshold=args.spill)
         mark("trace", 1)
         state["tr"] = tr
         mark("collect", 0)
@@ -108,6 +113,13 @@ def main():
         state["scene"] = sc
         return sc
 
+    if args.calib_copy_mb:
+        src_buf = torch.ones(args.calib_copy_mb * (1 << 20) // 4, dtype=torch.float32, device=dev)
+        dst_buf = torch.empty_like(src_buf)
+        torch.cuda.synchronize()
+        dst_buf.copy_(src_buf)
+        torch.cuda.synchronize()
+        del src_buf, dst_buf
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -167,6 +179,7 @@ def main():
         out["traversal_per_query"] = {"inner_nodes": st[0] / queries, "leaves": st[1] / queries,
                                       "triangles": st[2] / queries, "spills": st[3] / queries,
                                       "tree_nodes": sc.n_nodes, "tree_depth": sc.depth}
+    out["roofline"]["traffic"] = measured_traffic()
     # IR band error vs the oracle on a seeded image-source table of this shape
     try:
         out["ir_band_error"] = band_error(rt, state["scene"], s, taps)
@@ -175,6 +188,26 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(s, args.cpu_rays)
     print(json.dumps(out), flush=True)
+
+
+def measured_traffic():
+    """HBM bytes per k_trace launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary (copy-kernel calibrated), or None when the kernel
+    source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_trace_theater_436k_counters.txt")
+    src = os.path.join(ROOT, "paper_1811_05784_amd", "csrc", "trace.hip")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.strip().split("=", 1)
+            kv[k] = v
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if kv.get("trace_source_sha256_16") != sha:
+        return None
+    return int(kv["traffic_bytes_per_launch"])
 
 
 def band_error(rt, sc, s, taps):

@@ -110,6 +110,9 @@ typedef struct {
                                   their direction (and origin) for coherence; 1: in index order */
     int64_t* stats;            /* NULL or device int64[4], overwritten: inner nodes visited,
                                   leaves visited, triangle tests, stack spills                  */
+    int32_t rounds;            /* 0 = default (1); kernel launches: once the ray pool is empty,
+                                  a wavefront with few rays left hands them to the next launch  */
+    int32_t spill_threshold;   /* 0 = default; most rays a wavefront may still hold to hand over */
 } rt_trace_params;
 
 /*

@@ -24,7 +24,7 @@ class BuildParams(ctypes.Structure):
 class TraceParams(ctypes.Structure):
     _fields_ = [("max_reflections", I32), ("max_path_length", F32), ("record_states", I32),
                 ("fetch_threshold", I32), ("shade_threshold", I32), ("blocks_per_cu", I32),
-                ("keep_order", I32), ("stats", P)]
+                ("keep_order", I32), ("stats", P), ("rounds", I32), ("spill_threshold", I32)]
 
 
 # symbol -> (restype, argtypes); mirrors include/rtac.h

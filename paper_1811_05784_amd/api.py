@@ -119,7 +119,7 @@ def trace_rays(scene: Scene, dirs: torch.Tensor, rcv, max_reflections: int, src=
                det_cap: Optional[int] = None, fetch_threshold: int = 0, shade_threshold: int = 0,
                blocks_per_cu: int = 0, check_capacity: bool = True, out: Optional[TraceResult] = None,
                check_errors: bool = True, keep_order: bool = False,
-               stats: Optional[torch.Tensor] = None) -> TraceResult:
+               stats: Optional[torch.Tensor] = None, rounds: int = 0, spill_threshold: int = 0) -> TraceResult:
     """rt_trace_rays.  With check_capacity the call synchronises, and re-runs
     with a larger detection buffer if the first one overflowed."""
     lib = _lib.load()
@@ -143,7 +143,8 @@ def trace_rays(scene: Scene, dirs: torch.Tensor, rcv, max_reflections: int, src=
             else None,
             max_reflections=max_reflections)
     prm = TraceParams(int(max_reflections), float(max_path_length), int(bool(record_states)), int(fetch_threshold),
-                      int(shade_threshold), int(blocks_per_cu), int(bool(keep_order)), _ptr(stats))
+                      int(shade_threshold), int(blocks_per_cu), int(bool(keep_order)), _ptr(stats),
+                      int(rounds), int(spill_threshold))
     with torch.cuda.device(dev):
         check(lib.rt_trace_rays(scene.handle, src_h, _ptr(org), _ptr(dirs), _ptr(spl), _ptr(sln), n, _ptr(rcv_t),
                                 rcv_t.shape[0], ctypes.byref(prm), _ptr(out.hit_seq), _ptr(out.det),
@@ -157,7 +158,8 @@ def trace_rays(scene: Scene, dirs: torch.Tensor, rcv, max_reflections: int, src=
             return trace_rays(scene, dirs, rcv_t, max_reflections, src, org, spl, sln, max_path_length,
                               record_states, det_cap=int(c[0]) + 1024, fetch_threshold=fetch_threshold,
                               shade_threshold=shade_threshold, blocks_per_cu=blocks_per_cu,
-                              keep_order=keep_order, stats=stats)
+                              keep_order=keep_order, stats=stats, rounds=rounds,
+                              spill_threshold=spill_threshold)
     return out
 
 

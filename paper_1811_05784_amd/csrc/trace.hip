@@ -62,12 +62,23 @@ struct TraceArgs {
     int64_t max_steps;
     const uint32_t* order;          // pool index -> ray id (NULL: identity)
     unsigned long long* stats;      // NULL or [4]
+    // continuation rounds: rays still in flight when the pool is empty and a
+    // wavefront is mostly idle are written to q_out and finished by the next
+    // launch, which takes its rays from q_in instead of the source
+    const int4* q_in;
+    const unsigned long long* q_in_count;
+    int4* q_out;
+    unsigned long long* q_out_count;
+    int32_t spill_thr;
 };
+
+// queued ray: (ray, k, last plane, -) (o.x, o.y, o.z, L) (u.x, u.y, u.z, -)
+constexpr int kQueueInts = 12;
 
 __global__ void k_trace_reset(unsigned long long* counters, unsigned long long* pool, unsigned long long* stats) {
     if (threadIdx.x < 4) counters[threadIdx.x] = 0ull;
     if (stats && threadIdx.x < 4) stats[threadIdx.x] = 0ull;
-    if (threadIdx.x == 0) pool[0] = 0ull;
+    if (threadIdx.x < 32) pool[threadIdx.x] = 0ull;   // pool counters and queue lengths of every round
 }
 
 struct Ray {
@@ -209,7 +220,8 @@ __global__ void __launch_bounds__(kBlock) k_trace(TraceArgs a) {
     unsigned long long n_query = 0, n_escape = 0;
     unsigned long long st_nodes = 0, st_leaves = 0, st_tris = 0, st_spill = 0;
     const bool want_stats = a.stats != nullptr;
-    bool pool_empty = false;
+    const unsigned long long pool_n = a.q_in ? *a.q_in_count : (unsigned long long)a.n_rays;
+    bool pool_empty = pool_n == 0;
 
     for (;;) {
         // ---- refill idle lanes from the ray pool -----------------------------
@@ -220,26 +232,40 @@ __global__ void __launch_bounds__(kBlock) k_trace(TraceArgs a) {
             unsigned long long base = 0;
             if (lane == leader) base = atomicAdd(a.pool, (unsigned long long)n_idle);
             base = __shfl(base, leader);
-            if (base + (unsigned long long)n_idle >= (unsigned long long)a.n_rays) pool_empty = true;
+            if (base + (unsigned long long)n_idle >= pool_n) pool_empty = true;
             if (status == kIdle) {
                 const unsigned long long my = base + (unsigned long long)__popcll(idle & lt_mask);
-                if (my < (unsigned long long)a.n_rays) {
-                    ray = a.order ? (int64_t)a.order[my] : (int64_t)my;
-                    if (a.origins) {
-                        r.ox = a.origins[3 * ray];
-                        r.oy = a.origins[3 * ray + 1];
-                        r.oz = a.origins[3 * ray + 2];
+                if (my < pool_n) {
+                    if (a.q_in) {
+                        const int4 e0 = a.q_in[3 * my], e1 = a.q_in[3 * my + 1], e2 = a.q_in[3 * my + 2];
+                        ray = e0.x;
+                        k = e0.y;
+                        last_plane = e0.z;
+                        r.ox = __int_as_float(e1.x);
+                        r.oy = __int_as_float(e1.y);
+                        r.oz = __int_as_float(e1.z);
+                        L = __int_as_float(e1.w);
+                        r.ux = __int_as_float(e2.x);
+                        r.uy = __int_as_float(e2.y);
+                        r.uz = __int_as_float(e2.z);
                     } else {
-                        r.ox = a.src[0];
-                        r.oy = a.src[1];
-                        r.oz = a.src[2];
+                        ray = a.order ? (int64_t)a.order[my] : (int64_t)my;
+                        if (a.origins) {
+                            r.ox = a.origins[3 * ray];
+                            r.oy = a.origins[3 * ray + 1];
+                            r.oz = a.origins[3 * ray + 2];
+                        } else {
+                            r.ox = a.src[0];
+                            r.oy = a.src[1];
+                            r.oz = a.src[2];
+                        }
+                        r.ux = a.dirs[3 * ray];
+                        r.uy = a.dirs[3 * ray + 1];
+                        r.uz = a.dirs[3 * ray + 2];
+                        L = a.start_len ? a.start_len[ray] : 0.f;
+                        last_plane = a.start_plane ? a.start_plane[ray] : -1;
+                        k = 0;
                     }
-                    r.ux = a.dirs[3 * ray];
-                    r.uy = a.dirs[3 * ray + 1];
-                    r.uz = a.dirs[3 * ray + 2];
-                    L = a.start_len ? a.start_len[ray] : 0.f;
-                    last_plane = a.start_plane ? a.start_plane[ray] : -1;
-                    k = 0;
                     setup_ray(r);
                     cur = 0;
                     st = Stack{0, 0, 0};
@@ -250,6 +276,30 @@ __global__ void __launch_bounds__(kBlock) k_trace(TraceArgs a) {
                     status = kQuery;
                     if (r.ux == 0.f && r.uy == 0.f && r.uz == 0.f) status = kDone;   // degenerate: escapes
                 }
+            }
+        }
+        // ---- hand a mostly idle wavefront's rays to the next launch ----------
+        if (pool_empty && a.q_out) {
+            const uint64_t act = __ballot(status != kIdle);
+            if (__popcll(act) <= a.spill_thr && __ballot(status == kDone) == 0ull) {
+                const int n_act = __popcll(act);
+                if (n_act > 0) {
+                    const int leader = __ffsll((long long)act) - 1;
+                    unsigned long long base = 0;
+                    if (lane == leader) base = atomicAdd(a.q_out_count, (unsigned long long)n_act);
+                    base = __shfl(base, leader);
+                    if (status != kIdle) {
+                        // the current segment restarts from its input state
+                        const unsigned long long pos = base + (unsigned long long)__popcll(act & lt_mask);
+                        int4* q = a.q_out + 3 * pos;
+                        q[0] = make_int4((int)ray, k, last_plane, 0);
+                        q[1] = make_int4(__float_as_int(r.ox), __float_as_int(r.oy), __float_as_int(r.oz),
+                                         __float_as_int(L));
+                        q[2] = make_int4(__float_as_int(r.ux), __float_as_int(r.uy), __float_as_int(r.uz), 0);
+                        status = kIdle;
+                    }
+                }
+                break;
             }
         }
         if (__ballot(status != kIdle) == 0ull) {
@@ -615,7 +665,7 @@ extern "C" int rt_trace_rays(const rt_scene* scene, const float* src_host, const
     RT_CHECK(n_rays == 0 || (dirs && hit_seq), RT_EINVAL, "rt_trace_rays: dirs/hit_seq is NULL");
     hipStream_t st = (hipStream_t)stream;
     rt_scene* s = const_cast<rt_scene*>(scene);
-    if (s->ws.trace_pool.ensure(64)) return RT_ENOMEM;
+    if (s->ws.trace_pool.ensure(32 * sizeof(unsigned long long))) return RT_ENOMEM;
     unsigned long long* pool = s->ws.trace_pool.as<unsigned long long>();
     hipLaunchKernelGGL(k_trace_reset, dim3(1), dim3(64), 0, st, (unsigned long long*)counters, pool,
                        (unsigned long long*)p->stats);
@@ -691,7 +741,23 @@ extern "C" int rt_trace_rays(const rt_scene* scene, const float* src_host, const
             hipLaunchKernelGGL(k_fill_rows_scalar, dim3((unsigned)fb), dim3(256), 0, st, hit_seq, cells);
         }
     }
-    hipLaunchKernelGGL(k_trace, dim3((unsigned)nblk), dim3(kBlock), 0, st, a);
+    // continuation rounds: launch rd takes the rays left over by launch rd-1;
+    // every launch hands over at most one ray per lane, so a queue of one
+    // entry per lane of the grid never overflows
+    const int rounds = p->rounds > 0 ? (p->rounds < 16 ? p->rounds : 16) : 1;
+    const int64_t lanes = nblk * kBlock;
+    if (s->ws.generic[0].ensure(sizeof(int32_t) * kQueueInts * (size_t)lanes * 2)) return RT_ENOMEM;
+    int4* qbuf[2] = {s->ws.generic[0].as<int4>(), s->ws.generic[0].as<int4>() + 3 * lanes};
+    a.spill_thr = p->spill_threshold > 0 ? p->spill_threshold : 24;
+    for (int rd = 0; rd < rounds; rd++) {
+        a.pool = pool + rd;
+        a.q_in = rd == 0 ? nullptr : qbuf[(rd - 1) & 1];
+        a.q_in_count = rd == 0 ? nullptr : pool + 16 + (rd - 1);
+        a.q_out = rd + 1 < rounds ? qbuf[rd & 1] : nullptr;
+        a.q_out_count = pool + 16 + rd;
+        if (rd > 0) a.order = nullptr;
+        hipLaunchKernelGGL(k_trace, dim3((unsigned)nblk), dim3(kBlock), 0, st, a);
+    }
     RT_HIP(hipGetLastError());
     return RT_OK;
 }
