@@ -89,7 +89,7 @@ __global__ void __launch_bounds__(256) k_tri_prep(const float* __restrict__ vtx,
             const double cz = e1[0] * e2[1] - e1[1] * e2[0];
             if (cx == 0.0 && cy == 0.0 && cz == 0.0) err |= kErrZeroArea;
             atomicMax(&s_mat, (uint32_t)m);
-            atomicMin(&prep[p], (int32_t)i);
+            if ((int32_t)i < prep[p]) atomicMin(&prep[p], (int32_t)i);   // stale reads only add atomics
             for (int c = 0; c < 3; c++) {
                 const float lo = fminf(v[0][c], fminf(v[1][c], v[2][c]));
                 const float hi = fmaxf(v[0][c], fmaxf(v[1][c], v[2][c]));
@@ -266,45 +266,63 @@ __global__ void k_radix_tree(const uint64_t* __restrict__ k, int64_t n, int32_t*
     if (i == 0) parent_in[0] = -1;
 }
 
-// Bottom-up boxes: the second child to arrive at a node computes its box.
-// Boxes written by other threads are read with relaxed device-scope atomic
-// loads (no L1 staleness, and independent loads stay in flight together).
-__device__ inline float load_coherent(const float* p) {
-    return __uint_as_float(__hip_atomic_load(reinterpret_cast<const uint32_t*>(p), __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT));
-}
-__device__ inline void store_coherent(float* p, float v) {
-    __hip_atomic_store(reinterpret_cast<uint32_t*>(p), __float_as_uint(v), __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-}
+// Boxes of inner nodes.  Every inner node of the radix tree covers a range
+// [first, last] of the Morton-ordered triangles, so its box is a range union:
+// a segment tree over the ordered triangle boxes (level l entry i covers
+// triangles [i 2^l, (i+1) 2^l)) answers it with O(log M) reads and no atomics.
+struct SegBox {
+    float4 lo, hi;
+};
 
-__global__ void k_refit(int64_t n, const uint32_t* __restrict__ order, const float* __restrict__ tri_box,
-                        const int32_t* __restrict__ left, const int32_t* __restrict__ right,
-                        const int32_t* __restrict__ parent_in, const int32_t* __restrict__ parent_leaf,
-                        float* box_in, uint32_t* __restrict__ arrive) {
+__global__ void k_seg_leaves(int64_t n, const uint32_t* __restrict__ order, const float* __restrict__ tri_box,
+                             SegBox* __restrict__ lvl0) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
-    int32_t p = parent_leaf[j];
-    while (p >= 0) {
-        if (__hip_atomic_fetch_add(&arrive[p], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == 0) return;
-        float b[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
-        const int32_t ch[2] = {left[p], right[p]};
-        float cb[2][6];
-        for (int c2 = 0; c2 < 2; c2++) {
-            const int32_t c = ch[c2];
-            if (c < 0) {
-                const uint32_t t = order[~c];
-                for (int a = 0; a < 6; a++) cb[c2][a] = tri_box[6 * (int64_t)t + a];
-            } else {
-                for (int a = 0; a < 6; a++) cb[c2][a] = load_coherent(box_in + 6 * (int64_t)c + a);
-            }
+    const float* b = tri_box + 6 * (int64_t)order[j];
+    lvl0[j] = SegBox{make_float4(b[0], b[1], b[2], 0.f), make_float4(b[3], b[4], b[5], 0.f)};
+}
+
+__global__ void k_seg_up(int64_t n_child, const SegBox* __restrict__ child, SegBox* __restrict__ parent) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n_par = (n_child + 1) / 2;
+    if (i >= n_par) return;
+    SegBox a = child[2 * i];
+    if (2 * i + 1 < n_child) {
+        const SegBox b = child[2 * i + 1];
+        a.lo = make_float4(fminf(a.lo.x, b.lo.x), fminf(a.lo.y, b.lo.y), fminf(a.lo.z, b.lo.z), 0.f);
+        a.hi = make_float4(fmaxf(a.hi.x, b.hi.x), fmaxf(a.hi.y, b.hi.y), fmaxf(a.hi.z, b.hi.z), 0.f);
+    }
+    parent[i] = a;
+}
+
+struct SegLevels {
+    const SegBox* lvl[32];
+    int n_levels;
+};
+
+__global__ void k_node_boxes(int64_t n_in, const int32_t* __restrict__ first, const int32_t* __restrict__ last,
+                             SegLevels seg, float* __restrict__ box_in) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_in) return;
+    int64_t l = first[i], r = (int64_t)last[i] + 1;
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int lv = 0; l < r && lv < seg.n_levels; lv++) {
+        if (l & 1) {
+            const SegBox b = seg.lvl[lv][l++];
+            lo[0] = fminf(lo[0], b.lo.x); lo[1] = fminf(lo[1], b.lo.y); lo[2] = fminf(lo[2], b.lo.z);
+            hi[0] = fmaxf(hi[0], b.hi.x); hi[1] = fmaxf(hi[1], b.hi.y); hi[2] = fmaxf(hi[2], b.hi.z);
         }
-        for (int a = 0; a < 3; a++) {
-            b[a] = fminf(cb[0][a], cb[1][a]);
-            b[3 + a] = fmaxf(cb[0][3 + a], cb[1][3 + a]);
+        if (r & 1) {
+            const SegBox b = seg.lvl[lv][--r];
+            lo[0] = fminf(lo[0], b.lo.x); lo[1] = fminf(lo[1], b.lo.y); lo[2] = fminf(lo[2], b.lo.z);
+            hi[0] = fmaxf(hi[0], b.hi.x); hi[1] = fmaxf(hi[1], b.hi.y); hi[2] = fmaxf(hi[2], b.hi.z);
         }
-        for (int a = 0; a < 6; a++) store_coherent(box_in + 6 * (int64_t)p + a, b[a]);
-        p = parent_in[p];
+        l >>= 1;
+        r >>= 1;
+    }
+    for (int a = 0; a < 3; a++) {
+        box_in[6 * i + a] = lo[a];
+        box_in[6 * i + 3 + a] = hi[a];
     }
 }
 
@@ -532,19 +550,45 @@ extern "C" int rt_build_tree(const float* vtx, int64_t n_vtx, const int32_t* tri
         int32_t* par_leaf = tmp.get<int32_t>(nt);
         int32_t* depth = tmp.get<int32_t>(n_in);
         float* box_in = tmp.get<float>(6 * n_in);
-        uint32_t* arrive = tmp.get<uint32_t>(n_in);
         uint32_t* flag = tmp.get<uint32_t>(n_in);
         uint32_t* index = tmp.get<uint32_t>(n_in + 1);
-        if (!left || !right || !first || !last || !par_in || !par_leaf || !depth || !box_in || !arrive || !flag ||
+        if (!left || !right || !first || !last || !par_in || !par_leaf || !depth || !box_in || !flag ||
             !index) {
             set_error("rt_build_tree: out of device memory");
             return fail(RT_ENOMEM);
         }
-        hipLaunchKernelGGL(k_fill_i32, dim3(blocks(n_in)), dim3(256), 0, st, (int32_t*)arrive, n_in, 0);
         hipLaunchKernelGGL(k_radix_tree, dim3(blocks(n_in)), dim3(256), 0, st, codes, nt, left, right, first, last,
                            par_in, par_leaf);
-        hipLaunchKernelGGL(k_refit, dim3(blocks(nt)), dim3(256), 0, st, nt, order, tri_box, left, right, par_in,
-                           par_leaf, box_in, arrive);
+        // segment tree over the ordered triangle boxes, then one range query per inner node
+        SegLevels seg;
+        seg.n_levels = 0;
+        int64_t total = 0;
+        for (int64_t w = nt;; w = (w + 1) / 2) {
+            total += w;
+            seg.n_levels++;
+            if (w == 1 || seg.n_levels == 32) break;
+        }
+        SegBox* segbuf = tmp.get<SegBox>(total);
+        if (!segbuf) {
+            set_error("rt_build_tree: out of device memory");
+            return fail(RT_ENOMEM);
+        }
+        {
+            int64_t off = 0, w = nt;
+            for (int lv = 0; lv < seg.n_levels; lv++) {
+                seg.lvl[lv] = segbuf + off;
+                if (lv == 0) {
+                    hipLaunchKernelGGL(k_seg_leaves, dim3(blocks(nt)), dim3(256), 0, st, nt, order, tri_box,
+                                       segbuf);
+                } else {
+                    hipLaunchKernelGGL(k_seg_up, dim3(blocks((w + 1) / 2)), dim3(256), 0, st, w,
+                                       seg.lvl[lv - 1], segbuf + off);
+                    w = (w + 1) / 2;
+                }
+                off += w;
+            }
+        }
+        hipLaunchKernelGGL(k_node_boxes, dim3(blocks(n_in)), dim3(256), 0, st, n_in, first, last, seg, box_in);
         hipLaunchKernelGGL(k_flag4, dim3(blocks(n_in)), dim3(256), 0, st, n_in, first, last, par_in, leaf, flag,
                            depth);
         rc = exclusive_scan_u32(s->ws, flag, index, n_in, nullptr, st);

@@ -48,40 +48,57 @@ __global__ void __launch_bounds__(kThreads) k_digit_hist(const uint64_t* __restr
 }
 
 // In-place exclusive scan of a[0..len) by one workgroup of 1024 threads,
-// 4096 elements per round (coalesced uint4 loads, LDS scan of thread sums).
+// 8192 elements per round: each thread scans 8 consecutive elements, waves
+// scan their thread totals with lane shuffles, one wave scans the 16 wave
+// totals (two barriers per round).
 // len = len_mul * used_tiles(n) when n_dev is given, else len_fixed.
 __global__ void __launch_bounds__(1024) k_scan_single(uint32_t* __restrict__ a, int64_t len_fixed,
                                                        const int64_t* n_dev, int64_t cap, int len_mul,
                                                        uint32_t* __restrict__ total) {
-    __shared__ uint32_t sums[1024];
+    __shared__ uint32_t wsum[16];
     __shared__ uint32_t carry_s;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t len = n_dev ? (int64_t)len_mul * used_tiles(count_of(n_dev, cap)) : len_fixed;
-    if (tid == 0) carry_s = 0;
-    __syncthreads();
-    for (int64_t base = 0; base < len; base += 4096) {
-        const int64_t i0 = base + 4 * (int64_t)tid;
-        uint32_t v[4];
-        for (int j = 0; j < 4; j++) v[j] = i0 + j < len ? a[i0 + j] : 0u;
-        const uint32_t t = v[0] + v[1] + v[2] + v[3];
-        sums[tid] = t;
-        __syncthreads();
-        for (int off = 1; off < 1024; off <<= 1) {
-            const uint32_t x = tid >= off ? sums[tid - off] : 0u;
-            __syncthreads();
-            sums[tid] += x;
-            __syncthreads();
+    uint32_t carry = 0;
+    for (int64_t base = 0; base < len; base += 8192) {
+        const int64_t i0 = base + 8 * (int64_t)tid;
+        uint32_t v[8];
+        uint32_t t = 0;
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            v[j] = i0 + j < len ? a[i0 + j] : 0u;
+            t += v[j];
         }
-        uint32_t run = carry_s + sums[tid] - t;
-        for (int j = 0; j < 4; j++) {
+        uint32_t incl = t;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t x = __shfl_up(incl, off);
+            if (lane >= off) incl += x;
+        }
+        if (lane == 63) wsum[wave] = incl;
+        __syncthreads();
+        if (wave == 0) {
+            uint32_t w = lane < 16 ? wsum[lane] : 0u;
+            uint32_t wi = w;
+#pragma unroll
+            for (int off = 1; off < 16; off <<= 1) {
+                const uint32_t x = __shfl_up(wi, off);
+                if (lane >= off) wi += x;
+            }
+            if (lane < 16) wsum[lane] = wi - w;   // exclusive wave offsets
+            if (lane == 15) carry_s = wi;         // round total
+        }
+        __syncthreads();
+        uint32_t run = carry + wsum[wave] + incl - t;
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
             if (i0 + j < len) a[i0 + j] = run;
             run += v[j];
         }
-        __syncthreads();
-        if (tid == 1023) carry_s += sums[1023];
+        carry += carry_s;
         __syncthreads();
     }
-    if (total && tid == 0) *total = carry_s;
+    if (total && tid == 0) *total = carry;
 }
 
 __global__ void __launch_bounds__(kThreads) k_rank_scatter(const uint64_t* __restrict__ kin,
