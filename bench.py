@@ -47,6 +47,7 @@ def main():
     ap.add_argument("--keep-order", action="store_true")
     ap.add_argument("--rounds", type=int, default=0)
     ap.add_argument("--spill", type=int, default=0)
+    ap.add_argument("--wps", type=int, default=0, help="trace kernel waves per SIMD (4, 5, 6, 8)")
     ap.add_argument("--stats", action="store_true", help="count traversal work (extra pass, not timed)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (counter calibration)")
@@ -99,7 +100,7 @@ def main():
         tr = rt.trace_rays(sc, dirs, rcv, R, src=s.src, max_path_length=s.max_path_length, det_cap=det_cap,
                            check_capacity=False, out=state.get("tr"), shade_threshold=args.shade,
                            fetch_threshold=args.fetch, blocks_per_cu=args.bpc, keep_order=args.keep_order,
-                           rounds=args.rounds, spill_threshold=args.spill)
+                           rounds=args.rounds, spill_threshold=args.spill, waves_per_simd=args.wps)
         mark("trace", 1)
         state["tr"] = tr
         mark("collect", 0)

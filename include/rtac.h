@@ -113,6 +113,7 @@ typedef struct {
     int32_t rounds;            /* 0 = default (1); kernel launches: once the ray pool is empty,
                                   a wavefront with few rays left hands them to the next launch  */
     int32_t spill_threshold;   /* 0 = default; most rays a wavefront may still hold to hand over */
+    int32_t waves_per_simd;    /* 0 = default (4); register budget of the trace kernel: 4, 5, 6, 8  */
 } rt_trace_params;
 
 /*
@@ -214,6 +215,60 @@ int rt_band_energy_adjoint(const rt_scene* scene, const int32_t* is_key, const i
                            int32_t max_reflections, int64_t n_rays, int32_t n_rcv, const float* alpha,
                            int32_t n_mat, const float* beta, float c, float fs, int64_t L,
                            const float* grad_band_energy, float* grad_alpha, void* stream);
+
+/*
+ * Batches: many jobs -- a source with its own Fibonacci rays and receivers in
+ * one of several scenes (rooms of uneven size) -- traced by one persistent
+ * launch (spec add-on; each job follows the same definitions as
+ * rt_trace_rays, rt_collect_image_sources, rt_assemble_ir and
+ * rt_band_energy_adjoint).  Rays of job j are global ids ray_off_j ..
+ * ray_off_j + n_rays_j - 1 (jobs in order), receivers of job j are global rows
+ * rcv_off_j .. + n_rcv_j - 1, materials of scene i are global rows
+ * mat_off_i .. + n_mat_i - 1 (scenes in order).  Directions are generated on
+ * the device: ray i of a job with n rays takes Fibonacci direction i of n.
+ */
+typedef struct rt_batch rt_batch;
+
+typedef struct {
+    int32_t scene;             /* index into the scenes of rt_batch_create          */
+    int32_t n_rcv;             /* receivers of this job, 1..32                      */
+    int64_t n_rays;            /* rays of this job                                  */
+    float src[3];              /* point source                                      */
+    float max_path_length;     /* > 0: stop once travelled length reaches it        */
+} rt_job;
+
+/* Uploads the job and scene tables (synchronises `stream` once).  The scenes
+ * must outlive the batch; the first scene's scratch is used by batch calls. */
+int rt_batch_create(const rt_scene* const* scenes, int32_t n_scenes, const rt_job* jobs, int32_t n_jobs, void* stream,
+                    rt_batch** out);
+int rt_batch_destroy(rt_batch* batch);
+/* info_host[0] = jobs, [1] = total rays, [2] = total receivers, [3] = total materials */
+int rt_batch_info(const rt_batch* batch, int64_t* info_host);
+
+/* One persistent launch over every ray of every job.  rcv [total_rcv, 4];
+ * hit_seq [total_rays, R+1]; det rows are (global ray, k, global receiver);
+ * counters as in rt_trace_rays.  record_states is not supported. */
+int rt_trace_batch(rt_batch* batch, const float* rcv, const rt_trace_params* params, int32_t* hit_seq, int32_t* det,
+                   int64_t det_cap, int64_t* counters, void* stream);
+
+/* Image sources of all jobs: keys start with the global receiver row; the
+ * position mirrors the job's source in its scene's planes. */
+int rt_collect_batch(rt_batch* batch, const float* rcv, const int32_t* hit_seq, int32_t max_reflections,
+                     const int32_t* det, int64_t det_cap, const int64_t* n_det, int32_t* is_key, int32_t* is_count,
+                     double* is_pos, double* is_dist, int64_t is_cap, int64_t* n_is, void* stream);
+
+/* Impulse responses of all jobs: alpha [total_mat, 8]; E_s uses the job's ray
+ * count; outputs indexed by global receiver row ([total_rcv, 8] etc.). */
+int rt_assemble_batch(rt_batch* batch, const int32_t* is_key, const int32_t* is_count, const double* is_dist,
+                      const int64_t* n_is, int64_t is_cap, int32_t max_reflections, const float* alpha,
+                      const float* beta, float c, float fs, int64_t L, const float* fir, int32_t K,
+                      float* band_energy, float* hist, float* band_ir, float* ir, void* stream);
+
+/* Gradient of sum_r,b g[r,b] band_energy[r,b] w.r.t. alpha [total_mat, 8]. */
+int rt_adjoint_batch(rt_batch* batch, const int32_t* is_key, const int32_t* is_count, const double* is_dist,
+                     const int64_t* n_is, int64_t is_cap, int32_t max_reflections, const float* alpha,
+                     const float* beta, float c, float fs, int64_t L, const float* grad_band_energy,
+                     float* grad_alpha, void* stream);
 
 /* Test hook for the exact-grouping path of rt_collect_image_sources: keep
  * only the low `bits` bits (1..64, default 64) of the 64-bit key hash so that

@@ -6,6 +6,6 @@ kernels behind the C-ABI in include/rtac.h.  This package is the thin
 binding (ctypes + torch tensors for device memory and streams).
 """
 from ._lib import RtError, load  # noqa: F401
-from .api import (BandEnergy, ImageSources, ImpulseResponse, Scene, TraceResult,  # noqa: F401
-                  assemble_ir, band_energy_adjoint, collect_image_sources, fibonacci_directions,
-                  trace_rays, version)
+from .api import (BandEnergy, Batch, ImageSources, ImpulseResponse, Scene, TraceResult,  # noqa: F401
+                  adjoint_batch, assemble_batch, assemble_ir, band_energy_adjoint, collect_batch,
+                  collect_image_sources, fibonacci_directions, trace_batch, trace_rays, version)

@@ -24,7 +24,12 @@ class BuildParams(ctypes.Structure):
 class TraceParams(ctypes.Structure):
     _fields_ = [("max_reflections", I32), ("max_path_length", F32), ("record_states", I32),
                 ("fetch_threshold", I32), ("shade_threshold", I32), ("blocks_per_cu", I32),
-                ("keep_order", I32), ("stats", P), ("rounds", I32), ("spill_threshold", I32)]
+                ("keep_order", I32), ("stats", P), ("rounds", I32), ("spill_threshold", I32),
+                ("waves_per_simd", I32)]
+
+
+class Job(ctypes.Structure):
+    _fields_ = [("scene", I32), ("n_rcv", I32), ("n_rays", I64), ("src", F32 * 3), ("max_path_length", F32)]
 
 
 # symbol -> (restype, argtypes); mirrors include/rtac.h
@@ -40,6 +45,13 @@ SIGNATURES = {
                                       P]),
     "rt_band_energy_adjoint": (ctypes.c_int, [P, P, P, P, P, I64, I32, I64, I32, P, I32, P, F32, F32, I64, P, P,
                                               P]),
+    "rt_batch_create": (ctypes.c_int, [P, I32, P, I32, P, ctypes.POINTER(P)]),
+    "rt_batch_destroy": (ctypes.c_int, [P]),
+    "rt_batch_info": (ctypes.c_int, [P, P]),
+    "rt_trace_batch": (ctypes.c_int, [P, P, ctypes.POINTER(TraceParams), P, P, I64, P, P]),
+    "rt_collect_batch": (ctypes.c_int, [P, P, P, I32, P, I64, P, P, P, P, P, I64, P, P]),
+    "rt_assemble_batch": (ctypes.c_int, [P, P, P, P, P, I64, I32, P, P, F32, F32, I64, P, I32, P, P, P, P, P]),
+    "rt_adjoint_batch": (ctypes.c_int, [P, P, P, P, P, I64, I32, P, P, F32, F32, I64, P, P, P]),
     "rt_debug_set_hash_bits": (ctypes.c_int, [ctypes.c_int]),
     "rt_last_error": (ctypes.c_char_p, []),
     "rt_version": (ctypes.c_char_p, []),

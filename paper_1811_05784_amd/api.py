@@ -16,7 +16,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import BuildParams, TraceParams, check
+from ._lib import BuildParams, Job, TraceParams, check
 
 P = ctypes.c_void_p
 
@@ -119,7 +119,8 @@ def trace_rays(scene: Scene, dirs: torch.Tensor, rcv, max_reflections: int, src=
                det_cap: Optional[int] = None, fetch_threshold: int = 0, shade_threshold: int = 0,
                blocks_per_cu: int = 0, check_capacity: bool = True, out: Optional[TraceResult] = None,
                check_errors: bool = True, keep_order: bool = False,
-               stats: Optional[torch.Tensor] = None, rounds: int = 0, spill_threshold: int = 0) -> TraceResult:
+               stats: Optional[torch.Tensor] = None, rounds: int = 0, spill_threshold: int = 0,
+               waves_per_simd: int = 0) -> TraceResult:
     """rt_trace_rays.  With check_capacity the call synchronises, and re-runs
     with a larger detection buffer if the first one overflowed."""
     lib = _lib.load()
@@ -144,7 +145,7 @@ def trace_rays(scene: Scene, dirs: torch.Tensor, rcv, max_reflections: int, src=
             max_reflections=max_reflections)
     prm = TraceParams(int(max_reflections), float(max_path_length), int(bool(record_states)), int(fetch_threshold),
                       int(shade_threshold), int(blocks_per_cu), int(bool(keep_order)), _ptr(stats),
-                      int(rounds), int(spill_threshold))
+                      int(rounds), int(spill_threshold), int(waves_per_simd))
     with torch.cuda.device(dev):
         check(lib.rt_trace_rays(scene.handle, src_h, _ptr(org), _ptr(dirs), _ptr(spl), _ptr(sln), n, _ptr(rcv_t),
                                 rcv_t.shape[0], ctypes.byref(prm), _ptr(out.hit_seq), _ptr(out.det),
@@ -159,7 +160,7 @@ def trace_rays(scene: Scene, dirs: torch.Tensor, rcv, max_reflections: int, src=
                               record_states, det_cap=int(c[0]) + 1024, fetch_threshold=fetch_threshold,
                               shade_threshold=shade_threshold, blocks_per_cu=blocks_per_cu,
                               keep_order=keep_order, stats=stats, rounds=rounds,
-                              spill_threshold=spill_threshold)
+                              spill_threshold=spill_threshold, waves_per_simd=waves_per_simd)
     return out
 
 
@@ -277,6 +278,147 @@ class BandEnergy(torch.autograd.Function):
         g = band_energy_adjoint(scene, isrc, n_rays, n_rcv, alpha, beta, c, fs, L, grad.contiguous(),
                                 n_mat=alpha.shape[0])
         return g, None, None, None, None, None, None, None, None
+
+
+class Batch:
+    """Many jobs (source + receivers in one of several scenes) traced by one
+    persistent launch (rt_batch_create / rt_trace_batch and friends).
+
+    jobs: list of dicts with keys scene (index), src (3), rcv ([n, 4] array),
+    n_rays, max_path_length.  Receivers of all jobs are stacked in job order
+    (global rows); materials of all scenes are stacked in scene order."""
+
+    def __init__(self, scenes, jobs, device=None):
+        lib = _lib.load()
+        self.device = _dev(device)
+        self.scenes = list(scenes)
+        self.jobs = [dict(j) for j in jobs]
+        arr = (P * len(self.scenes))(*[sc.handle for sc in self.scenes])
+        jt = (Job * len(self.jobs))()
+        for i, j in enumerate(self.jobs):
+            rcv = np.asarray(j["rcv"], np.float32).reshape(-1, 4)
+            jt[i].scene = int(j["scene"])
+            jt[i].n_rcv = len(rcv)
+            jt[i].n_rays = int(j["n_rays"])
+            for c in range(3):
+                jt[i].src[c] = float(j["src"][c])
+            jt[i].max_path_length = float(j.get("max_path_length", 0.0))
+        self.rcv = torch.as_tensor(np.concatenate([np.asarray(j["rcv"], np.float32).reshape(-1, 4)
+                                                   for j in self.jobs]), device=self.device)
+        self._h = P()
+        with torch.cuda.device(self.device):
+            check(lib.rt_batch_create(arr, len(self.scenes), jt, len(self.jobs), _stream(self.device),
+                                      ctypes.byref(self._h)), "rt_batch_create")
+        info = (ctypes.c_int64 * 4)()
+        check(lib.rt_batch_info(self._h, info), "rt_batch_info")
+        self.n_jobs, self.n_rays, self.n_rcv, self.n_mat = [int(v) for v in info]
+        self.ray_off = np.concatenate([[0], np.cumsum([int(j["n_rays"]) for j in self.jobs])]).astype(np.int64)
+        self.rcv_off = np.concatenate([[0], np.cumsum([len(np.asarray(j["rcv"]).reshape(-1, 4))
+                                                       for j in self.jobs])]).astype(np.int64)
+        self.mat_off = np.concatenate([[0], np.cumsum([sc.n_mat for sc in self.scenes])]).astype(np.int64)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().rt_batch_destroy(self._h)
+            self._h = P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def trace_batch(b: Batch, max_reflections: int, det_cap: Optional[int] = None, out: Optional[TraceResult] = None,
+                check_capacity: bool = True, **tune) -> TraceResult:
+    lib = _lib.load()
+    dev = b.device
+    R1 = max_reflections + 1
+    if det_cap is None:
+        det_cap = max(2 * b.n_rays, 1024)
+    if out is None:
+        out = TraceResult(hit_seq=torch.empty((b.n_rays, R1), dtype=torch.int32, device=dev),
+                          det=torch.empty((det_cap, 3), dtype=torch.int32, device=dev),
+                          counters=torch.zeros(4, dtype=torch.int64, device=dev), states=None,
+                          max_reflections=max_reflections)
+    prm = TraceParams(int(max_reflections), 0.0, 0, int(tune.get("fetch_threshold", 0)),
+                      int(tune.get("shade_threshold", 0)), int(tune.get("blocks_per_cu", 0)), 1, None,
+                      int(tune.get("rounds", 0)), int(tune.get("spill_threshold", 0)),
+                      int(tune.get("waves_per_simd", 0)))
+    with torch.cuda.device(dev):
+        check(lib.rt_trace_batch(b.handle, _ptr(b.rcv), ctypes.byref(prm), _ptr(out.hit_seq), _ptr(out.det),
+                                 out.det.shape[0], _ptr(out.counters), _stream(dev)), "rt_trace_batch")
+    if check_capacity:
+        c = out.counters.cpu()
+        if int(c[3]) != 0:
+            raise _lib.RtError("rt_trace_batch: device error word %d" % int(c[3]))
+        if int(c[0]) > out.det.shape[0]:
+            return trace_batch(b, max_reflections, det_cap=int(c[0]) + 1024, **tune)
+    return out
+
+
+def collect_batch(b: Batch, tr: TraceResult, is_cap: Optional[int] = None, check_capacity: bool = True,
+                  out: Optional[ImageSources] = None) -> ImageSources:
+    lib = _lib.load()
+    dev = b.device
+    R = tr.max_reflections
+    if is_cap is None:
+        is_cap = max(tr.det.shape[0], 1)
+    if out is None:
+        out = ImageSources(key=torch.empty((is_cap, R + 2), dtype=torch.int32, device=dev),
+                           count=torch.empty(is_cap, dtype=torch.int32, device=dev),
+                           pos=torch.empty((is_cap, 3), dtype=torch.float64, device=dev),
+                           dist=torch.empty(is_cap, dtype=torch.float64, device=dev),
+                           n_is_dev=torch.zeros(1, dtype=torch.int64, device=dev), max_reflections=R)
+    with torch.cuda.device(dev):
+        check(lib.rt_collect_batch(b.handle, _ptr(b.rcv), _ptr(tr.hit_seq), R, _ptr(tr.det), tr.det.shape[0],
+                                   _ptr(tr.counters[0:1]), _ptr(out.key), _ptr(out.count), _ptr(out.pos),
+                                   _ptr(out.dist), out.key.shape[0], _ptr(out.n_is_dev), _stream(dev)),
+              "rt_collect_batch")
+    if check_capacity and out.n_is() > out.key.shape[0]:
+        return collect_batch(b, tr, out.n_is(), True)
+    return out
+
+
+def assemble_batch(b: Batch, isrc: ImageSources, alpha, beta, c: float, fs: float, L: int, fir,
+                   out: Optional[ImpulseResponse] = None) -> ImpulseResponse:
+    lib = _lib.load()
+    dev = b.device
+    a = _to_dev(alpha, torch.float32, dev)
+    be = _to_dev(beta, torch.float32, dev)
+    f = _to_dev(fir, torch.float32, dev)
+    n = b.n_rcv
+    if out is None:
+        out = ImpulseResponse(band_energy=torch.empty((n, 8), dtype=torch.float32, device=dev),
+                              hist=torch.empty((n, 8, L), dtype=torch.float32, device=dev),
+                              band_ir=torch.empty((n, 8, L), dtype=torch.float32, device=dev),
+                              ir=torch.empty((n, L), dtype=torch.float32, device=dev))
+    with torch.cuda.device(dev):
+        check(lib.rt_assemble_batch(b.handle, _ptr(isrc.key), _ptr(isrc.count), _ptr(isrc.dist), _ptr(isrc.n_is_dev),
+                                    isrc.key.shape[0], isrc.max_reflections, _ptr(a), _ptr(be), float(c), float(fs),
+                                    int(L), _ptr(f), int(f.shape[1]), _ptr(out.band_energy), _ptr(out.hist),
+                                    _ptr(out.band_ir), _ptr(out.ir), _stream(dev)), "rt_assemble_batch")
+    return out
+
+
+def adjoint_batch(b: Batch, isrc: ImageSources, alpha, beta, c: float, fs: float, L: int, grad_band_energy,
+                  out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    lib = _lib.load()
+    dev = b.device
+    a = _to_dev(alpha, torch.float32, dev)
+    be = _to_dev(beta, torch.float32, dev)
+    g = _to_dev(grad_band_energy, torch.float32, dev)
+    if out is None:
+        out = torch.empty((b.n_mat, 8), dtype=torch.float32, device=dev)
+    with torch.cuda.device(dev):
+        check(lib.rt_adjoint_batch(b.handle, _ptr(isrc.key), _ptr(isrc.count), _ptr(isrc.dist), _ptr(isrc.n_is_dev),
+                                   isrc.key.shape[0], isrc.max_reflections, _ptr(a), _ptr(be), float(c), float(fs),
+                                   int(L), _ptr(g), _ptr(out), _stream(dev)), "rt_adjoint_batch")
+    return out
 
 
 def version() -> str:

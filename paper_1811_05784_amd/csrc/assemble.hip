@@ -37,7 +37,27 @@ struct IsArgs {
     double c, fs;
     int64_t L;
     uint64_t invalid;   // sort key of sources outside the IR (n_rcv * L)
+    // batched calls: global receiver row -> job -> scene (materials, rays)
+    const int32_t* rcv_job;
+    const DevJob* jobs;
+    const DevScene* scenes;
 };
+
+// Material table view and ray count for image sources of receiver row m.
+struct MatView {
+    const int32_t* plane_mat;
+    int64_t n_tri;
+    int32_t mat_off;
+    int64_t n_rays;
+};
+__device__ inline MatView mat_view(const IsArgs& a, int32_t m) {
+    if (a.rcv_job) {
+        const DevJob& jb = a.jobs[a.rcv_job[m]];
+        const DevScene& sc = a.scenes[jb.scene];
+        return MatView{sc.plane_mat, sc.n_tri, sc.mat_off, jb.n_rays};
+    }
+    return MatView{a.plane_mat, a.n_tri, 0, a.n_rays};
+}
 
 __device__ inline int64_t is_count_of(const IsArgs& a) {
     int64_t n = *a.n_is;
@@ -53,16 +73,17 @@ __global__ void k_is_energy(IsArgs a, double* __restrict__ E, uint64_t* __restri
         const int32_t m = row[0], k = row[1];
         const double d = a.dist[i];
         double e[8];
-        const double base = (double)a.count[i] / (double)a.n_rays;
-        for (int b = 0; b < 8; b++) e[b] = base * exp(-(double)a.beta[b] * d);
         bool ok = m >= 0 && m < a.n_rcv && k >= 0 && k < a.R1;
+        const MatView mv = mat_view(a, ok ? m : 0);
+        const double base = (double)a.count[i] / (double)mv.n_rays;
+        for (int b = 0; b < 8; b++) e[b] = base * exp(-(double)a.beta[b] * d);
         for (int j = 0; ok && j < k; j++) {
             const int32_t p = row[2 + j];
-            if (p < 0 || p >= a.n_tri) {
+            if (p < 0 || p >= mv.n_tri) {
                 ok = false;
                 break;
             }
-            const int32_t mat = a.plane_mat[p];
+            const int32_t mat = mv.mat_off + mv.plane_mat[p];
             for (int b = 0; b < 8; b++) e[b] *= 1.0 - (double)a.alpha[8 * mat + b];
         }
         for (int b = 0; b < 8; b++) E[8 * i + b] = e[b];
@@ -204,30 +225,32 @@ __global__ void __launch_bounds__(kAdjThreads) k_adjoint_partial(IsArgs a, int32
     const int32_t* row = ok ? a.key + i * (int64_t)(a.R1 + 1) : nullptr;
     int32_t m = 0, k = 0;
     double base[8];
+    MatView mv{a.plane_mat, a.n_tri, 0, a.n_rays};
     if (ok) {
         m = row[0];
         k = row[1];
         ok = m >= 0 && m < a.n_rcv && k >= 0 && k < a.R1;
+        if (ok) mv = mat_view(a, m);
         const double d = a.dist[i];
         const double sb = floor(d * a.fs / a.c);
         ok = ok && sb >= 0.0 && sb < (double)a.L;
-        for (int j = 0; ok && j < k; j++) ok = row[2 + j] >= 0 && row[2 + j] < a.n_tri;
+        for (int j = 0; ok && j < k; j++) ok = row[2 + j] >= 0 && row[2 + j] < mv.n_tri;
         for (int b = 0; b < 8; b++)
-            base[b] = ok ? (double)a.count[i] / (double)a.n_rays * exp(-(double)a.beta[b] * d) * (double)g[8 * m + b]
+            base[b] = ok ? (double)a.count[i] / (double)mv.n_rays * exp(-(double)a.beta[b] * d) * (double)g[8 * m + b]
                          : 0.0;
     }
     for (int mat = 0; mat < n_mat; mat++) {
         double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         if (ok) {
             int cm = 0;
-            for (int j = 0; j < k; j++) cm += a.plane_mat[row[2 + j]] == mat;
+            for (int j = 0; j < k; j++) cm += mv.mat_off + mv.plane_mat[row[2 + j]] == mat;
             if (cm > 0) {
                 for (int b = 0; b < 8; b++) {
                     const double om = 1.0 - (double)a.alpha[8 * mat + b];
                     double dv = -(double)cm;
                     for (int e = 0; e < cm - 1; e++) dv *= om;
                     for (int j = 0; j < k; j++) {
-                        const int32_t mt = a.plane_mat[row[2 + j]];
+                        const int32_t mt = mv.mat_off + mv.plane_mat[row[2 + j]];
                         if (mt != mat) dv *= 1.0 - (double)a.alpha[8 * mt + b];
                     }
                     v[b] = base[b] * dv;
@@ -301,6 +324,9 @@ IsArgs make_is_args(const rt_scene* s, const int32_t* is_key, const int32_t* is_
     a.fs = fs;
     a.L = L;
     a.invalid = (uint64_t)n_rcv * (uint64_t)L;
+    a.rcv_job = nullptr;
+    a.jobs = nullptr;
+    a.scenes = nullptr;
     return a;
 }
 
@@ -310,13 +336,15 @@ IsArgs make_is_args(const rt_scene* s, const int32_t* is_key, const int32_t* is_
 
 using namespace rtac;
 
-extern "C" int rt_assemble_ir(const rt_scene* scene, const int32_t* is_key, const int32_t* is_count,
-                              const double* is_dist, const int64_t* n_is, int64_t is_cap, int32_t max_reflections,
-                              int64_t n_rays, int32_t n_rcv, const float* alpha, const float* beta, float c, float fs,
-                              int64_t L, const float* fir, int32_t K, float* band_energy, float* hist, float* band_ir,
-                              float* ir, void* stream) {
-    int rc = check_is_args(scene, is_key, is_count, is_dist, n_is, is_cap, max_reflections, n_rays, n_rcv, alpha,
-                           beta, c, fs, L);
+namespace rtac {
+namespace {
+int assemble_common(const rt_scene* scene, const rt_batch* bt, const int32_t* is_key, const int32_t* is_count,
+                    const double* is_dist, const int64_t* n_is, int64_t is_cap, int32_t max_reflections,
+                    int64_t n_rays, int32_t n_rcv, const float* alpha, const float* beta, float c, float fs,
+                    int64_t L, const float* fir, int32_t K, float* band_energy, float* hist, float* band_ir,
+                    float* ir, void* stream) {
+    int rc = check_is_args(scene, is_key, is_count, is_dist, n_is, is_cap, max_reflections, n_rays, bt ? 1 : n_rcv,
+                           alpha, beta, c, fs, L);
     if (rc) {
         set_error("rt_assemble_ir: %s", rt_last_error());
         return rc;
@@ -333,6 +361,11 @@ extern "C" int rt_assemble_ir(const rt_scene* scene, const int32_t* is_key, cons
         return RT_ENOMEM;
     IsArgs a = make_is_args(scene, is_key, is_count, is_dist, n_is, is_cap, max_reflections, n_rays, n_rcv, alpha,
                             beta, c, fs, L);
+    if (bt) {
+        a.rcv_job = bt->rcv_job;
+        a.jobs = bt->jobs;
+        a.scenes = bt->scenes;
+    }
     double* E = ws.asm_energy.as<double>();
     uint64_t* k0 = ws.sort_keys[0].as<uint64_t>();
     uint64_t* k1 = ws.sort_keys[1].as<uint64_t>();
@@ -365,21 +398,42 @@ extern "C" int rt_assemble_ir(const rt_scene* scene, const int32_t* is_key, cons
     RT_HIP(hipGetLastError());
     return RT_OK;
 }
+}  // namespace
+}  // namespace rtac
 
-extern "C" int rt_band_energy_adjoint(const rt_scene* scene, const int32_t* is_key, const int32_t* is_count,
-                                      const double* is_dist, const int64_t* n_is, int64_t is_cap,
-                                      int32_t max_reflections, int64_t n_rays, int32_t n_rcv, const float* alpha,
-                                      int32_t n_mat, const float* beta, float c, float fs, int64_t L,
-                                      const float* grad_band_energy, float* grad_alpha, void* stream) {
-    int rc = check_is_args(scene, is_key, is_count, is_dist, n_is, is_cap, max_reflections, n_rays, n_rcv, alpha,
-                           beta, c, fs, L);
+extern "C" int rt_assemble_ir(const rt_scene* scene, const int32_t* is_key, const int32_t* is_count,
+                              const double* is_dist, const int64_t* n_is, int64_t is_cap, int32_t max_reflections,
+                              int64_t n_rays, int32_t n_rcv, const float* alpha, const float* beta, float c, float fs,
+                              int64_t L, const float* fir, int32_t K, float* band_energy, float* hist, float* band_ir,
+                              float* ir, void* stream) {
+    return assemble_common(scene, nullptr, is_key, is_count, is_dist, n_is, is_cap, max_reflections, n_rays, n_rcv,
+                           alpha, beta, c, fs, L, fir, K, band_energy, hist, band_ir, ir, stream);
+}
+
+extern "C" int rt_assemble_batch(rt_batch* b, const int32_t* is_key, const int32_t* is_count, const double* is_dist,
+                                 const int64_t* n_is, int64_t is_cap, int32_t max_reflections, const float* alpha,
+                                 const float* beta, float c, float fs, int64_t L, const float* fir, int32_t K,
+                                 float* band_energy, float* hist, float* band_ir, float* ir, void* stream) {
+    RT_CHECK(b, RT_EINVAL, "rt_assemble_batch: null batch");
+    return assemble_common(b->ws_owner, b, is_key, is_count, is_dist, n_is, is_cap, max_reflections, b->n_rays,
+                           b->n_rcv, alpha, beta, c, fs, L, fir, K, band_energy, hist, band_ir, ir, stream);
+}
+
+namespace rtac {
+namespace {
+int adjoint_common(const rt_scene* scene, const rt_batch* bt, const int32_t* is_key, const int32_t* is_count,
+                   const double* is_dist, const int64_t* n_is, int64_t is_cap, int32_t max_reflections,
+                   int64_t n_rays, int32_t n_rcv, const float* alpha, int32_t n_mat, const float* beta, float c,
+                   float fs, int64_t L, const float* grad_band_energy, float* grad_alpha, void* stream) {
+    int rc = check_is_args(scene, is_key, is_count, is_dist, n_is, is_cap, max_reflections, n_rays, bt ? 1 : n_rcv,
+                           alpha, beta, c, fs, L);
     if (rc) {
         set_error("rt_band_energy_adjoint: %s", rt_last_error());
         return rc;
     }
     RT_CHECK(grad_band_energy && grad_alpha, RT_EINVAL, "rt_band_energy_adjoint: null gradient buffer");
-    RT_CHECK(n_mat >= scene->n_mat && n_mat <= 4096, RT_EINVAL,
-             "rt_band_energy_adjoint: n_mat must cover the scene's materials (%d)", scene->n_mat);
+    RT_CHECK(n_mat >= (bt ? bt->n_mat : scene->n_mat) && n_mat <= 4096, RT_EINVAL,
+             "rt_band_energy_adjoint: n_mat must cover the materials (%d)", bt ? bt->n_mat : scene->n_mat);
     hipStream_t st = (hipStream_t)stream;
     rt_scene* s = const_cast<rt_scene*>(scene);
     const int64_t cap = is_cap > 0 ? is_cap : 1;
@@ -387,10 +441,35 @@ extern "C" int rt_band_energy_adjoint(const rt_scene* scene, const int32_t* is_k
     if (s->ws.asm_partial.ensure(sizeof(double) * (size_t)nb * n_mat * 8)) return RT_ENOMEM;
     IsArgs a = make_is_args(scene, is_key, is_count, is_dist, n_is, is_cap, max_reflections, n_rays, n_rcv, alpha,
                             beta, c, fs, L);
+    if (bt) {
+        a.rcv_job = bt->rcv_job;
+        a.jobs = bt->jobs;
+        a.scenes = bt->scenes;
+    }
     double* part = s->ws.asm_partial.as<double>();
     hipLaunchKernelGGL(k_adjoint_partial, dim3(nb), dim3(kAdjThreads), 0, st, a, n_mat, grad_band_energy, part);
     hipLaunchKernelGGL(k_adjoint_final, dim3(nblk(n_mat * 8)), dim3(256), 0, st, part, nb, n_mat, n_is, is_cap,
                        grad_alpha);
     RT_HIP(hipGetLastError());
     return RT_OK;
+}
+}  // namespace
+}  // namespace rtac
+
+extern "C" int rt_band_energy_adjoint(const rt_scene* scene, const int32_t* is_key, const int32_t* is_count,
+                                      const double* is_dist, const int64_t* n_is, int64_t is_cap,
+                                      int32_t max_reflections, int64_t n_rays, int32_t n_rcv, const float* alpha,
+                                      int32_t n_mat, const float* beta, float c, float fs, int64_t L,
+                                      const float* grad_band_energy, float* grad_alpha, void* stream) {
+    return adjoint_common(scene, nullptr, is_key, is_count, is_dist, n_is, is_cap, max_reflections, n_rays, n_rcv,
+                          alpha, n_mat, beta, c, fs, L, grad_band_energy, grad_alpha, stream);
+}
+
+extern "C" int rt_adjoint_batch(rt_batch* b, const int32_t* is_key, const int32_t* is_count, const double* is_dist,
+                                const int64_t* n_is, int64_t is_cap, int32_t max_reflections, const float* alpha,
+                                const float* beta, float c, float fs, int64_t L, const float* grad_band_energy,
+                                float* grad_alpha, void* stream) {
+    RT_CHECK(b, RT_EINVAL, "rt_adjoint_batch: null batch");
+    return adjoint_common(b->ws_owner, b, is_key, is_count, is_dist, n_is, is_cap, max_reflections, b->n_rays,
+                          b->n_rcv, alpha, b->n_mat, beta, c, fs, L, grad_band_energy, grad_alpha, stream);
 }

@@ -36,6 +36,10 @@ struct CollectArgs {
     int32_t n_rcv;
     const int32_t* tri_plane;
     int64_t n_tri;
+    // batched calls: global receiver row -> job -> scene
+    const int32_t* rcv_job;
+    const DevJob* jobs;
+    const DevScene* scenes;
 };
 
 __device__ inline int64_t det_count(const CollectArgs& a) {
@@ -52,8 +56,14 @@ __device__ inline bool det_row(const CollectArgs& a, int64_t i, int32_t& ray, in
     return ray >= 0 && ray < a.n_rays && k >= 0 && k < a.R1 && m >= 0 && m < a.n_rcv;
 }
 
-__device__ inline int32_t plane_at(const CollectArgs& a, int32_t ray, int32_t j) {
+// Plane id of the triangle ending segment j of the ray, in the scene of
+// receiver row m (batched calls) or of the call.
+__device__ inline int32_t plane_at(const CollectArgs& a, int32_t m, int32_t ray, int32_t j) {
     const int32_t t = a.hit_seq[(int64_t)ray * a.R1 + j];
+    if (a.rcv_job) {
+        const DevScene& sc = a.scenes[a.jobs[a.rcv_job[m]].scene];
+        return (t >= 0 && t < sc.n_tri) ? sc.tri_plane[t] : -1;
+    }
     return (t >= 0 && t < a.n_tri) ? a.tri_plane[t] : -1;
 }
 
@@ -68,7 +78,7 @@ __global__ void k_hash(CollectArgs a, uint64_t mask, uint64_t* __restrict__ hash
         }
         uint64_t h = mix64(0x9E3779B97F4A7C15ull ^ ((uint64_t)(uint32_t)m << 32 | (uint32_t)k));
         for (int j = 0; j < k; j++) {
-            const int32_t p = plane_at(a, ray, j);
+            const int32_t p = plane_at(a, m, ray, j);
             if (p < 0) atomicOr(err, 2u);
             h = mix64(h + 0x632BE59BD9B4E019ull * (uint64_t)(uint32_t)(p + 1));
         }
@@ -84,7 +94,7 @@ __device__ inline int key_cmp(const CollectArgs& a, uint32_t x, uint32_t y) {
     if (mx != my) return mx < my ? -1 : 1;
     if (kx != ky) return kx < ky ? -1 : 1;
     for (int j = 0; j < kx; j++) {
-        const int32_t px = plane_at(a, rx, j), py = plane_at(a, ry, j);
+        const int32_t px = plane_at(a, mx, rx, j), py = plane_at(a, my, ry, j);
         if (px != py) return px < py ? -1 : 1;
     }
     return 0;
@@ -187,13 +197,23 @@ __device__ void emit_one(const CollectArgs& a, const EmitArgs& e, const uint32_t
     row[0] = m;
     row[1] = k;
     double x = e.src[0], y = e.src[1], z = e.src[2];
+    const double* pn = e.pn;
+    const double* pp = e.pp;
+    if (a.rcv_job) {
+        const DevJob& jb = a.jobs[a.rcv_job[m]];
+        x = jb.src[0];
+        y = jb.src[1];
+        z = jb.src[2];
+        pn = a.scenes[jb.scene].plane_n;
+        pp = a.scenes[jb.scene].plane_p;
+    }
     for (int j = 0; j < k; j++) {
-        const int32_t p = plane_at(a, ray, j);
+        const int32_t p = plane_at(a, m, ray, j);
         row[2 + j] = p;
         if (p < 0) continue;
-        const double nx = e.pn[3 * (int64_t)p], ny = e.pn[3 * (int64_t)p + 1], nz = e.pn[3 * (int64_t)p + 2];
-        const double h = (x - e.pp[3 * (int64_t)p]) * nx + (y - e.pp[3 * (int64_t)p + 1]) * ny +
-                         (z - e.pp[3 * (int64_t)p + 2]) * nz;
+        const double nx = pn[3 * (int64_t)p], ny = pn[3 * (int64_t)p + 1], nz = pn[3 * (int64_t)p + 2];
+        const double h = (x - pp[3 * (int64_t)p]) * nx + (y - pp[3 * (int64_t)p + 1]) * ny +
+                         (z - pp[3 * (int64_t)p + 2]) * nz;
         x -= 2.0 * h * nx;
         y -= 2.0 * h * ny;
         z -= 2.0 * h * nz;
@@ -231,22 +251,22 @@ extern "C" int rt_debug_set_hash_bits(int bits) {
     return RT_OK;
 }
 
-extern "C" int rt_collect_image_sources(const rt_scene* scene, const float* src_host, const float* rcv, int32_t n_rcv,
-                                        const int32_t* hit_seq, int64_t n_rays, int32_t max_reflections,
-                                        const int32_t* det, int64_t det_cap, const int64_t* n_det, int32_t* is_key,
-                                        int32_t* is_count, double* is_pos, double* is_dist, int64_t is_cap,
-                                        int64_t* n_is, void* stream) {
-    RT_CHECK(scene && src_host && n_det && n_is, RT_EINVAL, "rt_collect_image_sources: null argument");
+namespace rtac {
+namespace {
+int collect_common(rt_scene* s, const rt_batch* b, const float* src_host, const float* rcv, int32_t n_rcv,
+                   const int32_t* hit_seq, int64_t n_rays, int32_t max_reflections, const int32_t* det,
+                   int64_t det_cap, const int64_t* n_det, int32_t* is_key, int32_t* is_count, double* is_pos,
+                   double* is_dist, int64_t is_cap, int64_t* n_is, void* stream) {
+    RT_CHECK(s && src_host && n_det && n_is, RT_EINVAL, "rt_collect_image_sources: null argument");
     RT_CHECK(max_reflections >= 0 && max_reflections < 4096, RT_EINVAL,
              "rt_collect_image_sources: max_reflections out of range");
-    RT_CHECK(n_rcv >= 1 && n_rcv <= kMaxRcv && rcv, RT_EINVAL, "rt_collect_image_sources: bad receivers");
+    RT_CHECK(n_rcv >= 1 && (b || n_rcv <= kMaxRcv) && rcv, RT_EINVAL, "rt_collect_image_sources: bad receivers");
     RT_CHECK(det_cap >= 0 && (det_cap == 0 || (det && hit_seq)), RT_EINVAL,
              "rt_collect_image_sources: det/hit_seq is NULL");
     RT_CHECK(det_cap < ((int64_t)1 << 31), RT_EINVAL, "rt_collect_image_sources: det_cap must be < 2^31");
     RT_CHECK(is_cap >= 0 && (is_cap == 0 || (is_key && is_count && is_pos && is_dist)), RT_EINVAL,
              "rt_collect_image_sources: null output");
     hipStream_t st = (hipStream_t)stream;
-    rt_scene* s = const_cast<rt_scene*>(scene);
     Workspace& ws = s->ws;
     const int64_t cap = det_cap > 0 ? det_cap : 1;
     if (ws.sort_keys[0].ensure(8 * cap) || ws.sort_keys[1].ensure(8 * cap) || ws.sort_vals[0].ensure(4 * cap) ||
@@ -263,6 +283,9 @@ extern "C" int rt_collect_image_sources(const rt_scene* scene, const float* src_
     a.n_rcv = n_rcv;
     a.tri_plane = s->tri_plane;
     a.n_tri = s->n_tri;
+    a.rcv_job = b ? b->rcv_job : nullptr;
+    a.jobs = b ? b->jobs : nullptr;
+    a.scenes = b ? b->scenes : nullptr;
     uint32_t* err = ws.coll_err.as<uint32_t>();
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, err, 4);
     const uint64_t mask = g_hash_bits >= 64 ? ~0ull : ((1ull << g_hash_bits) - 1ull);
@@ -300,4 +323,26 @@ extern "C" int rt_collect_image_sources(const rt_scene* scene, const float* src_
     hipLaunchKernelGGL(k_emit, dim3(nblk(cap)), dim3(256), 0, st, a, e, ix, hpos, n_is);
     RT_HIP(hipGetLastError());
     return RT_OK;
+}
+}  // namespace
+}  // namespace rtac
+
+extern "C" int rt_collect_image_sources(const rt_scene* scene, const float* src_host, const float* rcv, int32_t n_rcv,
+                                        const int32_t* hit_seq, int64_t n_rays, int32_t max_reflections,
+                                        const int32_t* det, int64_t det_cap, const int64_t* n_det, int32_t* is_key,
+                                        int32_t* is_count, double* is_pos, double* is_dist, int64_t is_cap,
+                                        int64_t* n_is, void* stream) {
+    return collect_common(const_cast<rt_scene*>(scene), nullptr, src_host, rcv, n_rcv, hit_seq, n_rays,
+                          max_reflections, det, det_cap, n_det, is_key, is_count, is_pos, is_dist, is_cap, n_is,
+                          stream);
+}
+
+extern "C" int rt_collect_batch(rt_batch* b, const float* rcv, const int32_t* hit_seq, int32_t max_reflections,
+                                const int32_t* det, int64_t det_cap, const int64_t* n_det, int32_t* is_key,
+                                int32_t* is_count, double* is_pos, double* is_dist, int64_t is_cap, int64_t* n_is,
+                                void* stream) {
+    RT_CHECK(b, RT_EINVAL, "rt_collect_batch: null batch");
+    const float zero[3] = {0.f, 0.f, 0.f};
+    return collect_common(b->ws_owner, b, zero, rcv, b->n_rcv, hit_seq, b->n_rays, max_reflections, det, det_cap,
+                          n_det, is_key, is_count, is_pos, is_dist, is_cap, n_is, stream);
 }

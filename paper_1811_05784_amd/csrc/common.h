@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <vector>
 
 #include "../../include/rtac.h"
 
@@ -72,7 +73,74 @@ struct Workspace {
     void release_all();
 };
 
+// Device-side view of one scene and of one job (a source with its rays and
+// receivers in one scene) for batched calls.
+struct DevScene {
+    const Node4* nodes;
+    const float4* tri;
+    const double* plane_n;
+    const double* plane_p;
+    const int32_t* plane_mat;
+    const int32_t* tri_plane;
+    int32_t n_nodes;
+    int32_t n_tri;
+    int32_t mat_off;   // first row of this scene's materials in a batch absorption table
+    int32_t n_mat;
+};
+
+struct DevJob {
+    int64_t ray_off;   // first global ray id
+    int64_t n_rays;
+    float src[3];
+    float max_len;
+    int32_t scene;
+    int32_t rcv_off;   // first global receiver row
+    int32_t n_rcv;
+    int32_t pad;
+};
+
+// Fibonacci sphere direction i of n: z = 1 - (2i+1)/n, phi = i pi (3 - sqrt5)
+// mod 2 pi, FP64 without contraction, rounded once.
+__device__ inline void fibonacci_dir(int64_t i, int64_t n, float* out) {
+#pragma clang fp contract(off)
+    const double pi = 3.14159265358979323846;
+    const double golden = pi * (3.0 - sqrt(5.0));
+    const double two_pi = 2.0 * pi;
+    const double z = 1.0 - (double)(2 * i + 1) / (double)n;
+    const double phi = fmod((double)i * golden, two_pi);
+    const double zz = z * z;
+    const double rho = sqrt(1.0 - zz);
+    const double x = rho * cos(phi);
+    const double y = rho * sin(phi);
+    out[0] = (float)x;
+    out[1] = (float)y;
+    out[2] = (float)z;
+}
+
+// Job of a global ray id (jobs hold contiguous ray ranges, ray_off ascending).
+__device__ inline int32_t job_of_ray(const DevJob* jobs, int32_t n_jobs, int64_t g) {
+    int32_t lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].ray_off <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 }  // namespace rtac
+
+struct rt_batch {
+    int device = 0;
+    int32_t n_scenes = 0, n_jobs = 0, n_rcv = 0, n_mat = 0;
+    int64_t n_rays = 0;
+    rtac::DevScene* scenes = nullptr;   // device
+    rtac::DevJob* jobs = nullptr;       // device
+    int32_t* rcv_job = nullptr;         // device, [n_rcv]
+    rt_scene* ws_owner = nullptr;       // scene whose workspace the batch uses
+    int32_t max_depth = 0;
+    int64_t max_steps = 0;
+};
 
 struct rt_scene {
     int device = 0;

@@ -36,6 +36,7 @@ struct TraceArgs {
     const Node4* nodes;
     const float4* tri;
     const double* plane_n;
+    const double* plane_p;
     int32_t n_nodes;
     int32_t n_tri;
     float src[3];
@@ -59,7 +60,7 @@ struct TraceArgs {
     int32_t spill_per_lane;
     int32_t fetch_thr;
     int32_t shade_thr;
-    int64_t max_steps;
+    int32_t max_steps;
     const uint32_t* order;          // pool index -> ray id (NULL: identity)
     unsigned long long* stats;      // NULL or [4]
     // continuation rounds: rays still in flight when the pool is empty and a
@@ -70,6 +71,10 @@ struct TraceArgs {
     int4* q_out;
     unsigned long long* q_out_count;
     int32_t spill_thr;
+    // batched calls: rays of many jobs (source + receivers in one scene)
+    const DevJob* jobs;
+    const DevScene* scenes;
+    int32_t n_jobs;
 };
 
 // queued ray: (ray, k, last plane, -) (o.x, o.y, o.z, L) (u.x, u.y, u.z, -)
@@ -192,20 +197,29 @@ __device__ inline void cswap(float& ta, int32_t& ra, float& tb, int32_t& rb) {
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_trace(TraceArgs a) {
+template <int kWavesPerEU, bool kBatch>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWavesPerEU, 8)))
+k_trace(TraceArgs a) {
     __shared__ int32_t lds_stack[kRing * kBlock];
     __shared__ double rcv_s[kMaxRcv][4];
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
-    if (tid < a.n_rcv * 4) rcv_s[tid >> 2][tid & 3] = (double)a.rcv[tid];
+    if (!kBatch && tid < a.n_rcv * 4) rcv_s[tid >> 2][tid & 3] = (double)a.rcv[tid];
     __syncthreads();
+    // scene seen by this lane's ray (uniform unless batched)
+    const Node4* nodes = a.nodes;
+    const float4* tri = a.tri;
+    const double* pl_n = a.plane_n;
+    const double* pl_p = a.plane_p;
+    int32_t n_nodes = a.n_nodes, n_tri = a.n_tri, rcv_off = 0, n_rcv = a.n_rcv;
+    float max_len = a.max_len;
 
     int32_t* spill = a.spill + ((int64_t)blockIdx.x * kBlock + tid) * a.spill_per_lane;
     const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
     const int R1 = a.R + 1;
 
     int status = kIdle;
-    int64_t ray = 0;
+    int32_t ray = 0;
     int k = 0;
     float L = 0.f;
     int32_t last_plane = -1;
@@ -216,9 +230,9 @@ __global__ void __launch_bounds__(kBlock) k_trace(TraceArgs a) {
     Stack st{0, 0, 0};
     float best_t = INFINITY;
     int32_t best_j = -1, best_id = 0x7FFFFFFF;
-    int64_t steps = 0;
-    unsigned long long n_query = 0, n_escape = 0;
-    unsigned long long st_nodes = 0, st_leaves = 0, st_tris = 0, st_spill = 0;
+    int32_t steps = 0;
+    uint32_t n_query = 0, n_escape = 0;
+    uint32_t st_nodes = 0, st_leaves = 0, st_tris = 0, st_spill = 0;
     const bool want_stats = a.stats != nullptr;
     const unsigned long long pool_n = a.q_in ? *a.q_in_count : (unsigned long long)a.n_rays;
     bool pool_empty = pool_n == 0;
@@ -236,7 +250,22 @@ __global__ void __launch_bounds__(kBlock) k_trace(TraceArgs a) {
             if (status == kIdle) {
                 const unsigned long long my = base + (unsigned long long)__popcll(idle & lt_mask);
                 if (my < pool_n) {
-                    if (a.q_in) {
+                    if (kBatch && !a.q_in) {
+                        const int64_t g = a.order ? (int64_t)a.order[my] : (int64_t)my;
+                        const DevJob& jb = a.jobs[job_of_ray(a.jobs, a.n_jobs, g)];
+                        float d[3];
+                        fibonacci_dir(g - jb.ray_off, jb.n_rays, d);
+                        ray = (int32_t)g;
+                        r.ox = jb.src[0];
+                        r.oy = jb.src[1];
+                        r.oz = jb.src[2];
+                        r.ux = d[0];
+                        r.uy = d[1];
+                        r.uz = d[2];
+                        L = 0.f;
+                        last_plane = -1;
+                        k = 0;
+                    } else if (a.q_in) {
                         const int4 e0 = a.q_in[3 * my], e1 = a.q_in[3 * my + 1], e2 = a.q_in[3 * my + 2];
                         ray = e0.x;
                         k = e0.y;
@@ -249,7 +278,7 @@ __global__ void __launch_bounds__(kBlock) k_trace(TraceArgs a) {
                         r.uy = __int_as_float(e2.y);
                         r.uz = __int_as_float(e2.z);
                     } else {
-                        ray = a.order ? (int64_t)a.order[my] : (int64_t)my;
+                        ray = a.order ? (int32_t)a.order[my] : (int32_t)my;
                         if (a.origins) {
                             r.ox = a.origins[3 * ray];
                             r.oy = a.origins[3 * ray + 1];
@@ -265,6 +294,19 @@ __global__ void __launch_bounds__(kBlock) k_trace(TraceArgs a) {
                         L = a.start_len ? a.start_len[ray] : 0.f;
                         last_plane = a.start_plane ? a.start_plane[ray] : -1;
                         k = 0;
+                    }
+                    if (kBatch) {
+                        const DevJob& jb = a.jobs[job_of_ray(a.jobs, a.n_jobs, ray)];
+                        const DevScene& sc = a.scenes[jb.scene];
+                        nodes = sc.nodes;
+                        tri = sc.tri;
+                        pl_n = sc.plane_n;
+                        pl_p = sc.plane_p;
+                        n_nodes = sc.n_nodes;
+                        n_tri = sc.n_tri;
+                        rcv_off = jb.rcv_off;
+                        n_rcv = jb.n_rcv;
+                        max_len = jb.max_len;
                     }
                     setup_ray(r);
                     cur = 0;
@@ -320,20 +362,21 @@ __global__ void __launch_bounds__(kBlock) k_trace(TraceArgs a) {
                 status = kDone;
                 continue;
             }
-            if (cur >= 0) {
-                if (want_stats) st_nodes++;
-                if (cur >= a.n_nodes) {
-                    atomicOr(&a.counters[3], kErrNode);
-                    best_j = -1;
-                    status = kDone;
-                    continue;
-                }
-                const float4* np = reinterpret_cast<const float4*>(a.nodes + cur);
-                const float4 lx = np[0], hx = np[1], ly = np[2], hy = np[3], lz = np[4], hz = np[5];
-                const int4 ch = reinterpret_cast<const int4*>(np)[6];
-                const float tlim = best_t;
-                float tn[4];
-                int32_t rf[4];
+            // every step visits one inner node; leaf children whose box is hit
+            // are tested on the spot, inner children are descended or pushed
+            if (cur < 0 || cur >= n_nodes) {
+                atomicOr(&a.counters[3], kErrNode);
+                best_j = -1;
+                status = kDone;
+                continue;
+            }
+            if (want_stats) st_nodes++;
+            const float4* np = reinterpret_cast<const float4*>(nodes + cur);
+            const float4 lx = np[0], hx = np[1], ly = np[2], hy = np[3], lz = np[4], hz = np[5];
+            const int4 ch = reinterpret_cast<const int4*>(np)[6];
+            const float tlim = best_t;
+            float tn[4];
+            int32_t rf[4];
 #define RT_SLAB(S, LX, HX, LY, HY, LZ, HZ, CH)                                          \
     {                                                                                    \
         const float t0x = (LX - r.ox) * r.ix, t1x = (HX - r.ox) * r.ix;                  \
@@ -347,56 +390,72 @@ __global__ void __launch_bounds__(kBlock) k_trace(TraceArgs a) {
         tn[S] = h ? tmin : INFINITY;                                                     \
         rf[S] = CH;                                                                      \
     }
-                RT_SLAB(0, lx.x, hx.x, ly.x, hy.x, lz.x, hz.x, ch.x)
-                RT_SLAB(1, lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, ch.y)
-                RT_SLAB(2, lx.z, hx.z, ly.z, hy.z, lz.z, hz.z, ch.z)
-                RT_SLAB(3, lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, ch.w)
+            RT_SLAB(0, lx.x, hx.x, ly.x, hy.x, lz.x, hz.x, ch.x)
+            RT_SLAB(1, lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, ch.y)
+            RT_SLAB(2, lx.z, hx.z, ly.z, hy.z, lz.z, hz.z, ch.z)
+            RT_SLAB(3, lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, ch.w)
 #undef RT_SLAB
-                cswap(tn[0], rf[0], tn[1], rf[1]);
-                cswap(tn[2], rf[2], tn[3], rf[3]);
-                cswap(tn[0], rf[0], tn[2], rf[2]);
-                cswap(tn[1], rf[1], tn[3], rf[3]);
-                cswap(tn[1], rf[1], tn[2], rf[2]);
-                const int nh = (tn[0] < INFINITY) + (tn[1] < INFINITY) + (tn[2] < INFINITY) + (tn[3] < INFINITY);
-                bool ok = true;
-                if (want_stats && st.cnt + nh - 1 > kRing) st_spill++;
-                if (nh > 3) ok &= stack_push(st, lds_stack, spill, a.spill_per_lane, tid, rf[3]);
-                if (nh > 2) ok &= stack_push(st, lds_stack, spill, a.spill_per_lane, tid, rf[2]);
-                if (nh > 1) ok &= stack_push(st, lds_stack, spill, a.spill_per_lane, tid, rf[1]);
-                if (!ok) {
-                    atomicOr(&a.counters[3], kErrStack);
-                    best_j = -1;
-                    status = kDone;
-                    continue;
-                }
-                if (nh > 0)
-                    cur = rf[0];
-                else
-                    have = stack_pop(st, lds_stack, spill, tid, cur);
-            } else {
-                const int32_t first = leaf_first(cur), cnt = leaf_count(cur);
-                if (want_stats) {
-                    st_leaves++;
-                    st_tris += (unsigned long long)cnt;
-                }
-                if (first + cnt > a.n_tri) {
-                    atomicOr(&a.counters[3], kErrNode);
-                    best_j = -1;
-                    status = kDone;
-                    continue;
-                }
-                for (int i = 0; i < cnt; i++) {
-                    const int32_t j = first + i;
-                    const float4 v0 = a.tri[3 * j], v1 = a.tri[3 * j + 1], v2 = a.tri[3 * j + 2];
-                    if (__float_as_int(v0.w) == last_plane) continue;
-                    const float t = watertight(r, v0, v1, v2);
-                    const int32_t id = __float_as_int(v1.w);
-                    if (t > 0.f && (t < best_t || (t == best_t && id < best_id))) {
-                        best_t = t;
-                        best_j = j;
-                        best_id = id;
+            cswap(tn[0], rf[0], tn[1], rf[1]);
+            cswap(tn[2], rf[2], tn[3], rf[3]);
+            cswap(tn[0], rf[0], tn[2], rf[2]);
+            cswap(tn[1], rf[1], tn[3], rf[3]);
+            cswap(tn[1], rf[1], tn[2], rf[2]);
+            // leaves, near to far, each only while its box can still hold a nearer hit
+            uint32_t inner = 0;
+            bool bad = false;
+#pragma unroll
+            for (int sl = 0; sl < 4; sl++) {
+                if (tn[sl] < INFINITY) {
+                    if (rf[sl] >= 0) {
+                        inner |= 1u << sl;
+                    } else if (tn[sl] <= best_t) {
+                        const int32_t first = leaf_first(rf[sl]), cnt = leaf_count(rf[sl]);
+                        if (want_stats) {
+                            st_leaves++;
+                            st_tris += (uint32_t)cnt;
+                        }
+                        if (first + cnt > n_tri) {
+                            bad = true;
+                        } else {
+                            for (int i = 0; i < cnt; i++) {
+                                const int32_t j = first + i;
+                                const float4 v0 = tri[3 * j], v1 = tri[3 * j + 1], v2 = tri[3 * j + 2];
+                                if (__float_as_int(v0.w) == last_plane) continue;
+                                const float t = watertight(r, v0, v1, v2);
+                                const int32_t id = __float_as_int(v1.w);
+                                if (t > 0.f && (t < best_t || (t == best_t && id < best_id))) {
+                                    best_t = t;
+                                    best_j = j;
+                                    best_id = id;
+                                }
+                            }
+                        }
                     }
                 }
+            }
+            if (bad) {
+                atomicOr(&a.counters[3], kErrNode);
+                best_j = -1;
+                status = kDone;
+                continue;
+            }
+            // descend into the nearest inner child, push the others far to near
+            const int nearest = inner ? __ffs(inner) - 1 : -1;
+            bool ok = true;
+            if (want_stats && st.cnt + __popc(inner) - 1 > kRing) st_spill++;
+#pragma unroll
+            for (int sl = 3; sl >= 1; sl--)
+                if (((inner >> sl) & 1u) && sl != nearest)
+                    ok &= stack_push(st, lds_stack, spill, a.spill_per_lane, tid, rf[sl]);
+            if (!ok) {
+                atomicOr(&a.counters[3], kErrStack);
+                best_j = -1;
+                status = kDone;
+                continue;
+            }
+            if (nearest >= 0) {
+                cur = nearest == 0 ? rf[0] : nearest == 1 ? rf[1] : nearest == 2 ? rf[2] : rf[3];
+            } else {
                 have = stack_pop(st, lds_stack, spill, tid, cur);
             }
             if (!have) status = kDone;
@@ -411,27 +470,41 @@ __global__ void __launch_bounds__(kBlock) k_trace(TraceArgs a) {
         const double uu = ux * ux + uy * uy + uz * uz;
         if (shading) {
             if (best_j >= 0) {
-                const float4 v0 = a.tri[3 * best_j], v1 = a.tri[3 * best_j + 1], v2 = a.tri[3 * best_j + 2];
-                hit_plane = __float_as_int(v0.w);
-                hit_id = __float_as_int(v1.w);
-                const double e1x = (double)v1.x - v0.x, e1y = (double)v1.y - v0.y, e1z = (double)v1.z - v0.z;
-                const double e2x = (double)v2.x - v0.x, e2y = (double)v2.y - v0.y, e2z = (double)v2.z - v0.z;
-                const double nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
-                const double num = ((double)v0.x - ox) * nx + ((double)v0.y - oy) * ny + ((double)v0.z - oz) * nz;
+                // plane crossing of the chosen triangle in FP64 from its plane (unit
+                // normal and point of the plane id's representative)
+                hit_plane = __float_as_int(tri[3 * best_j].w);
+                hit_id = __float_as_int(tri[3 * best_j + 1].w);
+                const double* pn = pl_n + 3 * (int64_t)hit_plane;
+                const double* pp = pl_p + 3 * (int64_t)hit_plane;
+                const double nx = pn[0], ny = pn[1], nz = pn[2];
+                const double num = (pp[0] - ox) * nx + (pp[1] - oy) * ny + (pp[2] - oz) * nz;
                 const double den = ux * nx + uy * ny + uz * nz;
                 dl = num / den;
                 if (!(dl > 0.0)) dl = 0.0;
             }
             if (uu > 0.0) {
-                for (int m = 0; m < a.n_rcv; m++) {
-                    const double wx = rcv_s[m][0] - ox, wy = rcv_s[m][1] - oy, wz = rcv_s[m][2] - oz;
+                for (int m = 0; m < n_rcv; m++) {
+                    double cx, cy, cz, cr;
+                    if (kBatch) {
+                        const float* q = a.rcv + 4 * (int64_t)(rcv_off + m);
+                        cx = q[0];
+                        cy = q[1];
+                        cz = q[2];
+                        cr = q[3];
+                    } else {
+                        cx = rcv_s[m][0];
+                        cy = rcv_s[m][1];
+                        cz = rcv_s[m][2];
+                        cr = rcv_s[m][3];
+                    }
+                    const double wx = cx - ox, wy = cy - oy, wz = cz - oz;
                     double ts = (wx * ux + wy * uy + wz * uz) / uu;
                     if (ts < 0.0) ts = 0.0;
                     if (ts > dl) ts = dl;
-                    const double qx = ox + ts * ux - rcv_s[m][0];
-                    const double qy = oy + ts * uy - rcv_s[m][1];
-                    const double qz = oz + ts * uz - rcv_s[m][2];
-                    if (qx * qx + qy * qy + qz * qz <= rcv_s[m][3] * rcv_s[m][3]) dm |= 1u << m;
+                    const double qx = ox + ts * ux - cx;
+                    const double qy = oy + ts * uy - cy;
+                    const double qz = oz + ts * uz - cz;
+                    if (qx * qx + qy * qy + qz * qz <= cr * cr) dm |= 1u << m;
                 }
             }
         }
@@ -458,7 +531,7 @@ __global__ void __launch_bounds__(kBlock) k_trace(TraceArgs a) {
                         int32_t* d = a.det + 3 * pos;
                         d[0] = (int32_t)ray;
                         d[1] = k;
-                        d[2] = m;
+                        d[2] = rcv_off + m;
                     }
                     pos++;
                 }
@@ -466,10 +539,10 @@ __global__ void __launch_bounds__(kBlock) k_trace(TraceArgs a) {
         }
         if (shading) {
             n_query++;
-            int32_t* hs = a.hit_seq + ray * R1;
+            int32_t* hs = a.hit_seq + (int64_t)ray * R1;
             hs[k] = hit_id;
             if (a.record) {
-                float* sp = a.states + (ray * (R1 + 1) + k) * 8;
+                float* sp = a.states + ((int64_t)ray * (R1 + 1) + k) * 8;
                 sp[0] = r.ox;
                 sp[1] = r.oy;
                 sp[2] = r.oz;
@@ -483,8 +556,8 @@ __global__ void __launch_bounds__(kBlock) k_trace(TraceArgs a) {
             if (hit_id < 0) {
                 n_escape++;
             } else {
-                const double nx = a.plane_n[3 * (int64_t)hit_plane], ny = a.plane_n[3 * (int64_t)hit_plane + 1],
-                             nz = a.plane_n[3 * (int64_t)hit_plane + 2];
+                const double nx = pl_n[3 * (int64_t)hit_plane], ny = pl_n[3 * (int64_t)hit_plane + 1],
+                             nz = pl_n[3 * (int64_t)hit_plane + 2];
                 const double udn = ux * nx + uy * ny + uz * nz;
                 const double Ln = (double)L + dl * sqrt(uu);
                 r.ox = (float)(ox + dl * ux);
@@ -495,9 +568,9 @@ __global__ void __launch_bounds__(kBlock) k_trace(TraceArgs a) {
                 r.uz = (float)(uz - 2.0 * udn * nz);
                 L = (float)Ln;
                 last_plane = hit_plane;
-                stop = (k == a.R) || (a.max_len > 0.f && Ln >= (double)a.max_len);
+                stop = (k == a.R) || (max_len > 0.f && Ln >= (double)max_len);
                 if (a.record) {
-                    float* sp = a.states + (ray * (R1 + 1) + k + 1) * 8;
+                    float* sp = a.states + ((int64_t)ray * (R1 + 1) + k + 1) * 8;
                     sp[0] = r.ox;
                     sp[1] = r.oy;
                     sp[2] = r.oz;
@@ -535,13 +608,13 @@ __global__ void __launch_bounds__(kBlock) k_trace(TraceArgs a) {
         }
     }
     if (lane == 0) {
-        if (n_query) atomicAdd(&a.counters[1], n_query);
-        if (n_escape) atomicAdd(&a.counters[2], n_escape);
+        if (n_query) atomicAdd(&a.counters[1], (unsigned long long)n_query);
+        if (n_escape) atomicAdd(&a.counters[2], (unsigned long long)n_escape);
         if (want_stats) {
-            atomicAdd(&a.stats[0], st_nodes);
-            atomicAdd(&a.stats[1], st_leaves);
-            atomicAdd(&a.stats[2], st_tris);
-            atomicAdd(&a.stats[3], st_spill);
+            atomicAdd(&a.stats[0], (unsigned long long)st_nodes);
+            atomicAdd(&a.stats[1], (unsigned long long)st_leaves);
+            atomicAdd(&a.stats[2], (unsigned long long)st_tris);
+            atomicAdd(&a.stats[3], (unsigned long long)st_spill);
         }
     }
 }
@@ -616,21 +689,27 @@ __global__ void k_fill_rows_scalar(int32_t* __restrict__ p, int64_t n) {
 
 // Fibonacci sphere: z_i = 1 - (2i+1)/n, phi_i = i pi (3 - sqrt5) mod 2 pi.
 __global__ void k_fibonacci(int64_t n, float* __restrict__ out) {
-#pragma clang fp contract(off)
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const double pi = 3.14159265358979323846;
-    const double golden = pi * (3.0 - sqrt(5.0));
-    const double two_pi = 2.0 * pi;
-    const double z = 1.0 - (double)(2 * i + 1) / (double)n;
-    const double phi = fmod((double)i * golden, two_pi);
-    const double zz = z * z;
-    const double rho = sqrt(1.0 - zz);
-    const double x = rho * cos(phi);
-    const double y = rho * sin(phi);
-    out[3 * i + 0] = (float)x;
-    out[3 * i + 1] = (float)y;
-    out[3 * i + 2] = (float)z;
+    fibonacci_dir(i, n, out + 3 * i);
+}
+
+void launch_trace(int occ, bool batch, unsigned nblk, hipStream_t st, const TraceArgs& a) {
+    if (batch) {
+        switch (occ) {
+            case 8: hipLaunchKernelGGL((k_trace<8, true>), dim3(nblk), dim3(kBlock), 0, st, a); break;
+            case 6: hipLaunchKernelGGL((k_trace<6, true>), dim3(nblk), dim3(kBlock), 0, st, a); break;
+            case 5: hipLaunchKernelGGL((k_trace<5, true>), dim3(nblk), dim3(kBlock), 0, st, a); break;
+            default: hipLaunchKernelGGL((k_trace<4, true>), dim3(nblk), dim3(kBlock), 0, st, a); break;
+        }
+    } else {
+        switch (occ) {
+            case 8: hipLaunchKernelGGL((k_trace<8, false>), dim3(nblk), dim3(kBlock), 0, st, a); break;
+            case 6: hipLaunchKernelGGL((k_trace<6, false>), dim3(nblk), dim3(kBlock), 0, st, a); break;
+            case 5: hipLaunchKernelGGL((k_trace<5, false>), dim3(nblk), dim3(kBlock), 0, st, a); break;
+            default: hipLaunchKernelGGL((k_trace<4, false>), dim3(nblk), dim3(kBlock), 0, st, a); break;
+        }
+    }
 }
 
 }  // namespace
@@ -648,14 +727,96 @@ extern "C" int rt_fibonacci_directions(int64_t n, float* dirs, void* stream) {
     return RT_OK;
 }
 
+namespace rtac {
+namespace {
+
+// Shared host part of the single-scene and batched traces: ray order, row
+// fill, launches.  `ws` is the scene whose workspace holds the scratch.
+int run_trace(rt_scene* ws, TraceArgs& a, const rt_trace_params* p, int depth, int64_t max_steps, int64_t n_rays,
+              int32_t* hit_seq, const float* dirs, const float* origins, const float* bounds, hipStream_t st) {
+    const int occ = p->waves_per_simd == 5 || p->waves_per_simd == 6 || p->waves_per_simd == 8 ? p->waves_per_simd : 4;
+    const int bpc = p->blocks_per_cu > 0 ? p->blocks_per_cu : occ;
+    int64_t nblk = (int64_t)device_sm_count() * bpc;
+    const int64_t need = (n_rays + kBlock - 1) / kBlock;
+    if (nblk > need) nblk = need;
+    if (nblk < 1) nblk = 1;
+    const int spill_n = ((3 * (depth + 1) + 2 * kSpillChunk) / kSpillChunk + 1) * kSpillChunk;
+    if (ws->ws.stack_spill.ensure(sizeof(int32_t) * (size_t)nblk * kBlock * spill_n)) return RT_ENOMEM;
+    a.spill = ws->ws.stack_spill.as<int32_t>();
+    a.spill_per_lane = spill_n;
+    a.fetch_thr = p->fetch_threshold > 0 ? p->fetch_threshold : 16;
+    a.shade_thr = p->shade_threshold > 0 ? p->shade_threshold : 16;
+    a.max_steps = max_steps > 0x7FFFFFFF ? 0x7FFFFFFF : (int32_t)max_steps;
+    a.order = nullptr;
+    a.stats = (unsigned long long*)p->stats;
+    if (!p->keep_order && n_rays > 1 && dirs) {
+        Workspace& w = ws->ws;
+        if (w.sort_keys[0].ensure(8 * n_rays) || w.sort_keys[1].ensure(8 * n_rays) ||
+            w.sort_vals[0].ensure(4 * n_rays) || w.sort_vals[1].ensure(4 * n_rays))
+            return RT_ENOMEM;
+        float ext = 0.f;
+        for (int c = 0; c < 3; c++) ext = fmaxf(ext, bounds[3 + c] - bounds[c]);
+        hipLaunchKernelGGL(k_ray_keys, dim3((unsigned)((n_rays + 255) / 256)), dim3(256), 0, st, dirs, origins,
+                           n_rays, bounds[0], bounds[1], bounds[2], ext > 0.f ? 1.f / ext : 0.f,
+                           w.sort_keys[0].as<uint64_t>());
+        int which = 0;
+        int rc = radix_sort_pairs(w, w.sort_keys[0].as<uint64_t>(), w.sort_vals[0].as<uint32_t>(),
+                                  w.sort_keys[1].as<uint64_t>(), w.sort_vals[1].as<uint32_t>(), n_rays, nullptr, 0,
+                                  origins ? 64 : 32, st, &which, true);
+        if (rc) return rc;
+        a.order = which ? w.sort_vals[1].as<uint32_t>() : w.sort_vals[0].as<uint32_t>();
+    }
+    {
+        const int64_t cells = n_rays * (int64_t)(p->max_reflections + 1);
+        int64_t fb = (cells / 4 + 255) / 256;
+        const int64_t fcap = (int64_t)device_sm_count() * 16;
+        if (fb > fcap) fb = fcap;
+        if (fb < 1) fb = 1;
+        if (((uintptr_t)hit_seq & 15u) == 0) {
+            hipLaunchKernelGGL(k_fill_rows, dim3((unsigned)fb), dim3(256), 0, st, hit_seq, cells);
+        } else {
+            hipLaunchKernelGGL(k_fill_rows_scalar, dim3((unsigned)fb), dim3(256), 0, st, hit_seq, cells);
+        }
+    }
+    // continuation rounds: launch rd takes the rays left over by launch rd-1;
+    // every launch hands over at most one ray per lane, so a queue of one
+    // entry per lane of the grid never overflows
+    const int rounds = p->rounds > 0 ? (p->rounds < 16 ? p->rounds : 16) : 1;
+    const int64_t lanes = nblk * kBlock;
+    if (ws->ws.generic[0].ensure(sizeof(int32_t) * kQueueInts * (size_t)lanes * 2)) return RT_ENOMEM;
+    int4* qbuf[2] = {ws->ws.generic[0].as<int4>(), ws->ws.generic[0].as<int4>() + 3 * lanes};
+    a.spill_thr = p->spill_threshold > 0 ? p->spill_threshold : 24;
+    unsigned long long* pool = a.pool;
+    for (int rd = 0; rd < rounds; rd++) {
+        a.pool = pool + rd;
+        a.q_in = rd == 0 ? nullptr : qbuf[(rd - 1) & 1];
+        a.q_in_count = rd == 0 ? nullptr : pool + 16 + (rd - 1);
+        a.q_out = rd + 1 < rounds ? qbuf[rd & 1] : nullptr;
+        a.q_out_count = pool + 16 + rd;
+        if (rd > 0) a.order = nullptr;
+        launch_trace(occ, a.jobs != nullptr, (unsigned)nblk, st, a);
+    }
+    RT_HIP(hipGetLastError());
+    return RT_OK;
+}
+
+int check_params(const rt_trace_params* p) {
+    RT_CHECK(p, RT_EINVAL, "null params");
+    RT_CHECK(p->max_reflections >= 0 && p->max_reflections < 4096, RT_EINVAL,
+             "max_reflections must be in [0, 4096)");
+    return RT_OK;
+}
+
+}  // namespace
+}  // namespace rtac
+
 extern "C" int rt_trace_rays(const rt_scene* scene, const float* src_host, const float* origins, const float* dirs,
                              const int32_t* start_plane, const float* start_len, int64_t n_rays, const float* rcv,
                              int32_t n_rcv, const rt_trace_params* p, int32_t* hit_seq, int32_t* det, int64_t det_cap,
                              int64_t* counters, float* states, void* stream) {
     RT_CHECK(scene && p, RT_EINVAL, "rt_trace_rays: null scene or params");
     RT_CHECK(n_rays >= 0 && n_rays < ((int64_t)1 << 31), RT_EINVAL, "rt_trace_rays: n_rays out of range");
-    RT_CHECK(p->max_reflections >= 0 && p->max_reflections < 4096, RT_EINVAL,
-             "rt_trace_rays: max_reflections must be in [0, 4096)");
+    if (check_params(p)) return RT_EINVAL;
     RT_CHECK(n_rcv >= 0 && n_rcv <= kMaxRcv, RT_EINVAL, "rt_trace_rays: n_rcv must be in [0, %d]", kMaxRcv);
     RT_CHECK(n_rcv == 0 || rcv, RT_EINVAL, "rt_trace_rays: rcv is NULL");
     RT_CHECK(counters, RT_EINVAL, "rt_trace_rays: counters is NULL");
@@ -673,17 +834,11 @@ extern "C" int rt_trace_rays(const rt_scene* scene, const float* src_host, const
         RT_HIP(hipGetLastError());
         return RT_OK;
     }
-    const int bpc = p->blocks_per_cu > 0 ? p->blocks_per_cu : 4;
-    int64_t nblk = (int64_t)device_sm_count() * bpc;
-    const int64_t need = (n_rays + kBlock - 1) / kBlock;
-    if (nblk > need) nblk = need;
-    if (nblk < 1) nblk = 1;
-    const int spill_n = ((3 * (s->depth + 1) + 2 * kSpillChunk) / kSpillChunk + 1) * kSpillChunk;
-    if (s->ws.stack_spill.ensure(sizeof(int32_t) * (size_t)nblk * kBlock * spill_n)) return RT_ENOMEM;
-    TraceArgs a;
+    TraceArgs a{};
     a.nodes = s->nodes;
     a.tri = s->tri_rec;
     a.plane_n = s->plane_n;
+    a.plane_p = s->plane_p;
     a.n_nodes = s->n_nodes;
     a.n_tri = (int32_t)s->n_tri;
     a.src[0] = src_host ? src_host[0] : 0.f;
@@ -705,59 +860,129 @@ extern "C" int rt_trace_rays(const rt_scene* scene, const float* src_host, const
     a.counters = (unsigned long long*)counters;
     a.pool = pool;
     a.states = states;
-    a.spill = s->ws.stack_spill.as<int32_t>();
-    a.spill_per_lane = spill_n;
-    a.fetch_thr = p->fetch_threshold > 0 ? p->fetch_threshold : 16;
-    a.shade_thr = p->shade_threshold > 0 ? p->shade_threshold : 16;
-    a.max_steps = 8 * ((int64_t)s->n_nodes + s->n_tri) + 4096;
-    a.order = nullptr;
-    a.stats = (unsigned long long*)p->stats;
-    if (!p->keep_order && n_rays > 1) {
-        Workspace& ws = s->ws;
-        if (ws.sort_keys[0].ensure(8 * n_rays) || ws.sort_keys[1].ensure(8 * n_rays) ||
-            ws.sort_vals[0].ensure(4 * n_rays) || ws.sort_vals[1].ensure(4 * n_rays))
-            return RT_ENOMEM;
-        float ext = 0.f;
-        for (int c = 0; c < 3; c++) ext = fmaxf(ext, s->bounds[3 + c] - s->bounds[c]);
-        hipLaunchKernelGGL(k_ray_keys, dim3((unsigned)((n_rays + 255) / 256)), dim3(256), 0, st, dirs, origins,
-                           n_rays, s->bounds[0], s->bounds[1], s->bounds[2], ext > 0.f ? 1.f / ext : 0.f,
-                           ws.sort_keys[0].as<uint64_t>());
-        int which = 0;
-        int rc = radix_sort_pairs(ws, ws.sort_keys[0].as<uint64_t>(), ws.sort_vals[0].as<uint32_t>(),
-                                  ws.sort_keys[1].as<uint64_t>(), ws.sort_vals[1].as<uint32_t>(), n_rays, nullptr, 0,
-                                  origins ? 64 : 32, st, &which, true);
-        if (rc) return rc;
-        a.order = which ? ws.sort_vals[1].as<uint32_t>() : ws.sort_vals[0].as<uint32_t>();
+    a.jobs = nullptr;
+    a.scenes = nullptr;
+    a.n_jobs = 0;
+    return run_trace(s, a, p, s->depth, 8 * ((int64_t)s->n_nodes + s->n_tri) + 4096, n_rays, hit_seq, dirs,
+                     origins, s->bounds, st);
+}
+
+// ---------------------------------------------------------------------------
+// batches of jobs over several scenes
+// ---------------------------------------------------------------------------
+
+extern "C" int rt_batch_create(const rt_scene* const* scenes, int32_t n_scenes, const rt_job* jobs, int32_t n_jobs,
+                               void* stream, rt_batch** out) {
+    RT_CHECK(out, RT_EINVAL, "rt_batch_create: out is NULL");
+    *out = nullptr;
+    RT_CHECK(scenes && jobs && n_scenes >= 1 && n_jobs >= 1, RT_EINVAL, "rt_batch_create: empty batch");
+    std::vector<DevScene> hs(n_scenes);
+    int32_t mat_off = 0;
+    for (int i = 0; i < n_scenes; i++) {
+        const rt_scene* s = scenes[i];
+        RT_CHECK(s, RT_EINVAL, "rt_batch_create: scene %d is NULL", i);
+        hs[i] = DevScene{s->nodes, s->tri_rec, s->plane_n, s->plane_p, s->plane_mat, s->tri_plane, s->n_nodes,
+                         (int32_t)s->n_tri, mat_off, s->n_mat};
+        mat_off += s->n_mat;
     }
-    {
-        const int64_t cells = n_rays * (int64_t)(p->max_reflections + 1);
-        int64_t fb = (cells / 4 + 255) / 256;
-        const int64_t fcap = (int64_t)device_sm_count() * 16;
-        if (fb > fcap) fb = fcap;
-        if (fb < 1) fb = 1;
-        if (((uintptr_t)hit_seq & 15u) == 0) {
-            hipLaunchKernelGGL(k_fill_rows, dim3((unsigned)fb), dim3(256), 0, st, hit_seq, cells);
-        } else {
-            hipLaunchKernelGGL(k_fill_rows_scalar, dim3((unsigned)fb), dim3(256), 0, st, hit_seq, cells);
-        }
+    std::vector<DevJob> hj(n_jobs);
+    int64_t ray_off = 0;
+    int32_t rcv_off = 0;
+    std::vector<int32_t> rcv_job;
+    for (int j = 0; j < n_jobs; j++) {
+        const rt_job& jb = jobs[j];
+        RT_CHECK(jb.scene >= 0 && jb.scene < n_scenes, RT_EINVAL, "rt_batch_create: job %d: bad scene", j);
+        RT_CHECK(jb.n_rcv >= 1 && jb.n_rcv <= kMaxRcv, RT_EINVAL, "rt_batch_create: job %d: n_rcv in [1, %d]", j,
+                 kMaxRcv);
+        RT_CHECK(jb.n_rays >= 1, RT_EINVAL, "rt_batch_create: job %d: n_rays < 1", j);
+        hj[j] = DevJob{ray_off, jb.n_rays, {jb.src[0], jb.src[1], jb.src[2]}, jb.max_path_length, jb.scene, rcv_off,
+                       jb.n_rcv, 0};
+        ray_off += jb.n_rays;
+        for (int m = 0; m < jb.n_rcv; m++) rcv_job.push_back(j);
+        rcv_off += jb.n_rcv;
     }
-    // continuation rounds: launch rd takes the rays left over by launch rd-1;
-    // every launch hands over at most one ray per lane, so a queue of one
-    // entry per lane of the grid never overflows
-    const int rounds = p->rounds > 0 ? (p->rounds < 16 ? p->rounds : 16) : 1;
-    const int64_t lanes = nblk * kBlock;
-    if (s->ws.generic[0].ensure(sizeof(int32_t) * kQueueInts * (size_t)lanes * 2)) return RT_ENOMEM;
-    int4* qbuf[2] = {s->ws.generic[0].as<int4>(), s->ws.generic[0].as<int4>() + 3 * lanes};
-    a.spill_thr = p->spill_threshold > 0 ? p->spill_threshold : 24;
-    for (int rd = 0; rd < rounds; rd++) {
-        a.pool = pool + rd;
-        a.q_in = rd == 0 ? nullptr : qbuf[(rd - 1) & 1];
-        a.q_in_count = rd == 0 ? nullptr : pool + 16 + (rd - 1);
-        a.q_out = rd + 1 < rounds ? qbuf[rd & 1] : nullptr;
-        a.q_out_count = pool + 16 + rd;
-        if (rd > 0) a.order = nullptr;
-        hipLaunchKernelGGL(k_trace, dim3((unsigned)nblk), dim3(kBlock), 0, st, a);
+    RT_CHECK(ray_off < ((int64_t)1 << 31), RT_EINVAL, "rt_batch_create: more than 2^31 rays");
+    rt_batch* b = new rt_batch();
+    b->n_scenes = n_scenes;
+    b->n_jobs = n_jobs;
+    b->n_rcv = rcv_off;
+    b->n_mat = mat_off;
+    b->n_rays = ray_off;
+    b->ws_owner = const_cast<rt_scene*>(scenes[0]);
+    int depth = 0;
+    int64_t steps = 0;
+    for (int i = 0; i < n_scenes; i++) {
+        depth = depth > scenes[i]->depth ? depth : scenes[i]->depth;
+        const int64_t ms = 8 * ((int64_t)scenes[i]->n_nodes + scenes[i]->n_tri) + 4096;
+        steps = steps > ms ? steps : ms;
     }
-    RT_HIP(hipGetLastError());
+    b->max_depth = depth;
+    b->max_steps = steps;
+    b->scenes = (DevScene*)dcache_alloc(sizeof(DevScene) * n_scenes);
+    b->jobs = (DevJob*)dcache_alloc(sizeof(DevJob) * n_jobs);
+    b->rcv_job = (int32_t*)dcache_alloc(sizeof(int32_t) * rcv_off);
+    if (!b->scenes || !b->jobs || !b->rcv_job) {
+        rt_batch_destroy(b);
+        set_error("rt_batch_create: out of device memory");
+        return RT_ENOMEM;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    if (hipMemcpyAsync(b->scenes, hs.data(), sizeof(DevScene) * n_scenes, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(b->jobs, hj.data(), sizeof(DevJob) * n_jobs, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(b->rcv_job, rcv_job.data(), sizeof(int32_t) * rcv_off, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+        rt_batch_destroy(b);
+        set_error("rt_batch_create: upload failed");
+        return RT_EHIP;
+    }
+    RT_HIP(hipGetDevice(&b->device));
+    *out = b;
     return RT_OK;
+}
+
+extern "C" int rt_batch_destroy(rt_batch* b) {
+    if (!b) return RT_OK;
+    (void)hipDeviceSynchronize();
+    dcache_free(b->scenes);
+    dcache_free(b->jobs);
+    dcache_free(b->rcv_job);
+    delete b;
+    return RT_OK;
+}
+
+extern "C" int rt_batch_info(const rt_batch* b, int64_t* info_host) {
+    RT_CHECK(b && info_host, RT_EINVAL, "rt_batch_info: null argument");
+    info_host[0] = b->n_jobs;
+    info_host[1] = b->n_rays;
+    info_host[2] = b->n_rcv;
+    info_host[3] = b->n_mat;
+    return RT_OK;
+}
+
+extern "C" int rt_trace_batch(rt_batch* b, const float* rcv, const rt_trace_params* p, int32_t* hit_seq, int32_t* det,
+                              int64_t det_cap, int64_t* counters, void* stream) {
+    RT_CHECK(b && rcv && hit_seq && counters, RT_EINVAL, "rt_trace_batch: null argument");
+    if (check_params(p)) return RT_EINVAL;
+    RT_CHECK(!p->record_states, RT_EINVAL, "rt_trace_batch: record_states is not supported for batches");
+    RT_CHECK(det_cap >= 0 && (det_cap == 0 || det), RT_EINVAL, "rt_trace_batch: det is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    rt_scene* s = b->ws_owner;
+    if (s->ws.trace_pool.ensure(32 * sizeof(unsigned long long))) return RT_ENOMEM;
+    unsigned long long* pool = s->ws.trace_pool.as<unsigned long long>();
+    hipLaunchKernelGGL(k_trace_reset, dim3(1), dim3(64), 0, st, (unsigned long long*)counters, pool,
+                       (unsigned long long*)p->stats);
+    TraceArgs a{};
+    a.n_rays = b->n_rays;
+    a.rcv = rcv;
+    a.R = p->max_reflections;
+    a.hit_seq = hit_seq;
+    a.det = det;
+    a.det_cap = det_cap;
+    a.counters = (unsigned long long*)counters;
+    a.pool = pool;
+    a.jobs = b->jobs;
+    a.scenes = b->scenes;
+    a.n_jobs = b->n_jobs;
+    float bounds[6] = {0, 0, 0, 1, 1, 1};
+    return run_trace(s, a, p, b->max_depth, b->max_steps, b->n_rays, hit_seq, nullptr, nullptr, bounds, st);
 }

@@ -506,89 +506,126 @@ def tetra_room(scale: float = 4.0):
 # batched rooms (many rooms of uneven size)
 # ----------------------------------------------------------------------------
 
-def _room_grid_counts(dims, target: int):
-    """Grid resolution (nx, ny, nz) of a box whose surface has ~target tris."""
-    Lx, Ly, Lz = dims
-    area = 2 * (Lx * Ly + Ly * Lz + Lx * Lz)
-    h = math.sqrt(4 * area / max(target, 12) / 4.0) if target > 12 else max(dims)
-    h = math.sqrt(area * 2 / target)  # cell size so that 2*area/h^2 ~ target
-    return tuple(max(1, int(round(L / h))) for L in dims)
+def voxel_surface(inside: np.ndarray, spacing):
+    """Closed triangle surface of a union of lattice cells.
+
+    inside: bool [nx, ny, nz] (True = air).  Every cell face between an inside
+    cell and an outside cell (or the lattice border) becomes two triangles;
+    vertices are shared lattice points, so the surface is watertight.  Faces
+    in one axis-aligned plane share a plane id (their lowest triangle index);
+    material = face orientation: 0 -x, 1 +x, 2 -y, 3 +y, 4 floor, 5 ceiling
+    (the direction the wall faces into the room)."""
+    nx, ny, nz = inside.shape
+    pad = np.zeros((nx + 2, ny + 2, nz + 2), bool)
+    pad[1:-1, 1:-1, 1:-1] = inside
+    quads, mats, keys = [], [], []
+    V = lambda i, j, k: (i * (ny + 1) + j) * (nz + 1) + k   # noqa: E731
+    for ax in range(3):
+        a_ = np.moveaxis(pad, ax, 0)
+        diff = a_[1:].astype(np.int8) - a_[:-1].astype(np.int8)       # [n_ax+1, ., .] face planes
+        for sign, mat in ((1, 2 * ax), (-1, 2 * ax + 1)):
+            # sign=+1: outside -> inside going +axis: wall faces +axis into the room... material by facing
+            f = np.argwhere(diff == sign)
+            if len(f) == 0:
+                continue
+            f[:, 1:] -= 1                                               # back to cell coordinates
+            p = f[:, 0]
+            u = f[:, 1]
+            w = f[:, 2]
+            if ax == 0:
+                c = [(p, u, w), (p, u + 1, w), (p, u + 1, w + 1), (p, u, w + 1)]
+            elif ax == 1:
+                c = [(u, p, w), (u + 1, p, w), (u + 1, p, w + 1), (u, p, w + 1)]
+            else:
+                c = [(u, w, p), (u + 1, w, p), (u + 1, w + 1, p), (u, w + 1, p)]
+            q = np.stack([V(*cc) for cc in c], axis=1)
+            quads.append(q)
+            mats.append(np.full(len(q), mat, np.int32))
+            keys.append(np.stack([np.full(len(q), ax), p], axis=1))
+    q = np.concatenate(quads)
+    mat = np.concatenate(mats)
+    key = np.concatenate(keys)
+    tri = _quads_to_tris(q)
+    mat = np.repeat(mat, 2)
+    key = np.repeat(key, 2, axis=0)
+    used, inv = np.unique(tri.ravel(), return_inverse=True)
+    tri = inv.reshape(-1, 3).astype(np.int32)
+    ii = used // ((ny + 1) * (nz + 1))
+    jj = (used // (nz + 1)) % (ny + 1)
+    kk = used % (nz + 1)
+    vtx = np.stack([ii * spacing[0], jj * spacing[1], kk * spacing[2]], axis=1).astype(np.float32)
+    # plane ids: lowest triangle index of each (axis, plane index) group
+    _, first, grp = np.unique(key, axis=0, return_index=True, return_inverse=True)
+    plane = first[grp.ravel()].astype(np.int32)
+    return vtx, tri, mat, plane
+
+
+def _room_cells(kind: int, n):
+    nx, ny, nz = n
+    inside = np.ones((nx, ny, nz), bool)
+    if kind == 1:                                  # L-shape: remove one corner block
+        inside[nx // 2:, ny // 2:, :] = False
+    elif kind == 2:                                # tiered floor: 3 steps rising along y
+        step = max(1, nz // 6)
+        for t in range(1, 4):
+            inside[:, (t * ny) // 4:, : step * t] = False
+    return inside
+
+
+def _interior_points(rng, inside, spacing, n, margin):
+    """Seeded points inside the air cells at least `margin` from any wall."""
+    nx, ny, nz = inside.shape
+    hi = np.array([nx, ny, nz]) * np.asarray(spacing)
+    out = []
+    while len(out) < n:
+        p = rng.uniform(0, hi)
+        ok = True
+        for dx in (-margin, 0, margin):
+            for dy in (-margin, 0, margin):
+                for dz in (-margin, 0, margin):
+                    q = p + (dx, dy, dz)
+                    c = np.floor(q / spacing).astype(int)
+                    if np.any(c < 0) or np.any(c >= (nx, ny, nz)) or not inside[tuple(c)]:
+                        ok = False
+        if ok:
+            out.append(p)
+    return np.array(out, np.float32)
 
 
 def batched_rooms(seed: int = 4, n_rooms: int = 8, pairs_per_room: int = 8,
                   m_lo: float = 1000.0, m_hi: float = 200_000.0, rays_per_pair: int = 200_000,
                   max_reflections: int = 50, ir_seconds: float = 1.0,
                   alpha_range=(0.02, 0.3)) -> List[Scene]:
-    """Rooms of uneven size M_i ~ m_lo * (m_hi/m_lo)**(i/(n-1)), cycling through
-    shoebox, L-shape and tiered-floor variants, dims U[4,30] m, each meshed as
-    planar grids; 6 materials per room; pairs_per_room (source, receiver) pairs
-    at least 1 m from the walls (r = 0.3 m)."""
+    """Rooms of uneven size M_i ~ m_lo (m_hi/m_lo)^(i/(n-1)), cycling through
+    shoebox, L-shape and tiered floor, dims U[4, 30] m (height <= 12 m), each
+    a watertight lattice surface with exact coplanar plane groups; 6
+    materials per room (by wall orientation), alpha ~ U[alpha_range];
+    pairs_per_room (source, receiver) pairs at least 1 m from the walls,
+    receiver radius 0.3 m.  scene.src holds [pairs, 3] sources and scene.rcv
+    the [pairs, 4] receivers (pair p = source p with receiver p)."""
     rng = np.random.default_rng(seed)
     rooms = []
     for i in range(n_rooms):
         frac = i / max(1, n_rooms - 1)
         target = m_lo * (m_hi / m_lo) ** frac
         kind = i % 3
-        dims = tuple(sorted(rng.uniform(4.0, 30.0, size=3), reverse=True))
-        dims = (dims[0], dims[1], min(dims[2], 12.0))
-        n = _room_grid_counts(dims, target)
-        vtx, tri, mat, plane = box_mesh(dims, n, plane_per_wall=True)
-        if kind == 1:
-            # L-shape: fold a notch by pushing one corner region of the +x wall inward
-            vtx = vtx.copy()
-            sel = (vtx[:, 0] >= dims[0] - 1e-6) & (vtx[:, 1] >= 0.5 * dims[1])
-            vtx[sel, 0] = np.float32(0.6 * dims[0])
-            # the moved wall stays planar (x = 0.6 Lx); re-key its plane
-        elif kind == 2:
-            # tiered floor: floor vertices rise in steps along y (risers stay planar per step)
-            vtx = vtx.copy()
-            sel = vtx[:, 2] <= 1e-6
-            steps = np.floor(vtx[sel, 1] / (dims[1] / 4.0)).clip(0, 3)
-            vtx[sel, 2] = (0.3 * steps).astype(np.float32)
-        # recompute coplanar groups after deformation: plane id = tri id unless all
-        # of a wall stayed flat (checked exactly)
-        plane = _group_coplanar(vtx, tri, plane)
+        d = rng.uniform(4.0, 30.0, size=3)
+        dims = (float(d[0]), float(d[1]), float(min(d[2], 12.0)))
+        area = 2 * (dims[0] * dims[1] + dims[1] * dims[2] + dims[0] * dims[2])
+        h = math.sqrt(2 * area / target)          # a lattice box surface has 2 area / h^2 triangles
+        n = tuple(max(2, int(round(L / h))) for L in dims)
+        spacing = tuple(L / k for L, k in zip(dims, n))
+        inside = _room_cells(kind, n)
+        vtx, tri, mat, plane = voxel_surface(inside, spacing)
         alpha = random_alpha(rng, 6, *alpha_range)
-        lo = np.array([1.0, 1.0, 1.0 + (0.9 if kind == 2 else 0.0)])
-        hi = np.array([dims[0] * (0.6 if kind == 1 else 1.0), dims[1], dims[2]]) - 1.0
-        hi = np.maximum(hi, lo + 0.5)
-        srcs = rng.uniform(lo, hi, size=(pairs_per_room, 3)).astype(np.float32)
-        rcvs = np.concatenate([rng.uniform(lo, hi, size=(pairs_per_room, 3)),
-                               np.full((pairs_per_room, 1), 0.3)], axis=1).astype(np.float32)
+        srcs = _interior_points(rng, inside, spacing, pairs_per_room, 1.0)
+        rcvs = np.concatenate([_interior_points(rng, inside, spacing, pairs_per_room, 1.0),
+                               np.full((pairs_per_room, 1), 0.3, np.float32)], axis=1).astype(np.float32)
         s = Scene(f"room{i} kind{kind} {len(tri)} tris", vtx, tri, mat, plane, alpha, closed=True,
                   src=srcs, rcv=rcvs, beta=iso9613_beta(), n_rays=rays_per_pair,
                   max_reflections=max_reflections, ir_seconds=ir_seconds)
-        assert np.all(_tri_areas(vtx, tri) > 0)
-        rooms.append(s)
+        rooms.append(_check(s))
     return rooms
-
-
-def _group_coplanar(vtx, tri, plane):
-    """Keep a wall's shared plane id only where every member triangle is still
-    exactly in the representative's axis-aligned plane; otherwise one id per tri."""
-    out = plane.copy()
-    v = vtx.astype(np.float64)
-    for pid in np.unique(plane):
-        members = np.nonzero(plane == pid)[0]
-        p = v[tri[members]].reshape(-1, 3)
-        flat = any(np.all(p[:, ax] == p[0, ax]) for ax in range(3))
-        if not flat:
-            # split into exactly-flat subgroups by axis-aligned coordinate if possible
-            rep = {}
-            for m in members:
-                q = v[tri[m]]
-                key = None
-                for ax in range(3):
-                    if np.all(q[:, ax] == q[0, ax]):
-                        key = (ax, q[0, ax])
-                        break
-                if key is None:
-                    out[m] = m
-                else:
-                    if key not in rep:
-                        rep[key] = m
-                    out[m] = rep[key]
-    return out.astype(np.int32)
 
 
 # ----------------------------------------------------------------------------
