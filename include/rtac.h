@@ -114,6 +114,9 @@ typedef struct {
                                   a wavefront with few rays left hands them to the next launch  */
     int32_t spill_threshold;   /* 0 = default; most rays a wavefront may still hold to hand over */
     int32_t waves_per_simd;    /* 0 = default (4); register budget of the trace kernel: 4, 5, 6, 8  */
+    void* kernel_event_start;  /* NULL or a hipEvent_t: recorded on `stream` just before the first
+                                  traversal-kernel launch (after ray ordering and output fill)  */
+    void* kernel_event_stop;   /* NULL or a hipEvent_t: recorded just after the last one        */
 } rt_trace_params;
 
 /*
@@ -269,6 +272,69 @@ int rt_adjoint_batch(rt_batch* batch, const int32_t* is_key, const int32_t* is_c
                      const int64_t* n_is, int64_t is_cap, int32_t max_reflections, const float* alpha,
                      const float* beta, float c, float fs, int64_t L, const float* grad_band_energy,
                      float* grad_alpha, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Late-tail surrogate (an extension of the method, not in the paper).  The
+ * paper notes that late image sources are reached by few rays (section
+ * "Discrete model"), so the late response is the noisiest and costliest part
+ * of a trace.  A ReLU multilayer perceptron maps the per-band energy
+ * histogram of reflection orders 0..8 (features) to the per-band decay curve
+ * of the full trace (Schroeder backward integration, dB re total).
+ *
+ * Network: widths w_0 .. w_L (each a multiple of 64 in [64, 4096], L <= 8);
+ * hidden layers h_l = relu(W_l h_{l-1} + b_l), output y = W_L h_{L-1} + b_L.
+ * Parameters are one flat vector, layer after layer: W_l [w_l, w_{l-1}]
+ * row-major, then b_l [w_l].  theta (FP32 master copy) and theta_bf16 (its
+ * round-to-nearest-even BF16 copy, read by the matrix-core kernels) share
+ * that layout, as do the gradient and both Adam moments.  Products run on
+ * the BF16 matrix cores with FP32 accumulation; activations are stored in
+ * BF16.  A handle owns the activations of its last forward call and the
+ * backward scratch; calls on one handle must be ordered on one stream.
+ * ------------------------------------------------------------------------ */
+typedef struct rt_mlp rt_mlp;
+
+/* widths: host int32 [n_layers + 1]; max_batch: largest batch of any call. */
+int rt_mlp_create(const int32_t* widths, int32_t n_layers, int64_t max_batch, rt_mlp** out);
+int rt_mlp_destroy(rt_mlp* net);
+/* info: host int64[4] = number of parameters, layers, max_batch, activation elements. */
+int rt_mlp_info(const rt_mlp* net, int64_t* info);
+
+/* y [batch, w_L] float = network(x [batch, w_0] bf16).  theta_f32 (may be
+ * NULL): when given, biases are read from it in FP32, else from theta_bf16.
+ * x and theta_bf16 must be 16-byte aligned.  Keeps the hidden activations
+ * for rt_mlp_backward. */
+int rt_mlp_forward(rt_mlp* net, const uint16_t* theta_bf16, const float* theta_f32, const uint16_t* x,
+                   int64_t batch, float* y, void* stream);
+
+/* Masked squared error S = sum m (y - t)^2 over [batch, w_L] (mask NULL: all
+ * ones) and its gradient dS/dtheta into grad [n_params] float (overwritten,
+ * not divided by sum m).  loss_terms: device double[2] out = (S, sum m); the
+ * mean loss is S / sum m.  Must follow rt_mlp_forward on the same x and
+ * batch (the batch is checked, x is not). */
+int rt_mlp_backward(rt_mlp* net, const uint16_t* theta_bf16, const uint16_t* x, int64_t batch, const float* y,
+                    const float* target, const float* mask, float* grad, double* loss_terms, void* stream);
+
+/* One Adam step (Kingma & Ba 2015, bias-corrected moments) at step >= 1 on
+ * all n_params entries: g = grad / loss_terms[1] (g = grad when loss_terms
+ * is NULL; 0 when the mask sum is 0), m = b1 m + (1 - b1) g, v = b2 v +
+ * (1 - b2) g^2, theta -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps),
+ * in FP32; theta_bf16 (may be NULL) receives the rounded copy. */
+int rt_mlp_adam(int64_t n_params, float* theta, uint16_t* theta_bf16, const float* grad, float* m, float* v,
+                const double* loss_terms, int32_t step, float lr, float beta1, float beta2, float eps,
+                void* stream);
+
+/* y [n] bf16 = round-to-nearest-even(x [n] float). */
+int rt_to_bf16(const float* x, int64_t n, uint16_t* y, void* stream);
+
+/* Surrogate features: x[i] = (max(10 log10 hist[i], floor_db) + offset_db) /
+ * scale_db as BF16 (a bin with no energy gives floor_db). */
+int rt_hist_features(const float* hist, int64_t n, float floor_db, float offset_db, float scale_db, uint16_t* x,
+                     void* stream);
+
+/* Energy decay curve per row of hist [rows, bins] (energy per time bin):
+ * edc[r, s] = 10 log10(sum_{s' >= s} hist[r, s'] / sum_{s'} hist[r, s']),
+ * FP64 sums, clamped below at floor_db (a row without energy is all floor). */
+int rt_edc_db(const float* hist, int64_t rows, int32_t bins, float floor_db, float* edc, void* stream);
 
 /* Test hook for the exact-grouping path of rt_collect_image_sources: keep
  * only the low `bits` bits (1..64, default 64) of the 64-bit key hash so that

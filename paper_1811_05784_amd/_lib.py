@@ -25,7 +25,8 @@ class TraceParams(ctypes.Structure):
     _fields_ = [("max_reflections", I32), ("max_path_length", F32), ("record_states", I32),
                 ("fetch_threshold", I32), ("shade_threshold", I32), ("blocks_per_cu", I32),
                 ("keep_order", I32), ("stats", P), ("rounds", I32), ("spill_threshold", I32),
-                ("waves_per_simd", I32)]
+                ("waves_per_simd", I32), ("kernel_event_start", P),
+                ("kernel_event_stop", P)]
 
 
 class Job(ctypes.Structure):
@@ -52,6 +53,15 @@ SIGNATURES = {
     "rt_collect_batch": (ctypes.c_int, [P, P, P, I32, P, I64, P, P, P, P, P, I64, P, P]),
     "rt_assemble_batch": (ctypes.c_int, [P, P, P, P, P, I64, I32, P, P, F32, F32, I64, P, I32, P, P, P, P, P]),
     "rt_adjoint_batch": (ctypes.c_int, [P, P, P, P, P, I64, I32, P, P, F32, F32, I64, P, P, P]),
+    "rt_mlp_create": (ctypes.c_int, [P, I32, I64, ctypes.POINTER(P)]),
+    "rt_mlp_destroy": (ctypes.c_int, [P]),
+    "rt_mlp_info": (ctypes.c_int, [P, P]),
+    "rt_mlp_forward": (ctypes.c_int, [P, P, P, P, I64, P, P]),
+    "rt_mlp_backward": (ctypes.c_int, [P, P, P, I64, P, P, P, P, P, P]),
+    "rt_mlp_adam": (ctypes.c_int, [I64, P, P, P, P, P, P, I32, F32, F32, F32, F32, P]),
+    "rt_to_bf16": (ctypes.c_int, [P, I64, P, P]),
+    "rt_hist_features": (ctypes.c_int, [P, I64, F32, F32, F32, P, P]),
+    "rt_edc_db": (ctypes.c_int, [P, I64, I32, F32, P, P]),
     "rt_debug_set_hash_bits": (ctypes.c_int, [ctypes.c_int]),
     "rt_last_error": (ctypes.c_char_p, []),
     "rt_version": (ctypes.c_char_p, []),

@@ -787,6 +787,7 @@ int run_trace(rt_scene* ws, TraceArgs& a, const rt_trace_params* p, int depth, i
     int4* qbuf[2] = {ws->ws.generic[0].as<int4>(), ws->ws.generic[0].as<int4>() + 3 * lanes};
     a.spill_thr = p->spill_threshold > 0 ? p->spill_threshold : 24;
     unsigned long long* pool = a.pool;
+    if (p->kernel_event_start) RT_HIP(hipEventRecord((hipEvent_t)p->kernel_event_start, st));
     for (int rd = 0; rd < rounds; rd++) {
         a.pool = pool + rd;
         a.q_in = rd == 0 ? nullptr : qbuf[(rd - 1) & 1];
@@ -797,6 +798,7 @@ int run_trace(rt_scene* ws, TraceArgs& a, const rt_trace_params* p, int depth, i
         launch_trace(occ, a.jobs != nullptr, (unsigned)nblk, st, a);
     }
     RT_HIP(hipGetLastError());
+    if (p->kernel_event_stop) RT_HIP(hipEventRecord((hipEvent_t)p->kernel_event_stop, st));
     return RT_OK;
 }
 

@@ -608,24 +608,77 @@ def batched_rooms(seed: int = 4, n_rooms: int = 8, pairs_per_room: int = 8,
     for i in range(n_rooms):
         frac = i / max(1, n_rooms - 1)
         target = m_lo * (m_hi / m_lo) ** frac
-        kind = i % 3
-        d = rng.uniform(4.0, 30.0, size=3)
-        dims = (float(d[0]), float(d[1]), float(min(d[2], 12.0)))
-        area = 2 * (dims[0] * dims[1] + dims[1] * dims[2] + dims[0] * dims[2])
-        h = math.sqrt(2 * area / target)          # a lattice box surface has 2 area / h^2 triangles
-        n = tuple(max(2, int(round(L / h))) for L in dims)
-        spacing = tuple(L / k for L, k in zip(dims, n))
-        inside = _room_cells(kind, n)
-        vtx, tri, mat, plane = voxel_surface(inside, spacing)
-        alpha = random_alpha(rng, 6, *alpha_range)
-        srcs = _interior_points(rng, inside, spacing, pairs_per_room, 1.0)
-        rcvs = np.concatenate([_interior_points(rng, inside, spacing, pairs_per_room, 1.0),
-                               np.full((pairs_per_room, 1), 0.3, np.float32)], axis=1).astype(np.float32)
-        s = Scene(f"room{i} kind{kind} {len(tri)} tris", vtx, tri, mat, plane, alpha, closed=True,
-                  src=srcs, rcv=rcvs, beta=iso9613_beta(), n_rays=rays_per_pair,
-                  max_reflections=max_reflections, ir_seconds=ir_seconds)
-        rooms.append(_check(s))
+        rooms.append(_lattice_room(rng, i, target, i % 3, pairs_per_room, alpha_range, rays_per_pair,
+                                   max_reflections, ir_seconds))
     return rooms
+
+
+def _lattice_room(rng, i, target, kind, pairs, alpha_range, rays, max_reflections, ir_seconds) -> Scene:
+    d = rng.uniform(4.0, 30.0, size=3)
+    dims = (float(d[0]), float(d[1]), float(min(d[2], 12.0)))
+    area = 2 * (dims[0] * dims[1] + dims[1] * dims[2] + dims[0] * dims[2])
+    h = math.sqrt(2 * area / target)          # a lattice box surface has 2 area / h^2 triangles
+    n = tuple(max(2, int(round(L / h))) for L in dims)
+    spacing = tuple(L / k for L, k in zip(dims, n))
+    inside = _room_cells(kind, n)
+    vtx, tri, mat, plane = voxel_surface(inside, spacing)
+    alpha = random_alpha(rng, 6, *alpha_range)
+    srcs = _interior_points(rng, inside, spacing, pairs, 1.0)
+    rcvs = np.concatenate([_interior_points(rng, inside, spacing, pairs, 1.0),
+                           np.full((pairs, 1), 0.3, np.float32)], axis=1).astype(np.float32)
+    s = Scene(f"room{i} kind{kind} {len(tri)} tris", vtx, tri, mat, plane, alpha, closed=True,
+              src=srcs, rcv=rcvs, beta=iso9613_beta(), n_rays=rays,
+              max_reflections=max_reflections, ir_seconds=ir_seconds)
+    return _check(s)
+
+
+def surrogate_rooms(seed: int = 5, n_rooms: int = 2000, m_lo: float = 1000.0, m_hi: float = 50_000.0,
+                    alpha_range=(0.02, 0.5), rays_per_pair: int = 100_000, max_reflections: int = 60,
+                    ir_seconds: float = 2.0, first: int = 0) -> List[Scene]:
+    """Training rooms for the late-tail surrogate: like batched_rooms, but the
+    triangle count is log-uniform in [m_lo, m_hi] and the shape (shoebox,
+    L-shape, tiered floor) is drawn at random; one (source, receiver) pair
+    per room.  Rooms first .. n_rooms-1 of the seeded sequence are returned
+    (every room consumes the same generator state as when all are built)."""
+    rng = np.random.default_rng(seed)
+    rooms = []
+    for i in range(n_rooms):
+        target = float(np.exp(rng.uniform(np.log(m_lo), np.log(m_hi))))
+        kind = int(rng.integers(0, 3))
+        sub = np.random.default_rng([seed, i])
+        if i >= first:
+            rooms.append(_lattice_room(sub, i, target, kind, 1, alpha_range, rays_per_pair, max_reflections,
+                                       ir_seconds))
+    return rooms
+
+
+def mlp_init(seed: int, widths, bias_std: float = 0.0) -> np.ndarray:
+    """Flat FP32 parameter vector (W_l [w_l, w_{l-1}] row-major, then b_l,
+    layer after layer): He-normal weights (std sqrt(2 / fan_in)) quantised to
+    k 2^-e with |k| < 256, so every value is exactly representable in BF16;
+    biases N(0, bias_std^2) quantised the same way (0 by default)."""
+    rng = np.random.default_rng(seed)
+
+    def quant(x, std):
+        if std == 0:
+            return np.zeros_like(x)
+        e = math.floor(math.log2(std)) - 5               # step = std / 32 .. std / 64
+        k = np.clip(np.round(x / 2.0 ** e), -255, 255)
+        return (k * 2.0 ** e).astype(np.float32)
+
+    parts = []
+    for i, j in zip(widths[:-1], widths[1:]):
+        std = math.sqrt(2.0 / i)
+        parts.append(quant(rng.standard_normal(i * j) * std, std))
+        parts.append(quant(rng.standard_normal(j) * bias_std, bias_std))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def mlp_inputs(seed: int, batch: int, width: int, scale: float = 1.0) -> np.ndarray:
+    """[batch, width] FP32 inputs k/64 * scale, |k| <= 192 (exactly BF16 for a
+    power-of-two scale)."""
+    rng = np.random.default_rng(seed)
+    return (rng.integers(-192, 193, size=(batch, width)) / 64.0 * scale).astype(np.float32)
 
 
 # ----------------------------------------------------------------------------

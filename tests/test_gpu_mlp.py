@@ -1,0 +1,222 @@
+"""Parity of the late-tail surrogate kernels (BF16 matrix-core MLP forward
+and backward, Adam, features, decay curve) with the FP64 oracle.
+
+Inputs and weights are multiples of powers of two with at most 8
+significant bits, so the BF16 copies are exact and both sides start from the
+same values.  Tolerances:
+* one layer (no rounded intermediate): products of BF16 values are exact in
+  FP32, K-term FP32 sums -> 1e-5 relative to the output scale;
+* deep network: hidden activations are rounded to BF16 (2^-9 relative)
+  -> 1e-2 relative (RMS of the output / gradient norm per layer);
+* Adam in FP32: half an ulp of theta plus 1e-5 of the update;
+* decay curve: FP64 sums, FP32 output -> 1e-4 dB;
+* features: BF16 output -> 2^-7 relative.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import mlp as omlp
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def sg():
+    import paper_1811_05784_amd as m
+    m.load()
+    from paper_1811_05784_amd import surrogate
+    return surrogate
+
+
+def _bf16(a):
+    t = torch.as_tensor(np.asarray(a, np.float32), device=DEV)
+    b = t.to(torch.bfloat16)
+    assert torch.equal(b.float(), t), "input not exactly representable in BF16"
+    return b.contiguous()
+
+
+@pytest.mark.parametrize("batch", [1, 77, 256])
+def test_single_layer_forward_exact_layout(sg, batch):
+    widths = (128, 192)
+    theta = synth.mlp_init(1, widths, bias_std=0.5)
+    x = synth.mlp_inputs(2, batch, widths[0])
+    net = sg.Mlp(theta, widths, max_batch=256, device=DEV)
+    y = net.forward(_bf16(x)).cpu().numpy().astype(np.float64)
+    ref = omlp.forward(theta.astype(np.float64), widths, x.astype(np.float64))[-1]
+    scale = np.abs(ref).max()
+    assert np.abs(y - ref).max() <= 1e-5 * scale
+
+
+def test_deep_forward_matches_oracle(sg):
+    widths = sg.WIDTHS
+    theta = synth.mlp_init(3, widths, bias_std=0.1)
+    x = synth.mlp_inputs(4, 130, widths[0])
+    net = sg.Mlp(theta, widths, max_batch=256, device=DEV)
+    y = net.forward(_bf16(x)).cpu().numpy().astype(np.float64)
+    ref = omlp.forward(theta.astype(np.float64), widths, x.astype(np.float64))[-1]
+    rms = np.sqrt((ref ** 2).mean())
+    err = np.sqrt(((y - ref) ** 2).mean())
+    print("deep forward rel rms err %.3e" % (err / rms))
+    assert err <= 1e-2 * rms
+
+
+def _margin_rows(theta, widths, x, n_keep, margin=0.03):
+    """Rows of x whose FP64 hidden pre-activations all stay at least
+    margin * (layer RMS) away from 0, so BF16 rounding in the forward pass
+    cannot flip a ReLU (chosen with the oracle only)."""
+    acts = [x.astype(np.float64)]
+    ok = np.ones(len(x), bool)
+    for li, (W, b) in enumerate(omlp.split_params(theta.astype(np.float64), widths)):
+        z = acts[-1] @ W.T + b
+        if li + 1 < len(widths) - 1:
+            ok &= (np.abs(z) >= margin * np.sqrt((z ** 2).mean())).all(axis=1)
+            acts.append(np.maximum(z, 0))
+    idx = np.nonzero(ok)[0]
+    assert len(idx) >= n_keep, len(idx)
+    return x[idx[:n_keep]]
+
+
+@pytest.mark.parametrize("widths,batch,positive", [((128, 64), 50, False), ((128, 64, 64, 128), 60, False),
+                                                   ((512, 256, 256, 256, 1024), 100, True)])
+def test_backward_matches_oracle(sg, widths, batch, positive):
+    """One layer; three layers on inputs with every ReLU decided by a margin
+    (mixed signs); the surrogate's widths with nonnegative weights and inputs
+    (every unit active, no ReLU can flip) to exercise the full-size shapes."""
+    theta = synth.mlp_init(5, widths, bias_std=0.1)
+    x = synth.mlp_inputs(6, 8000 if len(widths) == 4 else batch, widths[0])
+    if positive:
+        theta = np.abs(theta)
+        x = np.abs(x)
+    if len(widths) == 4:
+        x = _margin_rows(theta, widths, x, batch)
+    rng = np.random.default_rng(7)
+    ref_y = omlp.forward(theta.astype(np.float64), widths, x.astype(np.float64))[-1]
+    # residuals of the size of the outputs, so that the forward pass's BF16
+    # rounding (a fraction of a percent of y) stays small next to y - t
+    tgt = (ref_y + np.sqrt((ref_y ** 2).mean()) * rng.standard_normal(ref_y.shape)).astype(np.float32)
+    mask = (rng.uniform(size=tgt.shape) < 0.8).astype(np.float32)
+    net = sg.Mlp(theta, widths, max_batch=128, device=DEV)
+    xb = _bf16(x)
+    y = net.forward(xb)
+    lt = net.backward(xb, y, torch.as_tensor(tgt, device=DEV), torch.as_tensor(mask, device=DEV))
+    S, msum = lt.cpu().numpy()
+    # oracle: mean loss and its gradient from the GPU's own starting point (theta, x): both exact inputs
+    Lref, gref = omlp.backward(theta.astype(np.float64), widths, x.astype(np.float64), tgt.astype(np.float64),
+                               mask.astype(np.float64))
+    assert msum == mask.sum()
+    # the GPU output differs from the FP64 one by BF16 rounding of hidden layers only
+    yg = y.cpu().numpy().astype(np.float64)
+    assert S == pytest.approx((mask * (yg - tgt) ** 2).sum(), rel=1e-6)
+    tol = 5e-3 if len(widths) == 2 else 2e-2
+    assert S / msum == pytest.approx(Lref, rel=tol)
+    g = net.grad.cpu().numpy().astype(np.float64) / msum
+    off = 0
+    for i, j in zip(widths[:-1], widths[1:]):
+        for n in (i * j, j):
+            a, b = g[off:off + n], gref[off:off + n]
+            rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+            print("layer %dx%d part %d: rel grad err %.3e" % (i, j, n, rel))
+            assert rel <= tol
+            off += n
+
+
+def _ulp(x):
+    x = np.abs(np.asarray(x, np.float32))
+    return np.spacing(x).astype(np.float64)
+
+
+def test_adam_matches_oracle(sg):
+    from paper_1811_05784_amd import _lib
+    rng = np.random.default_rng(8)
+    n = 10_000
+    theta = rng.standard_normal(n).astype(np.float32)
+    grad = (rng.standard_normal(n) * 10 ** rng.uniform(-4, 2, n)).astype(np.float32)
+    m = (rng.standard_normal(n) * 0.01).astype(np.float32)
+    v = (rng.uniform(0, 1e-3, n)).astype(np.float32)
+    lt = np.array([3.0, 4.0])
+    t, lr = 7, 1e-3
+    b1, b2, eps = np.float32(0.9), np.float32(0.999), np.float32(1e-8)   # the FP32 values the kernel receives
+    T = {k: torch.as_tensor(a, device=DEV).contiguous() for k, a in
+         dict(theta=theta, grad=grad, m=m, v=v).items()}
+    tb = torch.empty(n, dtype=torch.bfloat16, device=DEV)
+    ltd = torch.as_tensor(lt, device=DEV)
+    lib = _lib.load()
+    rc = lib.rt_mlp_adam(n, T["theta"].data_ptr(), tb.data_ptr(), T["grad"].data_ptr(), T["m"].data_ptr(),
+                         T["v"].data_ptr(), ltd.data_ptr(), t, np.float32(lr), b1, b2, eps,
+                         torch.cuda.current_stream().cuda_stream)
+    assert rc == 0
+    g = grad.astype(np.float64) / lt[1]
+    th_ref, m_ref, v_ref = omlp.adam(theta, g, m, v, t, float(np.float32(lr)), float(b1), float(b2), float(eps))
+    # FP32 rounding bounds: a few ulp of the largest term of each moment update
+    dm = 2 * _ulp(np.maximum(np.abs(float(b1) * m), np.abs((1 - float(b1)) * g)))
+    dv = 2 * _ulp(np.maximum(float(b2) * v, (1 - float(b2)) * g * g))
+    mg = T["m"].cpu().numpy().astype(np.float64)
+    vg = T["v"].cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(mg - m_ref) <= dm)
+    assert np.all(np.abs(vg - v_ref) <= dv)
+    c1 = 1 / (1 - float(b1) ** t)
+    c2 = 1 / (1 - float(b2) ** t)
+    den = np.sqrt(v_ref * c2) + float(eps)
+    step = float(np.float32(lr)) * c1 * np.abs(m_ref) / den
+    # propagated moment errors plus 1e-5 relative for the FP32 update chain and half an ulp of theta
+    prop = float(np.float32(lr)) * c1 * (dm + np.abs(m_ref) * c2 * dv / (2 * np.sqrt(v_ref * c2) * den + 1e-300)) / den
+    th = T["theta"].cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(th - th_ref) <= 0.5 * _ulp(th_ref) + 1e-5 * step + prop + 1e-12)
+    # the BF16 copy is the round-to-nearest-even of the FP32 master
+    u = T["theta"].cpu().numpy().view(np.uint32).astype(np.uint64)
+    rne = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+    assert np.array_equal(tb.cpu().view(torch.int16).numpy().view(np.uint16), rne)
+
+
+def test_training_reduces_loss(sg):
+    widths = (64, 128, 64)
+    teacher = synth.mlp_init(9, widths, bias_std=0.2)
+    x = synth.mlp_inputs(10, 512, widths[0])
+    tgt = omlp.forward(teacher.astype(np.float64), widths, x.astype(np.float64))[-1].astype(np.float32)
+    net = sg.Mlp(synth.mlp_init(11, widths), widths, max_batch=512, device=DEV)
+    xb = _bf16(x)
+    t = torch.as_tensor(tgt, device=DEV)
+    losses = sg.train(net, xb, t, torch.ones_like(t), epochs=150, batch=128, lr=3e-3)
+    print("loss %.4f -> %.4f" % (losses[0], losses[-1]))
+    assert losses[-1] < 0.1 * losses[0]
+
+
+@pytest.mark.parametrize("bins", [64, 100, 128, 1000])
+def test_edc_matches_oracle(sg, bins):
+    rng = np.random.default_rng(bins)
+    h = (rng.exponential(size=(37, bins)) * np.exp(-np.arange(bins) / (bins / 8))).astype(np.float32)
+    h[rng.uniform(size=h.shape) < 0.3] = 0.0
+    h[3] = 0.0                       # a row without energy
+    h[5, bins // 2:] = 0.0           # energy ends early
+    got = sg.edc_db(torch.as_tensor(h, device=DEV)).cpu().numpy().astype(np.float64)
+    ref = omlp.schroeder_edc_db(h.astype(np.float64), sg.FLOOR_DB)
+    assert np.abs(got - ref).max() <= 1e-4
+
+
+def test_features_match_oracle(sg):
+    rng = np.random.default_rng(12)
+    h = (10.0 ** rng.uniform(-20, 1, size=(9, 8, 64))).astype(np.float32)
+    h[rng.uniform(size=h.shape) < 0.2] = 0.0
+    got = sg.hist_features(torch.as_tensor(h, device=DEV)).float().cpu().numpy().astype(np.float64)
+    ref = omlp.hist_features(h.astype(np.float64))
+    assert np.all(np.abs(got - ref) <= 2.0 ** -7 * np.abs(ref) + 1e-6)
+
+
+def test_pipeline_small_rooms(sg):
+    """Rooms -> histograms -> features / decay targets; the early-only curve
+    matches the full one at the start and the network trains on them."""
+    rooms = synth.surrogate_rooms(n_rooms=16, m_hi=5000.0)
+    x, tgt, mask, base = sg.dataset(rooms, n_rays=20_000, full_order=30, T=1.0, device=DEV)
+    assert x.shape == (16, 512) and tgt.shape == (16, 1024)
+    t = tgt.cpu().numpy().reshape(16, 8, 128)
+    assert np.all(t[:, :, 0] == 0.0)                      # EDC starts at 0 dB re total
+    assert np.all(np.diff(t, axis=-1) <= 1e-4)            # and never rises
+    assert mask.sum() > 0
+    net = sg.Mlp(synth.mlp_init(13, sg.WIDTHS), sg.WIDTHS, max_batch=16, device=DEV)
+    losses = sg.train(net, x, tgt, mask, epochs=60, batch=16, lr=1e-3)
+    assert losses[-1] < losses[0]
+    err = sg.band_rms_db(net.forward(x), tgt)
+    assert torch.isfinite(err).all()
