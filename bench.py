@@ -52,13 +52,27 @@ def main():
     ap.add_argument("--stats", action="store_true", help="count traversal work (extra pass, not timed)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (counter calibration)")
+    ap.add_argument("--workload", choices=("theater", "rooms", "surrogate"), default="theater",
+                    help="theater: 436k-triangle open-air theater (default); rooms: 8 rooms of 1k-200k "
+                         "triangles x 8 source/receiver pairs in one batched launch with the absorption "
+                         "gradient; surrogate: late-tail MLP trained on traced rooms")
+    ap.add_argument("--rooms", type=int, default=2000, help="surrogate: training + held-out rooms")
+    ap.add_argument("--epochs", type=int, default=300, help="surrogate: training epochs")
+    ap.add_argument("--no-tune", action="store_true", help="rooms: skip the launch autotuner")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (the ray set would be split "
               "by ray id across GPUs with the scene replicated; not implemented). Use --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == "rooms":
+        return run_rooms(args)
+    if args.workload == "surrogate":
+        return run_surrogate(args)
+    return run_theater(args)
 
+
+def run_theater(args):
     import torch
 
     import paper_1811_05784_amd as rt
@@ -237,6 +251,223 @@ def band_error(rt, sc, s, taps):
     return {"band_energy_max_rel": float(np.max(np.abs(be - ref["band_energy"]) / ref["band_energy"])),
             "fir_energy_max_rel": float(np.max(np.abs(eb - er) / er)),
             "sample": "seeded image-source table, %d sources, 2 receivers, L=%d, K=4095" % (n, L)}
+
+
+def queries_per_job(b, hit_seq, escapes_dev=None):
+    """Ray segments traced per job, from the hit sequences: every recorded
+    hit ends one segment; a ray that escaped traced one more (closed rooms
+    have none, which the trace counters confirm)."""
+    import torch
+    hits = (hit_seq >= 0).sum(dim=1)
+    off = torch.as_tensor(b.ray_off, device=hit_seq.device)
+    cs = torch.cat([torch.zeros(1, dtype=torch.int64, device=hit_seq.device), hits.cumsum(0)])
+    return (cs[off[1:]] - cs[off[:-1]]).cpu().numpy()
+
+
+def run_rooms(args):
+    """Batched workload: 8 watertight rooms (about 1k to 200k triangles), 8
+    (source, receiver) pairs each, 2e5 rays per pair (1.28e7 rays), R = 50,
+    1 s IR at 48 kHz, 8 bands, K = 4095, and the gradient of the band
+    energies with respect to all 384 absorption coefficients.  Scenes are
+    built once and stay resident; one step = trace, image sources, IR and
+    adjoint, captured in one HIP graph and replayed."""
+    import torch
+
+    import paper_1811_05784_amd as rt
+    import synth
+    from paper_1811_05784_amd import autotune
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    rooms = synth.batched_rooms(seed=4)
+    R, T, c, fs = rooms[0].max_reflections, rooms[0].ir_seconds, rooms[0].c, rooms[0].fs
+    L = int(round(T * fs))
+    t0 = time.perf_counter()
+    scenes = [rt.Scene.from_synth(r, device=dev) for r in rooms]
+    jobs = []
+    for i, r in enumerate(rooms):
+        for p in range(len(r.src)):
+            jobs.append(dict(scene=i, src=r.src[p], rcv=r.rcv[p:p + 1], n_rays=r.n_rays,
+                             max_path_length=c * T + float(r.rcv[p, 3])))
+    b = rt.Batch(scenes, jobs, device=dev)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3
+    alpha = torch.as_tensor(np.concatenate([r.alpha for r in rooms]), device=dev)
+    beta = torch.as_tensor(rooms[0].beta, device=dev)
+    taps = torch.as_tensor(synth.octave_fir_taps(4095), device=dev)
+    g = torch.ones((b.n_rcv, 8), dtype=torch.float32, device=dev)
+    tune = {}
+    tr = rt.trace_batch(b, R, det_cap=2 * b.n_rays)
+    if not args.no_tune:
+        space = {"waves_per_simd": [4], "blocks_per_cu": [0, 8], "fetch_threshold": [16, 32],
+                 "shade_threshold": [16]}
+        key = autotune.key_for(max(sc.n_tri for sc in scenes), b.n_rays)
+        tune = autotune.tune(lambda st: rt.trace_batch(b, R, out=tr, check_capacity=False, **st), key,
+                             space=space, repeats=1)
+    tr = rt.trace_batch(b, R, det_cap=2 * b.n_rays, **tune)
+    isb = rt.collect_batch(b, tr, is_cap=tr.det.shape[0])
+    ir = rt.assemble_batch(b, isb, alpha, beta, c, fs, L, taps)
+    ga = rt.adjoint_batch(b, isb, alpha, beta, c, fs, L, g)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+
+    def body():
+        rt.trace_batch(b, R, out=tr, check_capacity=False, **tune)
+        rt.collect_batch(b, tr, out=isb, check_capacity=False)
+        rt.assemble_batch(b, isb, alpha, beta, c, fs, L, taps, out=ir)
+        rt.adjoint_batch(b, isb, alpha, beta, c, fs, L, g, out=ga)
+
+    with torch.cuda.stream(side):
+        body()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        body()
+    for _ in range(args.warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    cnt = tr.counters.cpu()
+    if int(cnt[3]) != 0 or int(cnt[0]) > tr.det.shape[0] or isb.n_is() > isb.key.shape[0]:
+        raise SystemExit("capacity or device error: counters=%s" % cnt.tolist())
+    queries = int(cnt[1])
+    # traversal kernel alone, eager, with the library's own events around its launch
+    ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+    kms = []
+    for _ in range(3):
+        rt.trace_batch(b, R, out=tr, check_capacity=False, kernel_events=ev, **tune)
+        torch.cuda.synchronize()
+        kms.append(ev[0].elapsed_time(ev[1]))
+    kernel_ms = sorted(kms)[1]
+    qj = queries_per_job(b, tr.hit_seq)
+    escapes = int(cnt[2])
+    nbytes = sum(int(q) * algorithmic_bytes_per_query(scenes[j["scene"]].n_tri) for q, j in zip(qj, jobs))
+    if escapes == 0:
+        assert int(qj.sum()) == queries, (int(qj.sum()), queries)
+    achieved = nbytes / (kernel_ms * 1e-3) / 1e9
+    out = {
+        "metric": "rays·bounces/s, 8 rooms x 8 pairs in one batched launch, IR + absorption gradient",
+        "value": queries / (ms * 1e-3), "unit": "rays·bounces/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 traversal, f64 shading/image sources/gradient, f32 MFMA FIR",
+        "data": "synthetic (seeded watertight lattice rooms; Fibonacci rays per pair)",
+        "config": {"workload": "8 rooms %s tris, 64 pairs x 2e5 rays, R=50, 1 s IR @48 kHz, 8 bands, K=4095, "
+                               "grad over %d alpha" % ([sc.n_tri for sc in scenes], b.n_mat * 8),
+                   "rays": b.n_rays, "max_reflections": R, "pairs": b.n_jobs},
+        "queries": queries, "detections": int(cnt[0]), "escapes": escapes, "image_sources": isb.n_is(),
+        "build_ms_once": build_ms, "graph_step": True, "autotuned": tune,
+        "trace_kernel_rays_bounces_per_s": queries / (kernel_ms * 1e-3),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_trace (batched)",
+                     "bytes_per_query": "76 + 48 ceil(log2 M_room) + 40 per job", "kernel_ms": kernel_ms},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_surrogate(args):
+    """Late-tail surrogate workload: trace seeded training rooms (1k to 50k
+    triangles, absorption 0.02..0.5, 1e5 rays, R = 60, T = 2 s), train the
+    512-256-256-256-1024 MLP, then compare on held-out rooms (a) the decay
+    curve predicted from orders 0..8 and (b) the one of the 8-bounce trace
+    alone against the full trace, and time full trace vs 8-bounce + MLP."""
+    import torch
+
+    import paper_1811_05784_amd as rt
+    import synth
+    from paper_1811_05784_amd import surrogate as sg
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    n_rooms = args.rooms
+    n_rays, R_full, T = 100_000, 60, 2.0
+    t0 = time.perf_counter()
+    xs, ts, ms_, bs = [], [], [], []
+    chunk = 100
+    for r0 in range(0, n_rooms, chunk):
+        rooms = synth.surrogate_rooms(n_rooms=min(n_rooms, r0 + chunk), first=r0)
+        x, tgt, mask, base = sg.dataset(rooms, n_rays, R_full, T=T, device=dev, rooms_per_batch=25)
+        xs.append(x)
+        ts.append(tgt)
+        ms_.append(mask)
+        bs.append(base)
+        print("surrogate data: %d/%d rooms, %.0f s" % (r0 + len(rooms), n_rooms, time.perf_counter() - t0),
+              file=sys.stderr, flush=True)
+    x, tgt, mask, base = (torch.cat(v) for v in (xs, ts, ms_, bs))
+    data_s = time.perf_counter() - t0
+    n_train = int(0.9 * n_rooms)
+    net = sg.Mlp(synth.mlp_init(5, sg.WIDTHS), sg.WIDTHS, max_batch=max(256, n_rooms - n_train), device=dev)
+    t0 = time.perf_counter()
+    val = (x[n_train:].contiguous(), tgt[n_train:].contiguous(), mask[n_train:].contiguous())
+    losses = sg.train(net, x[:n_train].contiguous(), tgt[:n_train].contiguous(), mask[:n_train].contiguous(),
+                      epochs=args.epochs, batch=256, lr=1e-3, log_every=max(1, args.epochs // 10), val=val)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    xe, te, be = x[n_train:].contiguous(), tgt[n_train:], base[n_train:]
+    pred = net.forward(xe)
+    e_mlp = sg.band_rms_db(pred, te).cpu().numpy()
+    e_base = sg.band_rms_db(be, te).cpu().numpy()
+    # timing on the held-out rooms: full 60-bounce trace vs 8 bounces + MLP
+    held = synth.surrogate_rooms(n_rooms=n_rooms, first=n_train)
+    timers = {}
+    sg.room_histograms(held, n_rays, (R_full, sg.EARLY_ORDER), (sg.TARGET_BINS, sg.FEAT_BINS), T=T, device=dev,
+                       rooms_per_batch=len(held), timers=timers, spans=(T, sg.FEAT_SECONDS))     # warm-up
+    timers = {}
+    h_full, h_early = sg.room_histograms(held, n_rays, (R_full, sg.EARLY_ORDER), (sg.TARGET_BINS, sg.FEAT_BINS),
+                                         T=T, device=dev, rooms_per_batch=len(held), timers=timers,
+                                         spans=(T, sg.FEAT_SECONDS))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    sg.edc_db(h_full)
+    e1.record()
+    torch.cuda.synchronize()
+    t_edc = e0.elapsed_time(e1)
+    e0.record()
+    yy = net.forward(sg.hist_features(h_early).reshape(len(held), -1))
+    e1.record()
+    torch.cuda.synchronize()
+    t_mlp = e0.elapsed_time(e1)
+    t_full = sum(timers[R_full]) + t_edc
+    t_sur = sum(timers[sg.EARLY_ORDER]) + t_mlp
+    # one training step (forward + backward + Adam) at batch 256: matrix-core rate
+    xb, tb, mb = x[:256].contiguous(), tgt[:256].contiguous(), mask[:256].contiguous()
+    for _ in range(3):
+        net.train_step(xb, tb, mb, 0.0)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(20):
+        net.train_step(xb, tb, mb, 0.0)
+    e1.record()
+    torch.cuda.synchronize()
+    step_ms = e0.elapsed_time(e1) / 20
+    macs = sum(i * j for i, j in zip(sg.WIDTHS[:-1], sg.WIDTHS[1:]))
+    flops = 2 * 256 * macs * 3 - 2 * 256 * sg.WIDTHS[0] * sg.WIDTHS[1]   # fwd + dW + dX (no dX for layer 1)
+    tflops = flops / (step_ms * 1e-3) / 1e12
+    out = {
+        "metric": "late-tail surrogate: speed-up of 8 bounces + MLP over the 60-bounce trace; RMS dB error",
+        "value": t_full / t_sur, "unit": "x (full trace time / surrogate time)", "n_gpus": 1,
+        "steps": 1, "warmup": 1, "ms_per_step": t_sur, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16 MFMA (fp32 accumulate, fp32 master weights); trace as theater",
+        "data": "synthetic (seeded lattice rooms, 1k-50k tris, alpha U[0.02,0.5]; Fibonacci rays)",
+        "config": {"workload": "%d rooms (90%% train / 10%% held out), 1 pair each, 1e5 rays, R=60, T=2 s; "
+                               "MLP 512-256-256-256-1024, Adam, %d epochs, batch 256" % (n_rooms, args.epochs)},
+        "held_out_rooms": len(held),
+        "full_trace_ms": t_full, "surrogate_ms": t_sur, "mlp_forward_ms": t_mlp,
+        "rms_db_mlp": {"mean": float(e_mlp.mean()), "median": float(np.median(e_mlp)),
+                       "per_band_mean": [float(v) for v in e_mlp.mean(0)],
+                       "frac_bands_le_0.5dB": float((e_mlp <= 0.5).mean())},
+        "rms_db_8_bounce_only": {"mean": float(e_base.mean()), "median": float(np.median(e_base))},
+        "train_loss_first_last": [losses[0], losses[-1]], "data_s": data_s, "train_s": train_s,
+        "roofline": {"bound": "mfma", "achieved": tflops, "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": tflops / 2500.0, "traffic": None, "kernel": "MLP train step (batch 256)",
+                     "step_ms": step_ms},
+    }
+    print(json.dumps(out), flush=True)
 
 
 def cpu_baseline(s, n_cpu):

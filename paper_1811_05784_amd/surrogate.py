@@ -3,8 +3,8 @@ rt_edc_db entry points and the pipeline from traces to network inputs and
 targets.
 
 The surrogate extends the method (it is not in the paper): the energy
-histogram of reflection orders 0..8 (8 bands x 64 bins on [0, T], dB) goes
-in, the per-band decay curve of the full trace (8 bands x 128 bins,
+histogram of reflection orders 0..8 (8 bands x 64 bins on [0, 0.25 s], dB)
+goes in, the per-band decay curve of the full trace (8 bands x 128 bins,
 Schroeder backward integration, dB re total) comes out.  Inference replaces
 the bounces after the 8th; the full trace stays available as the fallback.
 
@@ -27,6 +27,7 @@ P = ctypes.c_void_p
 WIDTHS = (512, 256, 256, 256, 1024)
 N_BANDS = 8
 FEAT_BINS = 64
+FEAT_SECONDS = 0.25      # feature histogram span: orders 0..8 arrive early, so 3.9 ms bins
 TARGET_BINS = 128
 EARLY_ORDER = 8
 FLOOR_DB = -150.0
@@ -154,11 +155,15 @@ def _delta(device) -> torch.Tensor:
 
 
 def room_histograms(rooms, n_rays: int, orders: Sequence[int], bins: Sequence[int], c: float = 343.0,
-                    T: float = 2.0, device=None, rooms_per_batch: int = 8, timers: Optional[Dict] = None):
+                    T: float = 2.0, device=None, rooms_per_batch: int = 8, timers: Optional[Dict] = None,
+                    spans: Optional[Sequence[float]] = None):
     """Per-band energy histograms of image sources for each room's (source,
-    receiver) pairs, one per (max reflection order, bin count) in
+    receiver) pairs (or, for a room with a single source, its receivers), one per (max reflection order, bin count) in
     zip(orders, bins): [n_pairs, 8, bins] each.  Rooms are traced in
-    batches of rooms_per_batch in one persistent launch."""
+    batches of rooms_per_batch in one persistent launch, once per distinct
+    order.  timers (a dict) collects the milliseconds per order and batch.
+    spans: time span in seconds of each histogram (default T for all)."""
+    spans = list(spans) if spans is not None else [T] * len(orders)
     dev = _dev(device)
     outs = [[] for _ in orders]
     delta = _delta(dev)
@@ -168,23 +173,29 @@ def room_histograms(rooms, n_rays: int, orders: Sequence[int], bins: Sequence[in
         scenes = [Scene.from_synth(r, device=dev) for r in chunk]
         jobs = []
         for i, r in enumerate(chunk):
-            for p in range(len(r.src)):
-                jobs.append(dict(scene=i, src=r.src[p], rcv=r.rcv[p:p + 1], n_rays=n_rays,
+            src = np.asarray(r.src, np.float32)
+            if src.ndim == 1:          # one source heard by all the scene's receivers
+                jobs.append(dict(scene=i, src=src, rcv=r.rcv, n_rays=n_rays,
+                                 max_path_length=c * T + float(np.max(r.rcv[:, 3]))))
+                continue
+            for p in range(len(src)):  # (source p, receiver p) pairs
+                jobs.append(dict(scene=i, src=src[p], rcv=r.rcv[p:p + 1], n_rays=n_rays,
                                  max_path_length=c * T + float(r.rcv[p, 3])))
         b = Batch(scenes, jobs, device=dev)
         alpha = torch.as_tensor(np.concatenate([r.alpha for r in chunk]), dtype=torch.float32, device=dev)
-        for o, (R, L) in enumerate(zip(orders, bins)):
+        for R in sorted(set(orders)):
             ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)] if timers is not None else None
             if ev:
                 ev[0].record()
             tr = trace_batch(b, R)
             isb = collect_batch(b, tr)
-            ir = assemble_batch(b, isb, alpha, beta, c, L / T, L, delta)
+            for o, (Ro, L) in enumerate(zip(orders, bins)):
+                if Ro == R:
+                    outs[o].append(assemble_batch(b, isb, alpha, beta, c, L / spans[o], L, delta).hist)
             if ev:
                 ev[1].record()
                 torch.cuda.synchronize()
-                timers.setdefault((R, L), []).append(ev[0].elapsed_time(ev[1]))
-            outs[o].append(ir.hist.clone())
+                timers.setdefault(R, []).append(ev[0].elapsed_time(ev[1]))
     return [torch.cat(x) for x in outs]
 
 
@@ -193,7 +204,8 @@ def dataset(rooms, n_rays: int, full_order: int = 60, c: float = 343.0, T: float
     """(features [n, 512] bf16, targets [n, 1024] f32 in dB, mask [n, 1024],
     early-only decay curve [n, 1024] dB) for the rooms' pairs."""
     early_f, early_t, full = room_histograms(rooms, n_rays, (EARLY_ORDER, EARLY_ORDER, full_order),
-                                             (FEAT_BINS, TARGET_BINS, TARGET_BINS), c, T, device, rooms_per_batch)
+                                             (FEAT_BINS, TARGET_BINS, TARGET_BINS), c, T, device, rooms_per_batch,
+                                             spans=(FEAT_SECONDS, T, T))
     n = full.shape[0]
     x = hist_features(early_f).reshape(n, N_BANDS * FEAT_BINS)
     tgt = edc_db(full).reshape(n, N_BANDS * TARGET_BINS)
@@ -211,10 +223,18 @@ def band_rms_db(pred: torch.Tensor, full: torch.Tensor, min_db: float = MASK_DB)
     return torch.sqrt((w * (p - f) ** 2).sum(-1) / w.sum(-1).clamp_min(1.0))
 
 
+def eval_loss(net: Mlp, x, tgt, mask) -> float:
+    """Masked mean squared error of the network on (x, tgt, mask)."""
+    y = net.forward(x)
+    m = mask.double()
+    return float(((y.double() - tgt.double()) ** 2 * m).sum() / m.sum().clamp_min(1.0))
+
+
 def train(net: Mlp, x, tgt, mask, epochs: int = 200, batch: int = 256, lr: float = 1e-3, seed: int = 0,
-          log_every: int = 0) -> List[float]:
+          log_every: int = 0, val=None) -> List[float]:
     """Adam on the masked squared error over shuffled minibatches, cosine
-    learning-rate decay; returns the mean training loss per epoch."""
+    learning-rate decay; returns the mean training loss per epoch.  val:
+    optional held-out (x, tgt, mask) whose loss is printed with the log."""
     n = x.shape[0]
     g = torch.Generator(device="cpu").manual_seed(seed)
     steps_per_epoch = max(1, n // batch)
@@ -235,5 +255,6 @@ def train(net: Mlp, x, tgt, mask, epochs: int = 200, batch: int = 256, lr: float
         a = acc.cpu()
         hist.append(float(a[0] / max(float(a[1]), 1.0)))
         if log_every and (ep % log_every == 0 or ep == epochs - 1):
-            print("epoch %d loss %.4f dB^2" % (ep, hist[-1]), flush=True)
+            v = " held-out %.4f" % eval_loss(net, *val) if val is not None else ""
+            print("epoch %d loss %.4f dB^2%s" % (ep, hist[-1], v), flush=True)
     return hist
