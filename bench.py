@@ -49,6 +49,8 @@ def main():
     ap.add_argument("--rounds", type=int, default=0)
     ap.add_argument("--spill", type=int, default=0)
     ap.add_argument("--wps", type=int, default=0, help="trace kernel waves per SIMD (4, 5, 6, 8)")
+    ap.add_argument("--suspend", type=int, default=0,
+                    help="queue rays continuing past this segment for a second launch (0 = off)")
     ap.add_argument("--stats", action="store_true", help="count traversal work (extra pass, not timed)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (counter calibration)")
@@ -116,7 +118,7 @@ def run_theater(args):
                            check_capacity=False, out=state.get("tr"), shade_threshold=args.shade,
                            fetch_threshold=args.fetch, blocks_per_cu=args.bpc, keep_order=args.keep_order,
                            rounds=args.rounds, spill_threshold=args.spill, waves_per_simd=args.wps,
-                           kernel_events=ev["k_trace"] if record else None)
+                           kernel_events=ev["k_trace"] if record else None, suspend_after=args.suspend)
         mark("trace", 1)
         state["tr"] = tr
         mark("collect", 0)

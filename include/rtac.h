@@ -117,6 +117,10 @@ typedef struct {
     void* kernel_event_start;  /* NULL or a hipEvent_t: recorded on `stream` just before the first
                                   traversal-kernel launch (after ray ordering and output fill)  */
     void* kernel_event_stop;   /* NULL or a hipEvent_t: recorded just after the last one        */
+    int32_t suspend_after;     /* 0 = off; S in [1, R]: two launches, the first traces segments
+                                  0..S-1 of every ray and queues the rays that continue, the second
+                                  finishes them all together (long bounce chains start at once).
+                                  Results are identical; overrides `rounds`                     */
 } rt_trace_params;
 
 /*

@@ -30,7 +30,7 @@ constexpr int kSpillChunk = 8;
 
 enum : int { kIdle = 0, kQuery = 1, kDone = 2 };
 
-enum : unsigned long long { kErrStack = 1ull, kErrNode = 2ull, kErrSteps = 4ull };
+enum : unsigned long long { kErrStack = 1ull, kErrNode = 2ull, kErrSteps = 4ull, kErrQueue = 8ull };
 
 struct TraceArgs {
     const Node4* nodes;
@@ -70,7 +70,9 @@ struct TraceArgs {
     const unsigned long long* q_in_count;
     int4* q_out;
     unsigned long long* q_out_count;
+    int64_t q_cap;                  // entries of q_in / q_out
     int32_t spill_thr;
+    int32_t suspend_k;              // > 0: a ray about to start segment >= suspend_k goes to q_out
     // batched calls: rays of many jobs (source + receivers in one scene)
     const DevJob* jobs;
     const DevScene* scenes;
@@ -234,7 +236,8 @@ k_trace(TraceArgs a) {
     uint32_t n_query = 0, n_escape = 0;
     uint32_t st_nodes = 0, st_leaves = 0, st_tris = 0, st_spill = 0;
     const bool want_stats = a.stats != nullptr;
-    const unsigned long long pool_n = a.q_in ? *a.q_in_count : (unsigned long long)a.n_rays;
+    unsigned long long pool_n = a.q_in ? *a.q_in_count : (unsigned long long)a.n_rays;
+    if (a.q_in && pool_n > (unsigned long long)a.q_cap) pool_n = (unsigned long long)a.q_cap;
     bool pool_empty = pool_n == 0;
 
     for (;;) {
@@ -537,6 +540,7 @@ k_trace(TraceArgs a) {
                 }
             }
         }
+        bool susp = false;
         if (shading) {
             n_query++;
             int32_t* hs = a.hit_seq + (int64_t)ray * R1;
@@ -583,6 +587,11 @@ k_trace(TraceArgs a) {
             }
             if (stop) {
                 status = kIdle;   // rest of the row keeps the -1 written by k_fill_rows
+            } else if (a.suspend_k > 0 && a.q_out && k + 1 >= a.suspend_k) {
+                // long chains: finish them in the next launch, all started together
+                k++;
+                susp = true;
+                status = kIdle;
             } else {
                 k++;
                 setup_ray(r);
@@ -593,6 +602,27 @@ k_trace(TraceArgs a) {
                 best_id = 0x7FFFFFFF;
                 steps = 0;
                 status = kQuery;
+            }
+        }
+        if (a.suspend_k > 0 && a.q_out) {
+            const uint64_t sm = __ballot(susp);
+            if (sm) {
+                const int leader = __ffsll((long long)sm) - 1;
+                unsigned long long base = 0;
+                if (lane == leader) base = atomicAdd(a.q_out_count, (unsigned long long)__popcll(sm));
+                base = __shfl(base, leader);
+                if (susp) {
+                    const unsigned long long pos = base + (unsigned long long)__popcll(sm & lt_mask);
+                    if (pos < (unsigned long long)a.q_cap) {
+                        int4* q = a.q_out + 3 * pos;
+                        q[0] = make_int4((int)ray, k, last_plane, 0);
+                        q[1] = make_int4(__float_as_int(r.ox), __float_as_int(r.oy), __float_as_int(r.oz),
+                                         __float_as_int(L));
+                        q[2] = make_int4(__float_as_int(r.ux), __float_as_int(r.uy), __float_as_int(r.uz), 0);
+                    } else {
+                        atomicOr(&a.counters[3], kErrQueue);
+                    }
+                }
             }
         }
     }
@@ -780,12 +810,17 @@ int run_trace(rt_scene* ws, TraceArgs& a, const rt_trace_params* p, int depth, i
     }
     // continuation rounds: launch rd takes the rays left over by launch rd-1;
     // every launch hands over at most one ray per lane, so a queue of one
-    // entry per lane of the grid never overflows
-    const int rounds = p->rounds > 0 ? (p->rounds < 16 ? p->rounds : 16) : 1;
+    // entry per lane of the grid never overflows.  With suspension, launch 0
+    // traces every ray up to segment suspend_after - 1 and queues the rays
+    // that go on (at most all of them); launch 1 finishes those together.
+    const bool suspend = p->suspend_after > 0 && p->suspend_after <= p->max_reflections;
+    const int rounds = suspend ? 2 : (p->rounds > 0 ? (p->rounds < 16 ? p->rounds : 16) : 1);
     const int64_t lanes = nblk * kBlock;
-    if (ws->ws.generic[0].ensure(sizeof(int32_t) * kQueueInts * (size_t)lanes * 2)) return RT_ENOMEM;
-    int4* qbuf[2] = {ws->ws.generic[0].as<int4>(), ws->ws.generic[0].as<int4>() + 3 * lanes};
-    a.spill_thr = p->spill_threshold > 0 ? p->spill_threshold : 24;
+    const int64_t qcap = suspend ? (n_rays > lanes ? n_rays : lanes) : lanes;
+    if (ws->ws.generic[0].ensure(sizeof(int32_t) * kQueueInts * (size_t)qcap * 2)) return RT_ENOMEM;
+    int4* qbuf[2] = {ws->ws.generic[0].as<int4>(), ws->ws.generic[0].as<int4>() + 3 * qcap};
+    a.q_cap = qcap;
+    const int32_t spill_thr = p->spill_threshold > 0 ? p->spill_threshold : 24;
     unsigned long long* pool = a.pool;
     if (p->kernel_event_start) RT_HIP(hipEventRecord((hipEvent_t)p->kernel_event_start, st));
     for (int rd = 0; rd < rounds; rd++) {
@@ -794,6 +829,8 @@ int run_trace(rt_scene* ws, TraceArgs& a, const rt_trace_params* p, int depth, i
         a.q_in_count = rd == 0 ? nullptr : pool + 16 + (rd - 1);
         a.q_out = rd + 1 < rounds ? qbuf[rd & 1] : nullptr;
         a.q_out_count = pool + 16 + rd;
+        a.suspend_k = suspend && rd == 0 ? p->suspend_after : 0;
+        a.spill_thr = suspend ? 0 : spill_thr;
         if (rd > 0) a.order = nullptr;
         launch_trace(occ, a.jobs != nullptr, (unsigned)nblk, st, a);
     }
@@ -806,6 +843,7 @@ int check_params(const rt_trace_params* p) {
     RT_CHECK(p, RT_EINVAL, "null params");
     RT_CHECK(p->max_reflections >= 0 && p->max_reflections < 4096, RT_EINVAL,
              "max_reflections must be in [0, 4096)");
+    RT_CHECK(p->suspend_after >= 0, RT_EINVAL, "suspend_after must be >= 0");
     return RT_OK;
 }
 

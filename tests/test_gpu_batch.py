@@ -178,3 +178,12 @@ def test_autotuner_picks_and_caches(rt, setup, tmp_path, monkeypatch):
     ref = rt.trace_batch(b, R).hit_seq
     got = rt.trace_batch(b, R, **best).hit_seq
     assert torch.equal(ref, got)
+
+
+def test_batch_suspension_unchanged(rt, setup):
+    rooms, scenes, jobs, b = setup
+    a = rt.trace_batch(b, R)
+    s = rt.trace_batch(b, R, suspend_after=2)
+    assert torch.equal(a.hit_seq, s.hit_seq) and torch.equal(a.counters[:3], s.counters[:3])
+    da, ds = a.detections().cpu().numpy(), s.detections().cpu().numpy()
+    assert np.array_equal(da[np.lexsort(da.T[::-1])], ds[np.lexsort(ds.T[::-1])])

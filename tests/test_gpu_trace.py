@@ -213,3 +213,26 @@ def test_edge_cases(rt, scenes):
     assert need > 16
     full = rt.trace_rays(sc, dirs, s.rcv, 20, src=s.src, det_cap=16)
     assert full.n_det() == need and full.det.shape[0] >= need
+
+
+def _sorted_det(tr):
+    d = tr.detections().cpu().numpy()
+    return d[np.lexsort(d.T[::-1])]
+
+
+@pytest.mark.parametrize("name,R,n,kw", [("c2", 20, 50_000, dict(suspend_after=1)),
+                                         ("c2", 20, 50_000, dict(suspend_after=3)),
+                                         ("c2", 20, 50_000, dict(suspend_after=20)),
+                                         ("c2", 20, 50_000, dict(rounds=3, spill_threshold=40)),
+                                         ("c3", 60, 200_000, dict(suspend_after=2))])
+def test_scheduling_leaves_results_unchanged(rt, scenes, name, R, n, kw):
+    """Suspension into a second launch and continuation rounds reorder work
+    only: hit sequences, detections and counters are identical."""
+    s, sc = scenes[name]
+    dirs = rt.fibonacci_directions(n, device="cuda:0")
+    mpl = s.max_path_length if name == "c3" else 0.0
+    a = rt.trace_rays(sc, dirs, s.rcv, R, src=s.src, max_path_length=mpl)
+    b = rt.trace_rays(sc, dirs, s.rcv, R, src=s.src, max_path_length=mpl, **kw)
+    assert torch.equal(a.hit_seq, b.hit_seq)
+    assert torch.equal(a.counters[:3], b.counters[:3]) and int(b.counters[3]) == 0
+    assert np.array_equal(_sorted_det(a), _sorted_det(b))
