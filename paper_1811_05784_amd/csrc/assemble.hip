@@ -201,6 +201,133 @@ __global__ void __launch_bounds__(256) k_fir_mfma(const float* __restrict__ hist
     }
 }
 
+// ---------------------------------------------------------------------------
+// FIR by FFT (overlap-save) for long filters
+// ---------------------------------------------------------------------------
+// N = 4^7-point transforms held in LDS, in place: the forward transform is
+// radix-4 decimation in frequency (output in base-4 digit-reversed order),
+// the inverse is its exact stage-by-stage inverse (decimation in time from
+// digit-reversed input to natural order), so the pointwise product with a
+// filter spectrum computed the same way needs no permutation.  Two
+// consecutive segments of one band signal ride as the real and imaginary
+// parts of one transform (the taps are real).  A segment of N samples yields
+// N - K + 1 outputs of the 'same'-aligned convolution.
+constexpr int kFftLog4 = 7;
+constexpr int kFftN = 1 << (2 * kFftLog4);
+constexpr int kFftThreads = 1024;
+constexpr int kFirFftMinK = 1024;
+
+__device__ inline float2 cmulf(float2 a, float2 b) { return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__device__ inline float2 cmulf_conj(float2 a, float2 b) {   // a * conj(b)
+    return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__device__ inline float2 addf2(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ inline float2 subf2(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+
+// tw[m] = exp(-2 pi i m / N), FP64 rounded once
+__global__ void k_fft_twiddles(float2* __restrict__ tw) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= kFftN) return;
+    double s, c;
+    sincos(-2.0 * 3.14159265358979323846 * (double)m / (double)kFftN, &s, &c);
+    tw[m] = make_float2((float)c, (float)s);
+}
+
+// Stage s works on blocks of M = N / 4^s with quarter q = M / 4; output k of
+// the butterfly at offset j gets the twiddle w_M^(j k) = tw[j k 4^s].
+__device__ inline void fft_dif(float2* x, const float2* __restrict__ tw) {
+    for (int s = 0; s < kFftLog4; s++) {
+        const int lq = 2 * (kFftLog4 - 1 - s);   // log2 q
+        const int q = 1 << lq;
+        for (int u = threadIdx.x; u < kFftN / 4; u += kFftThreads) {
+            const int j = u & (q - 1);
+            const int base = ((u >> lq) << (lq + 2)) + j;
+            const float2 a0 = x[base], a1 = x[base + q], a2 = x[base + 2 * q], a3 = x[base + 3 * q];
+            const float2 t0 = addf2(a0, a2), t1 = subf2(a0, a2), t2 = addf2(a1, a3), d = subf2(a1, a3);
+            const float2 t3 = make_float2(d.y, -d.x);   // -i d
+            const int e = j << (2 * s);
+            x[base] = addf2(t0, t2);
+            x[base + q] = cmulf(addf2(t1, t3), tw[e]);
+            x[base + 2 * q] = cmulf(subf2(t0, t2), tw[2 * e]);
+            x[base + 3 * q] = cmulf(subf2(t1, t3), tw[3 * e]);
+        }
+        __syncthreads();
+    }
+}
+
+// Inverse of fft_dif up to the factor N (undo the twiddles, 4-point inverse
+// transform, stages in reverse order).
+__device__ inline void fft_dit_inv(float2* x, const float2* __restrict__ tw) {
+    for (int s = kFftLog4 - 1; s >= 0; s--) {
+        const int lq = 2 * (kFftLog4 - 1 - s);
+        const int q = 1 << lq;
+        for (int u = threadIdx.x; u < kFftN / 4; u += kFftThreads) {
+            const int j = u & (q - 1);
+            const int base = ((u >> lq) << (lq + 2)) + j;
+            const int e = j << (2 * s);
+            const float2 a0 = x[base];
+            const float2 a1 = cmulf_conj(x[base + q], tw[e]);
+            const float2 a2 = cmulf_conj(x[base + 2 * q], tw[2 * e]);
+            const float2 a3 = cmulf_conj(x[base + 3 * q], tw[3 * e]);
+            const float2 t0 = addf2(a0, a2), t1 = subf2(a0, a2), t2 = addf2(a1, a3), d = subf2(a1, a3);
+            const float2 t3 = make_float2(-d.y, d.x);   // i d
+            x[base] = addf2(t0, t2);
+            x[base + q] = addf2(t1, t3);
+            x[base + 2 * q] = subf2(t0, t2);
+            x[base + 3 * q] = subf2(t1, t3);
+        }
+        __syncthreads();
+    }
+}
+
+// spec[b] = forward transform of the zero-padded taps of band b, times 1 / N
+__global__ void __launch_bounds__(kFftThreads) k_fir_spectrum(const float* __restrict__ fir, int K,
+                                                               const float2* __restrict__ tw,
+                                                               float2* __restrict__ spec) {
+    extern __shared__ float2 xs[];
+    const int b = blockIdx.x;
+    for (int i = threadIdx.x; i < kFftN; i += kFftThreads)
+        xs[i] = make_float2(i < K ? fir[(int64_t)b * K + i] : 0.f, 0.f);
+    __syncthreads();
+    fft_dif(xs, tw);
+    const float inv = 1.0f / (float)kFftN;
+    for (int i = threadIdx.x; i < kFftN; i += kFftThreads)
+        spec[(int64_t)b * kFftN + i] = make_float2(xs[i].x * inv, xs[i].y * inv);
+}
+
+// grid: (ceil(n_seg / 2), n_rcv * 8); segment g covers outputs [g B, g B + B)
+// with B = N - K + 1 and reads samples from g B - (K - 1) / 2.
+__global__ void __launch_bounds__(kFftThreads) k_fir_fft(const float* __restrict__ hist,
+                                                          const float2* __restrict__ spec,
+                                                          const float2* __restrict__ tw, int K, int64_t L,
+                                                          float* __restrict__ band_ir) {
+    extern __shared__ float2 xs[];
+    const int sig = blockIdx.y;
+    const int band = sig & 7;
+    const int64_t B = kFftN - K + 1;
+    const int c = (K - 1) / 2;
+    const int64_t n0a = (int64_t)(2 * blockIdx.x) * B, n0b = n0a + B;
+    const float* x = hist + (int64_t)sig * L;
+    for (int i = threadIdx.x; i < kFftN; i += kFftThreads) {
+        const int64_t ga = n0a - c + i, gb = n0b - c + i;
+        const float va = (ga >= 0 && ga < L) ? sqrtf(x[ga]) : 0.f;
+        const float vb = (n0b < L && gb >= 0 && gb < L) ? sqrtf(x[gb]) : 0.f;
+        xs[i] = make_float2(va, vb);
+    }
+    __syncthreads();
+    fft_dif(xs, tw);
+    const float2* hs = spec + (int64_t)band * kFftN;
+    for (int i = threadIdx.x; i < kFftN; i += kFftThreads) xs[i] = cmulf(xs[i], hs[i]);
+    __syncthreads();
+    fft_dit_inv(xs, tw);
+    float* y = band_ir + (int64_t)sig * L;
+    for (int64_t t = threadIdx.x; t < B; t += kFftThreads) {
+        const float2 v = xs[K - 1 + t];
+        if (n0a + t < L) y[n0a + t] = v.x;
+        if (n0b + t < L) y[n0b + t] = v.y;
+    }
+}
+
 __global__ void k_sum_bands(const float* __restrict__ band_ir, int64_t L, int32_t n_rcv, float* __restrict__ ir) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (int64_t)n_rcv * L) return;
@@ -382,18 +509,39 @@ int assemble_common(const rt_scene* scene, const rt_batch* bt, const int32_t* is
     hipLaunchKernelGGL(k_fill_f32, dim3(nblk(hn)), dim3(256), 0, st, hist, hn, 0.f);
     hipLaunchKernelGGL(k_bin_sum, dim3(nblk_gs(cap)), dim3(256), 0, st, a, which ? k1 : k0, which ? v1 : v0, E, hist);
     hipLaunchKernelGGL(k_band_energy, dim3(n_rcv * 8), dim3(1024), 0, st, hist, L, band_energy);
-    const int Kpad = K + 112;
-    const int Smax = (K + 15 + 15 + 3) / 4;
-    const int W = kFirOut + 4 * Smax + 16;
-    const size_t shm = sizeof(float) * ((size_t)Kpad + (size_t)((W >> 4) + 2) * 20);
-    RT_CHECK(shm <= 160 * 1024, RT_EINVAL, "rt_assemble_ir: FIR taps too long for LDS");
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipFuncSetAttribute((const void*)k_fir_mfma, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        attr_set = true;
+    if (K >= kFirFftMinK && K <= kFftN / 2) {
+        // long filters: overlap-save FFT convolution
+        if (ws.fir_twiddle.ensure(sizeof(float2) * kFftN) || ws.fir_spec.ensure(sizeof(float2) * 8 * kFftN))
+            return RT_ENOMEM;
+        static bool fft_attr_set = false;
+        const size_t fshm = sizeof(float2) * kFftN;
+        if (!fft_attr_set) {
+            hipFuncSetAttribute((const void*)k_fir_spectrum, hipFuncAttributeMaxDynamicSharedMemorySize, (int)fshm);
+            hipFuncSetAttribute((const void*)k_fir_fft, hipFuncAttributeMaxDynamicSharedMemorySize, (int)fshm);
+            fft_attr_set = true;
+        }
+        float2* tw = ws.fir_twiddle.as<float2>();
+        float2* spec = ws.fir_spec.as<float2>();
+        hipLaunchKernelGGL(k_fft_twiddles, dim3(kFftN / 256), dim3(256), 0, st, tw);
+        hipLaunchKernelGGL(k_fir_spectrum, dim3(8), dim3(kFftThreads), fshm, st, fir, K, tw, spec);
+        const int64_t B = kFftN - K + 1;
+        const int64_t n_seg = (L + B - 1) / B;
+        dim3 fgrid((unsigned)((n_seg + 1) / 2), (unsigned)(n_rcv * 8));
+        hipLaunchKernelGGL(k_fir_fft, fgrid, dim3(kFftThreads), fshm, st, hist, spec, tw, K, L, band_ir);
+    } else {
+        const int Kpad = K + 112;
+        const int Smax = (K + 15 + 15 + 3) / 4;
+        const int W = kFirOut + 4 * Smax + 16;
+        const size_t shm = sizeof(float) * ((size_t)Kpad + (size_t)((W >> 4) + 2) * 20);
+        RT_CHECK(shm <= 160 * 1024, RT_EINVAL, "rt_assemble_ir: FIR taps too long for LDS");
+        static bool attr_set = false;
+        if (!attr_set) {
+            hipFuncSetAttribute((const void*)k_fir_mfma, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            attr_set = true;
+        }
+        dim3 grid((unsigned)((L + kFirOut - 1) / kFirOut), (unsigned)(n_rcv * 8));
+        hipLaunchKernelGGL(k_fir_mfma, grid, dim3(256), shm, st, hist, fir, K, L, band_ir);
     }
-    dim3 grid((unsigned)((L + kFirOut - 1) / kFirOut), (unsigned)(n_rcv * 8));
-    hipLaunchKernelGGL(k_fir_mfma, grid, dim3(256), shm, st, hist, fir, K, L, band_ir);
     hipLaunchKernelGGL(k_sum_bands, dim3(nblk((int64_t)n_rcv * L)), dim3(256), 0, st, band_ir, L, n_rcv, ir);
     RT_HIP(hipGetLastError());
     return RT_OK;

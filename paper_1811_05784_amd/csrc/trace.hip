@@ -445,7 +445,7 @@ k_trace(TraceArgs a) {
             // descend into the nearest inner child, push the others far to near
             const int nearest = inner ? __ffs(inner) - 1 : -1;
             bool ok = true;
-            if (want_stats && st.cnt + __popc(inner) - 1 > kRing) st_spill++;
+            if (want_stats && st.cnt + (int)__popc(inner) - 1 > kRing) st_spill++;
 #pragma unroll
             for (int sl = 3; sl >= 1; sl--)
                 if (((inner >> sl) & 1u) && sl != nearest)

@@ -113,8 +113,12 @@ def _is_from_table(rt, sc, arr, tab, R):
 
 
 @pytest.mark.parametrize("n_is,R,n_rcv,L,K", [(1, 0, 1, 1, 1), (3000, 10, 2, 5000, 63), (40_000, 30, 3, 48_000, 4095),
-                                             (20_000, 20, 8, 24_321, 1023)])
+                                             (20_000, 20, 8, 24_321, 1023), (5000, 12, 1, 1000, 1025),
+                                             (30_000, 25, 5, 37_001, 8191), (2, 3, 2, 7, 2049)])
 def test_assemble_parity(rt, oracle_lib, c2, n_is, R, n_rcv, L, K):
+    """K >= 1024 takes the overlap-save FFT path (16384-point segments; one
+    segment, several, and the longest filter), shorter filters the direct
+    matrix-core path."""
     s, sc = c2
     n_rays = 1_000_000
     tab, arr = synthetic_is_table(s, n_is, R, n_rcv, seed=n_is + L, L=L, c=s.c, fs=s.fs, n_rays=n_rays)
