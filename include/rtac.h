@@ -341,7 +341,7 @@ int rt_hist_features(const float* hist, int64_t n, float floor_db, float offset_
 int rt_edc_db(const float* hist, int64_t rows, int32_t bins, float floor_db, float* edc, void* stream);
 
 /* Test hook for the exact-grouping path of rt_collect_image_sources: keep
- * only the low `bits` bits (1..64, default 64) of the 64-bit key hash so that
+ * only the low `bits` bits (1..64, default 32) of the 64-bit key hash so that
  * distinct keys collide.  Process-wide; not thread-safe with concurrent
  * collect calls.  Grouping stays exact at any setting (full-key comparison);
  * only speed changes. */

@@ -59,6 +59,10 @@ __global__ void __launch_bounds__(256) k_tri_prep(const float* __restrict__ vtx,
     }
     __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + tid;
+    // this lane's contribution to the 12 bounds (identity when it has none)
+    uint32_t bl[12];
+    for (int k = 0; k < 12; k++) bl[k] = (k % 6) < 3 ? 0xFFFFFFFFu : 0u;
+    uint32_t mat_l = 0;
     if (i < nt) {
         const int3 t = tri[i];
         uint32_t err = 0;
@@ -88,7 +92,7 @@ __global__ void __launch_bounds__(256) k_tri_prep(const float* __restrict__ vtx,
             const double cy = e1[2] * e2[0] - e1[0] * e2[2];
             const double cz = e1[0] * e2[1] - e1[1] * e2[0];
             if (cx == 0.0 && cy == 0.0 && cz == 0.0) err |= kErrZeroArea;
-            atomicMax(&s_mat, (uint32_t)m);
+            mat_l = (uint32_t)m;
             if ((int32_t)i < prep[p]) atomicMin(&prep[p], (int32_t)i);   // stale reads only add atomics
             for (int c = 0; c < 3; c++) {
                 const float lo = fminf(v[0][c], fminf(v[1][c], v[2][c]));
@@ -97,10 +101,10 @@ __global__ void __launch_bounds__(256) k_tri_prep(const float* __restrict__ vtx,
                 tri_box[6 * i + 3 + c] = hi;
                 const float cen = (v[0][c] + v[1][c] + v[2][c]) * (1.0f / 3.0f);
                 centroid[3 * i + c] = cen;
-                atomicMin(&sb[c], ford(lo));
-                atomicMax(&sb[3 + c], ford(hi));
-                atomicMin(&sb[6 + c], ford(cen));
-                atomicMax(&sb[9 + c], ford(cen));
+                bl[c] = ford(lo);
+                bl[3 + c] = ford(hi);
+                bl[6 + c] = ford(cen);
+                bl[9 + c] = ford(cen);
             }
         } else {
             for (int c = 0; c < 3; c++) {
@@ -110,6 +114,22 @@ __global__ void __launch_bounds__(256) k_tri_prep(const float* __restrict__ vtx,
             }
         }
         if (err) atomicOr(&s_err, err);
+    }
+    // wave reductions, then one LDS atomic per wave and bound
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        for (int k = 0; k < 12; k++) {
+            const uint32_t o = __shfl_down(bl[k], off);
+            bl[k] = (k % 6) < 3 ? (o < bl[k] ? o : bl[k]) : (o > bl[k] ? o : bl[k]);
+        }
+        const uint32_t om = __shfl_down(mat_l, off);
+        mat_l = om > mat_l ? om : mat_l;
+    }
+    if ((tid & (kWave - 1)) == 0) {
+        for (int k = 0; k < 12; k++) {
+            if ((k % 6) < 3) atomicMin(&sb[k], bl[k]);
+            else atomicMax(&sb[k], bl[k]);
+        }
+        atomicMax(&s_mat, mat_l);
     }
     __syncthreads();
     if (tid < 12) {
@@ -192,8 +212,9 @@ __device__ inline uint64_t spread21(uint64_t x) {
     return x;
 }
 
-// 63-bit Morton code of the centroid, quantised on a cube spanning the
-// centroid box (equal cells on every axis).
+// 48-bit Morton code of the centroid, quantised to 2^16 cells per axis on a
+// cube spanning the centroid box (equal cells on every axis; equal codes are
+// ordered by triangle index).
 __global__ void k_morton(const float* __restrict__ centroid, int64_t nt, const uint32_t* __restrict__ bounds,
                          uint64_t* __restrict__ code) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -203,11 +224,11 @@ __global__ void k_morton(const float* __restrict__ centroid, int64_t nt, const u
         lo[c] = funord(bounds[6 + c]);
         ext = fmaxf(ext, funord(bounds[9 + c]) - lo[c]);
     }
-    const float scale = ext > 0.f ? 2097151.0f / ext : 0.f;
+    const float scale = ext > 0.f ? 65535.0f / ext : 0.f;
     uint64_t q[3];
     for (int c = 0; c < 3; c++) {
         float f = (centroid[3 * i + c] - lo[c]) * scale;
-        f = fminf(fmaxf(f, 0.f), 2097151.0f);
+        f = fminf(fmaxf(f, 0.f), 65535.0f);
         q[c] = (uint64_t)f;
     }
     code[i] = (spread21(q[0]) << 2) | (spread21(q[1]) << 1) | spread21(q[2]);
@@ -343,14 +364,12 @@ __global__ void k_flag4(int64_t n_in, const int32_t* __restrict__ first, const i
     flag[i] = (size > leaf_size && (depth & 1) == 0) ? 1u : 0u;
 }
 
-__global__ void k_emit4(int64_t n_in, const int32_t* __restrict__ left, const int32_t* __restrict__ right,
-                        const int32_t* __restrict__ first, const int32_t* __restrict__ last,
-                        const uint32_t* __restrict__ flag, const uint32_t* __restrict__ index,
-                        const int32_t* __restrict__ depth_in, const float* __restrict__ box_in,
-                        const float* __restrict__ tri_box, const uint32_t* __restrict__ order, int32_t leaf_size,
-                        Node4* __restrict__ nodes, uint32_t* __restrict__ info) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_in || !flag[i]) return;
+// Writes the 4-wide node of flagged binary node i; returns its depth level.
+__device__ inline uint32_t emit4_one(int64_t i, const int32_t* __restrict__ left, const int32_t* __restrict__ right,
+                                     const int32_t* __restrict__ first, const int32_t* __restrict__ last,
+                                     const uint32_t* __restrict__ index, const int32_t* __restrict__ depth_in,
+                                     const float* __restrict__ box_in, const float* __restrict__ tri_box,
+                                     const uint32_t* __restrict__ order, int32_t leaf_size, Node4* __restrict__ nodes) {
     int32_t slot_ref[4];
     float slot_box[4][6];
     int ns = 0;
@@ -395,7 +414,25 @@ __global__ void k_emit4(int64_t n_in, const int32_t* __restrict__ left, const in
         nd.pad[s] = 0;
     }
     nodes[index[i]] = nd;
-    atomicMax(&info[2], (uint32_t)(depth_in[i] / 2 + 1));
+    return (uint32_t)(depth_in[i] / 2 + 1);
+}
+
+__global__ void k_emit4(int64_t n_in, const int32_t* __restrict__ left, const int32_t* __restrict__ right,
+                        const int32_t* __restrict__ first, const int32_t* __restrict__ last,
+                        const uint32_t* __restrict__ flag, const uint32_t* __restrict__ index,
+                        const int32_t* __restrict__ depth_in, const float* __restrict__ box_in,
+                        const float* __restrict__ tri_box, const uint32_t* __restrict__ order, int32_t leaf_size,
+                        Node4* __restrict__ nodes, uint32_t* __restrict__ info) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t d = 0;
+    if (i < n_in && flag[i])
+        d = emit4_one(i, left, right, first, last, index, depth_in, box_in, tri_box, order, leaf_size, nodes);
+    // tree depth: one atomic per wavefront
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        const uint32_t o = __shfl_down(d, off);
+        d = o > d ? o : d;
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0 && d) atomicMax(&info[2], d);
 }
 
 // Root made of a single leaf (the whole mesh fits one leaf).
@@ -534,7 +571,7 @@ extern "C" int rt_build_tree(const float* vtx, int64_t n_vtx, const int32_t* tri
                        plane_id, s->plane_n, s->plane_p, s->plane_mat, bounds, s->tri_plane, info);
     hipLaunchKernelGGL(k_morton, dim3(blocks(nt)), dim3(256), 0, st, cen, nt, bounds, codes0);
     int which = 0;
-    int rc = radix_sort_pairs(s->ws, codes0, ord0, codes1, ord1, nt, nullptr, 0, 64, st, &which, true);
+    int rc = radix_sort_pairs(s->ws, codes0, ord0, codes1, ord1, nt, nullptr, 0, 48, st, &which, true);
     if (rc) return fail(rc);
     uint64_t* codes = which ? codes1 : codes0;
     uint32_t* order = which ? ord1 : ord0;

@@ -15,7 +15,7 @@ namespace rtac {
 
 namespace {
 
-int g_hash_bits = 64;   // test hook: fewer bits force hash collisions
+int g_hash_bits = 32;   // key hash width (keys are compared in full); the test hook lowers it
 
 __device__ inline uint64_t mix64(uint64_t x) {
     x ^= x >> 30;

@@ -3,8 +3,9 @@
 // producer kernel's count never has to come back to the host.
 //
 // Radix sort: 8-bit digits; per pass (1) per-tile digit histograms, (2) one
-// workgroup scans the digit-major histogram table, (3) each tile ranks its
-// keys stably (wave ballots on the 8 digit bits give each lane its peers,
+// workgroup per digit scans that digit's row of tile counts and records the
+// row total, (3) each tile scans the 256 row totals into digit bases, ranks
+// its keys stably (wave ballots on the 8 digit bits give each lane its peers,
 // per-wave counts are combined in LDS in wave order) and scatters.
 #include "common.h"
 
@@ -101,21 +102,81 @@ __global__ void __launch_bounds__(1024) k_scan_single(uint32_t* __restrict__ a, 
     if (total && tid == 0) *total = carry;
 }
 
+// Row d of the digit-major table (tile counts of digit d) -> exclusive
+// prefix over tiles, in place; rowtot[d] = the row's total.
+__global__ void __launch_bounds__(kThreads) k_row_scan(uint32_t* __restrict__ hist, int64_t cap, const int64_t* n_dev,
+                                                        uint32_t* __restrict__ rowtot) {
+    __shared__ uint32_t wsum[kWaves];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const int used = used_tiles(count_of(n_dev, cap));
+    uint32_t* row = hist + (int64_t)blockIdx.x * used;
+    uint32_t carry = 0;
+    for (int base = 0; base < used; base += kThreads * 4) {
+        const int i0 = base + 4 * tid;
+        uint32_t v[4], t = 0;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            v[j] = i0 + j < used ? row[i0 + j] : 0u;
+            t += v[j];
+        }
+        uint32_t incl = t;
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const uint32_t x = __shfl_up(incl, off);
+            if (lane >= off) incl += x;
+        }
+        if (lane == kWave - 1) wsum[wave] = incl;
+        __syncthreads();
+        uint32_t before = 0, round = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; w++) {
+            before += w < wave ? wsum[w] : 0u;
+            round += wsum[w];
+        }
+        uint32_t run = carry + before + incl - t;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            if (i0 + j < used) row[i0 + j] = run;
+            run += v[j];
+        }
+        carry += round;
+        __syncthreads();
+    }
+    if (tid == 0) rowtot[blockIdx.x] = carry;
+}
+
 __global__ void __launch_bounds__(kThreads) k_rank_scatter(const uint64_t* __restrict__ kin,
                                                             const uint32_t* __restrict__ vin,
                                                             uint64_t* __restrict__ kout,
                                                             uint32_t* __restrict__ vout, int64_t cap,
                                                             const int64_t* n_dev, int shift,
-                                                            const uint32_t* __restrict__ offs) {
+                                                            const uint32_t* __restrict__ offs,
+                                                            const uint32_t* __restrict__ rowtot) {
     __shared__ uint32_t run[256];
     __shared__ uint32_t wcnt[kWaves][256];
+    __shared__ uint32_t wtot[kWaves];
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wave = tid / kWave;
     const int64_t n = count_of(n_dev, cap);
     const int64_t base = (int64_t)blockIdx.x * kTile;
     if (base >= n) return;   // whole workgroup leaves together
-    run[tid] = offs[(int64_t)tid * used_tiles(n) + blockIdx.x];
+    {
+        // digit bases: exclusive scan of the 256 row totals
+        const uint32_t t = rowtot[tid];
+        uint32_t incl = t;
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const uint32_t x = __shfl_up(incl, off);
+            if (lane >= off) incl += x;
+        }
+        if (lane == kWave - 1) wtot[wave] = incl;
+        __syncthreads();
+        uint32_t before = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; w++) before += w < wave ? wtot[w] : 0u;
+        run[tid] = offs[(int64_t)tid * used_tiles(n) + blockIdx.x] + before + incl - t;
+    }
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int i = 0; i < kItems; i++) {
         const int64_t idx = base + (int64_t)i * kThreads + tid;
@@ -216,8 +277,9 @@ int radix_sort_pairs(Workspace& ws, uint64_t* k0, uint32_t* v0, uint64_t* k1, ui
     if (cap <= 0) return RT_OK;
     const int nblocks = (int)((cap + kTile - 1) / kTile);
     const int64_t hlen = (int64_t)256 * nblocks;
-    if (ws.sort_hist.ensure(sizeof(uint32_t) * (size_t)hlen)) return RT_ENOMEM;
+    if (ws.sort_hist.ensure(sizeof(uint32_t) * (size_t)(hlen + 256))) return RT_ENOMEM;
     uint32_t* hist = ws.sort_hist.as<uint32_t>();
+    uint32_t* rowtot = hist + hlen;
     uint64_t* kin = k0;
     uint32_t* vin = v0;
     uint64_t* kout = k1;
@@ -226,11 +288,10 @@ int radix_sort_pairs(Workspace& ws, uint64_t* k0, uint32_t* v0, uint64_t* k1, ui
     bool first = true;
     for (int shift = begin_bit; shift < end_bit; shift += 8) {
         hipLaunchKernelGGL(k_digit_hist, dim3(nblocks), dim3(kThreads), 0, st, kin, cap, n_dev, shift, hist);
-        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, st, hist, hlen, n_dev, cap, 256,
-                           (uint32_t*)nullptr);
+        hipLaunchKernelGGL(k_row_scan, dim3(256), dim3(kThreads), 0, st, hist, cap, n_dev, rowtot);
         hipLaunchKernelGGL(k_rank_scatter, dim3(nblocks), dim3(kThreads), 0, st, kin,
                            first && iota_values ? (const uint32_t*)nullptr : vin, kout, vout, cap, n_dev,
-                           shift, hist);
+                           shift, hist, rowtot);
         first = false;
         std::swap(kin, kout);
         std::swap(vin, vout);

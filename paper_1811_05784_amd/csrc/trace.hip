@@ -649,8 +649,8 @@ k_trace(TraceArgs a) {
     }
 }
 
-// Sort key of a ray: Morton code of its direction's octahedral map (16 bits
-// per axis) in the low 32 bits and, for per-ray origins, the Morton code of
+// Sort key of a ray: Morton code of its direction's octahedral map (8 bits
+// per axis) in the low 16 bits and, for per-ray origins, the Morton code of
 // the origin in the scene box (10 bits per axis) above it.
 __device__ inline uint32_t spread16(uint32_t x) {
     x &= 0xFFFFu;
@@ -689,7 +689,7 @@ __global__ void k_ray_keys(const float* __restrict__ dirs, const float* __restri
         u = fminf(fmaxf((x + 1.f) * 0.5f, 0.f), 1.f);
         v = fminf(fmaxf((y + 1.f) * 0.5f, 0.f), 1.f);
     }
-    const uint32_t qu = (uint32_t)(u * 65535.f), qv = (uint32_t)(v * 65535.f);
+    const uint32_t qu = (uint32_t)(u * 255.f), qv = (uint32_t)(v * 255.f);
     uint64_t k = (uint64_t)(spread16(qu) | (spread16(qv) << 1));
     if (origins) {
         const float ox = fminf(fmaxf((origins[3 * i] - bx0) * inv_ext, 0.f), 1.f);
@@ -697,7 +697,7 @@ __global__ void k_ray_keys(const float* __restrict__ dirs, const float* __restri
         const float oz = fminf(fmaxf((origins[3 * i + 2] - bz0) * inv_ext, 0.f), 1.f);
         const uint64_t m = (spread10((uint64_t)(ox * 1023.f)) << 2) | (spread10((uint64_t)(oy * 1023.f)) << 1) |
                            spread10((uint64_t)(oz * 1023.f));
-        k |= m << 32;
+        k |= m << 16;
     }
     key[i] = k;
 }
@@ -792,7 +792,7 @@ int run_trace(rt_scene* ws, TraceArgs& a, const rt_trace_params* p, int depth, i
         int which = 0;
         int rc = radix_sort_pairs(w, w.sort_keys[0].as<uint64_t>(), w.sort_vals[0].as<uint32_t>(),
                                   w.sort_keys[1].as<uint64_t>(), w.sort_vals[1].as<uint32_t>(), n_rays, nullptr, 0,
-                                  origins ? 64 : 32, st, &which, true);
+                                  origins ? 48 : 16, st, &which, true);
         if (rc) return rc;
         a.order = which ? w.sort_vals[1].as<uint32_t>() : w.sort_vals[0].as<uint32_t>();
     }
