@@ -63,6 +63,7 @@ __global__ void __launch_bounds__(256) k_tri_prep(const float* __restrict__ vtx,
     uint32_t bl[12];
     for (int k = 0; k < 12; k++) bl[k] = (k % 6) < 3 ? 0xFFFFFFFFu : 0u;
     uint32_t mat_l = 0;
+    bool plane_ok = false;   // valid triangle whose plane id may vote for the representative
     if (i < nt) {
         const int3 t = tri[i];
         uint32_t err = 0;
@@ -93,7 +94,7 @@ __global__ void __launch_bounds__(256) k_tri_prep(const float* __restrict__ vtx,
             const double cz = e1[0] * e2[1] - e1[1] * e2[0];
             if (cx == 0.0 && cy == 0.0 && cz == 0.0) err |= kErrZeroArea;
             mat_l = (uint32_t)m;
-            if ((int32_t)i < prep[p]) atomicMin(&prep[p], (int32_t)i);   // stale reads only add atomics
+            plane_ok = true;
             for (int c = 0; c < 3; c++) {
                 const float lo = fminf(v[0][c], fminf(v[1][c], v[2][c]));
                 const float hi = fmaxf(v[0][c], fmaxf(v[1][c], v[2][c]));
@@ -114,6 +115,15 @@ __global__ void __launch_bounds__(256) k_tri_prep(const float* __restrict__ vtx,
             }
         }
         if (err) atomicOr(&s_err, err);
+    }
+    // plane representative = lowest triangle index of each plane id: only the
+    // first lane of a run of equal ids in a wavefront (the lowest index of the
+    // run) competes, and only while it can still lower the stored value
+    {
+        const int32_t pid = (i < nt && plane_ok) ? (plane_id ? plane_id[i] : (int32_t)i) : -1;
+        const int32_t prev = __shfl_up(pid, 1);
+        const bool first_of_run = (tid & (kWave - 1)) == 0 || prev != pid;
+        if (pid >= 0 && first_of_run && (int32_t)i < prep[pid]) atomicMin(&prep[pid], (int32_t)i);
     }
     // wave reductions, then one LDS atomic per wave and bound
     for (int off = kWave / 2; off > 0; off >>= 1) {
