@@ -54,7 +54,7 @@ def main():
     ap.add_argument("--stats", action="store_true", help="count traversal work (extra pass, not timed)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (counter calibration)")
-    ap.add_argument("--workload", choices=("theater", "rooms", "surrogate"), default="theater",
+    ap.add_argument("--workload", choices=("theater", "rooms", "surrogate", "table2"), default="theater",
                     help="theater: 436k-triangle open-air theater (default); rooms: 8 rooms of 1k-200k "
                          "triangles x 8 source/receiver pairs in one batched launch with the absorption "
                          "gradient; surrogate: late-tail MLP trained on traced rooms")
@@ -71,6 +71,8 @@ def main():
         return run_rooms(args)
     if args.workload == "surrogate":
         return run_surrogate(args)
+    if args.workload == "table2":
+        return run_table2(args)
     return run_theater(args)
 
 
@@ -469,6 +471,93 @@ def run_surrogate(args):
                      "frac": tflops / 2500.0, "traffic": None, "kernel": "MLP train step (batch 256)",
                      "step_ms": step_ms},
     }
+    print(json.dumps(out), flush=True)
+
+
+def run_table2(args):
+    """The paper's complexity study ("Tree-base acceleration", Table 2): one
+    ray-tracing iteration (every ray's first segment) with N rays = M faces,
+    source at the centre of a unit tetrahedron tessellated into 4 k^2
+    triangles, M from 2^10 to 2^20.  Per size: tree build and one-iteration
+    trace on the GPU (medians of 5, the trace by the library's kernel
+    events), and the FP64 brute-force oracle on all host cores, projected
+    from a sample of rays (it tests all M faces per ray).  The paper's
+    single-core times are quoted as context."""
+    import torch
+
+    import oracle
+    import paper_1811_05784_amd as rt
+    import synth
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    paper = {}
+    for line in open(os.path.join(ROOT, "tests", "golden", "table2_timings.txt")):
+        if line.strip() and not line.startswith("#"):
+            n, a, b = line.split()
+            paper[int(n)] = (float(a), float(b))
+    rows = []
+    threads = oracle.default_threads()
+    for p in range(10, 21):
+        k = max(1, int(round(math.sqrt(2 ** p / 4))))
+        s = synth.tessellated_tetra(k)
+        m = s.n_tri
+        n = m
+        vtx = torch.as_tensor(s.vtx, device=dev)
+        tri = torch.as_tensor(s.tri, device=dev)
+        mat = torch.as_tensor(s.material, device=dev)
+        pid = torch.as_tensor(s.plane_id, device=dev)
+        bt = []
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            sc = rt.Scene(vtx, tri, mat, pid, device=dev)
+            e1.record()
+            torch.cuda.synchronize()
+            bt.append(e0.elapsed_time(e1))
+        dirs = rt.fibonacci_directions(n, device=dev)
+        tt, out = [], None
+        for _ in range(6):
+            ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            out = rt.trace_rays(sc, dirs, s.rcv, 0, src=s.src, det_cap=max(1024, n), out=out, check_capacity=False,
+                                kernel_events=ev)
+            torch.cuda.synchronize()
+            tt.append(ev[0].elapsed_time(ev[1]))
+        c = out.counters.cpu()
+        if int(c[3]) != 0:
+            raise SystemExit("device error at M=%d" % m)
+        # CPU brute force on a sample of the same rays
+        sample = min(n, max(64, int(2e9 / (m * 50))))
+        pick = np.linspace(0, n - 1, sample).astype(np.int64)
+        dsel = oracle.fibonacci(n)[pick]
+        osc = oracle.OracleScene.of(s)
+        t0 = time.perf_counter()
+        q = oracle.query_batch(osc, np.repeat(s.src[None, :], sample, 0), dsel, flags=False, threads=threads)
+        cpu_s = (time.perf_counter() - t0) * n / sample
+        gpu_hits = out.hit_seq[torch.as_tensor(pick, device=dev), 0].cpu().numpy()
+        differ = gpu_hits != q["hit"]
+        unflagged = 0
+        if differ.any():   # decisions inside the oracle's flag margin are correct either way
+            qf = oracle.query_batch(osc, np.repeat(s.src[None, :], int(differ.sum()), 0), dsel[differ], threads=threads)
+            unflagged = int((qf["flags"] == 0).sum())
+        row = {"N=M": m, "k": k, "gpu_build_ms": sorted(bt)[2], "gpu_trace_ms": sorted(tt)[2],
+               "gpu_escapes": int(c[2]), "cpu_bruteforce_s": cpu_s, "cpu_sample_rays": sample,
+               "sample_hit_differences": int(differ.sum()), "sample_unflagged_differences": unflagged}
+        ref = paper.get(2 ** p)
+        if ref:
+            row["paper_single_core_s"] = {"without_tree": ref[0], "with_tree": ref[1]}
+        rows.append(row)
+        print("table2 M=%d build %.3f ms trace %.3f ms cpu %.3g s differences %d (unflagged %d)" % (
+            m, row["gpu_build_ms"], row["gpu_trace_ms"], cpu_s, int(differ.sum()), unflagged), file=sys.stderr,
+            flush=True)
+    big = rows[-1]
+    out = {"metric": "one ray-tracing iteration with N rays = M faces (tessellated tetrahedron), GPU tree + trace time",
+           "value": (big["gpu_build_ms"] + big["gpu_trace_ms"]) * 1e-3, "unit": "s at N=M=%d" % big["N=M"],
+           "n_gpus": 1, "steps": 5, "warmup": 1, "ms_per_step": big["gpu_build_ms"] + big["gpu_trace_ms"],
+           "higher_is_better": False, "scaling": "strong", "vs_baseline": None, "dtype": "f32 traversal, f64 shading",
+           "data": "synthetic (regular tetrahedron inscribed in the unit sphere, source at its centre)",
+           "config": {"workload": "paper's complexity sweep, N = M from 2^10 to 2^20, one iteration"},
+           "cpu_threads": threads, "rows": rows}
     print(json.dumps(out), flush=True)
 
 

@@ -502,6 +502,49 @@ def tetra_room(scale: float = 4.0):
     return v.astype(np.float32), tri, np.arange(4, dtype=np.int32), np.arange(4, dtype=np.int32)
 
 
+def tessellated_tetra(k: int, n_rays: int = 0) -> Scene:
+    """Regular tetrahedron inscribed in the unit sphere, each face a
+    triangular grid of k^2 triangles (4 k^2 in all), source at the centre:
+    the workload of the paper's complexity study (one iteration with N rays
+    and M faces, "Tree-base acceleration", Table 2).  Grid points are built
+    from integer barycentric coordinates on the tetrahedron's 4 vertices, so
+    points on shared edges are the same vertex for both faces (watertight).
+    Each face is one material; each triangle is its own plane id (the FP32
+    vertices of a tilted face are not coplanar to 1e-9 of the diagonal)."""
+    A = np.array([[1, 1, 1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]], np.float64) / math.sqrt(3.0)
+    faces = [(0, 2, 1), (0, 1, 3), (1, 2, 3), (2, 0, 3)]      # outward orientation irrelevant here
+    index, verts, tris, mats = {}, [], [], []
+
+    def vid(bary):
+        if bary not in index:
+            index[bary] = len(verts)
+            verts.append(sum(b * A[q] for q, b in enumerate(bary)) / k)
+        return index[bary]
+
+    for f, (a, b, c) in enumerate(faces):
+        def pt(i, j):
+            bary = [0, 0, 0, 0]
+            bary[a] += k - i - j
+            bary[b] += i
+            bary[c] += j
+            return vid(tuple(bary))
+        for i in range(k):
+            for j in range(k - i):
+                tris.append((pt(i, j), pt(i + 1, j), pt(i, j + 1)))
+                mats.append(f)
+                if i + j < k - 1:
+                    tris.append((pt(i + 1, j), pt(i + 1, j + 1), pt(i, j + 1)))
+                    mats.append(f)
+    tri = np.array(tris, np.int32)
+    mat = np.array(mats, np.int32)
+    plane = np.arange(len(tri), dtype=np.int32)
+    s = Scene(f"tetra k={k} {len(tri)} tris", np.array(verts, np.float32), tri, mat, plane,
+              np.full((4, 8), 0.1, np.float32), closed=True, src=np.zeros(3, np.float32),
+              rcv=np.array([[0.0, 0.0, 0.0, 0.05]], np.float32), beta=np.zeros(8, np.float32),
+              n_rays=n_rays or len(tri), max_reflections=0, ir_seconds=0.01)
+    return _check(s)
+
+
 # ----------------------------------------------------------------------------
 # batched rooms (many rooms of uneven size)
 # ----------------------------------------------------------------------------

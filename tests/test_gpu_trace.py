@@ -236,3 +236,23 @@ def test_scheduling_leaves_results_unchanged(rt, scenes, name, R, n, kw):
     assert torch.equal(a.hit_seq, b.hit_seq)
     assert torch.equal(a.counters[:3], b.counters[:3]) and int(b.counters[3]) == 0
     assert np.array_equal(_sorted_det(a), _sorted_det(b))
+
+
+@pytest.mark.parametrize("k", [1, 16, 91])
+def test_tetra_one_iteration_matches_oracle(rt, oracle_lib, k):
+    """The complexity study's workload ("Tree-base acceleration", Table 2):
+    one iteration from the centre of a tessellated unit tetrahedron.  Every
+    ray hits the oracle's triangle unless the oracle flags the query, and no
+    ray escapes the watertight surface."""
+    s = synth.tessellated_tetra(k)
+    sc = rt.Scene.from_synth(s, device="cuda:0")
+    n = s.n_tri
+    dirs = rt.fibonacci_directions(n, device="cuda:0")
+    tr = rt.trace_rays(sc, dirs, s.rcv, 0, src=s.src)
+    gpu = tr.hit_seq[:, 0].cpu().numpy()
+    assert int(tr.counters[2]) == 0 and np.all(gpu >= 0)
+    osc = oracle_lib.OracleScene.of(s)
+    q = oracle_lib.query_batch(osc, np.repeat(s.src[None, :], n, 0), oracle_lib.fibonacci(n))
+    bad = (gpu != q["hit"]) & (q["flags"] == 0)
+    _say("tetra k=%d M=%d flagged %d mismatches %d" % (k, n, int((q["flags"] != 0).sum()), int((gpu != q["hit"]).sum())))
+    assert not bad.any()
