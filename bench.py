@@ -202,6 +202,15 @@ def run_theater(args):
                                       "triangles": st[2] / queries, "spills": st[3] / queries,
                                       "tree_nodes": sc.n_nodes, "tree_depth": sc.depth}
     out["roofline"]["traffic"] = measured_traffic()
+    # perceptive factors of the last step's IR (not timed): 500 Hz and 1 kHz octaves, every receiver
+    pr = rt.room_params(state["ir"].hist, s.fs).cpu().numpy()
+    names = ("EDT_s", "T30_s", "C80_dB", "D50", "Ts_s", "SPL_dB")
+    out["room_params_500_1k"] = {
+        "receivers": [{n: (None if not np.isfinite(v) else round(float(v), 4)) for n, v in zip(names, pr[m, 3:5].mean(0))}
+                      for m in range(n_rcv)],
+        "note": "mean of the 500 Hz and 1 kHz octaves; the paper's Table 3 (roofed restitution of the theater, "
+                "one listener on the axis, 500-1000 Hz) lists EDT 1.85 s, T30 3.59 s, SPL -32 dB, C80 1.12 dB, "
+                "D50 47 %, Ts 117 ms: context only (different geometry, this stand-in has no roof)"}
     # IR band error vs the oracle on a seeded image-source table of this shape
     try:
         out["ir_band_error"] = band_error(rt, state["scene"], s, taps)

@@ -340,6 +340,25 @@ int rt_hist_features(const float* hist, int64_t n, float floor_db, float offset_
  * FP64 sums, clamped below at floor_db (a row without energy is all floor). */
 int rt_edc_db(const float* hist, int64_t rows, int32_t bins, float floor_db, float* edc, void* stream);
 
+/*
+ * rt_room_params -- perceptive factors from the per-band energy histogram of
+ * an impulse response (the paper tabulates EDT, T30, SPL, C80, D50 and Ts for
+ * its theater, Table 3; definitions as in room-acoustics practice, ISO 3382-1).
+ *   hist   [n_rcv, 8, L] float: energy per time bin of width 1/fs (e.g. the
+ *          `hist` output of rt_assemble_ir)
+ *   params [n_rcv, 8, 6] double out: EDT (s), T30 (s), C80 (dB), D50
+ *          (fraction), Ts (s), SPL (dB re the emitted energy)
+ * Origin s0 = first bin with energy in any band of the receiver.  Schroeder
+ * curve EDC(s) = sum_{s' >= s} H[s'] in dB re EDC(s0), up to the last bin with
+ * energy.  EDT, T30 = -60 / slope of the least-squares line of EDC_dB against
+ * (s - s0) / fs over 0..-10 dB and -5..-35 dB; NaN unless the curve reaches
+ * -10 (-35) dB and 2 bins qualify.  C80 = 10 log10(E_early / E_late) with
+ * floor(0.08 fs + 1/2) early bins (NaN without late energy); D50 = share of
+ * the first floor(0.05 fs + 1/2) bins; Ts = energy-weighted mean of
+ * (s - s0) / fs; SPL = 10 log10 sum H.  A band without energy gives NaN.
+ */
+int rt_room_params(const float* hist, int32_t n_rcv, int64_t L, float fs, double* params, void* stream);
+
 /* Test hook for the exact-grouping path of rt_collect_image_sources: keep
  * only the low `bits` bits (1..64, default 32) of the 64-bit key hash so that
  * distinct keys collide.  Process-wide; not thread-safe with concurrent

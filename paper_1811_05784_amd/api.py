@@ -168,6 +168,23 @@ def trace_rays(scene: Scene, dirs: torch.Tensor, rcv, max_reflections: int, src=
     return out
 
 
+PARAM_NAMES = ("EDT", "T30", "C80", "D50", "Ts", "SPL")
+
+
+def room_params(hist, fs: float, device=None) -> torch.Tensor:
+    """rt_room_params: [n_rcv, 8, L] energy histogram -> [n_rcv, 8, 6] float64
+    (EDT s, T30 s, C80 dB, D50, Ts s, SPL dB); NaN where undefined."""
+    lib = _lib.load()
+    dev = hist.device if isinstance(hist, torch.Tensor) else _dev(device)
+    h = _to_dev(hist, torch.float32, dev)
+    assert h.dim() == 3 and h.shape[1] == 8
+    out = torch.empty((h.shape[0], 8, 6), dtype=torch.float64, device=dev)
+    with torch.cuda.device(dev):
+        check(lib.rt_room_params(_ptr(h), h.shape[0], h.shape[2], float(fs), _ptr(out), _stream(dev)),
+              "rt_room_params")
+    return out
+
+
 def _event_ptrs(events):
     """(start, stop) torch.cuda.Event pair -> their hipEvent_t handles (the
     events are created by a first record on the current stream)."""
