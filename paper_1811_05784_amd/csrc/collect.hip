@@ -113,38 +113,59 @@ __global__ void k_heads(CollectArgs a, const uint64_t* __restrict__ hash, const 
     }
 }
 
-__device__ void fix_run(const CollectArgs& a, const uint64_t* hash, uint32_t* idx, uint32_t* head, int64_t n,
-                        int64_t i);
+// First row of the sorted hash array [lo, hi) not below h / above h.
+__device__ inline int64_t lower_row(const uint64_t* hash, int64_t lo, int64_t hi, uint64_t h) {
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (hash[mid] < h) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+__device__ inline int64_t upper_row(const uint64_t* hash, int64_t lo, int64_t hi, uint64_t h) {
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (hash[mid] <= h) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
 
-// Runs of equal hash holding different keys: sort the run by full key and
-// recompute its group heads.  Does nothing unless a collision was seen.
+// Runs of equal hash holding different keys: a row whose hash equals the
+// previous one but whose key differs marks the first row of its run (bit 1
+// of head; the run start is found by binary search in the sorted hashes).
+// Does nothing unless a collision was seen.
+__global__ void k_mark_mixed(CollectArgs a, const uint64_t* __restrict__ hash, uint32_t* __restrict__ head,
+                             const uint32_t* __restrict__ flags) {
+    if (!(*flags & 4u)) return;
+    const int64_t n = det_count(a);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        if (i == 0 || !(head[i] & 1u) || hash[i] != hash[i - 1]) continue;
+        atomicOr(&head[lower_row(hash, 0, i, hash[i])], 2u);
+    }
+}
+
+// One thread per marked run: sort the run by full key (stable) and recompute
+// its group heads.  Unmarked runs, however long, are not touched.
 __global__ void k_fix_collisions(CollectArgs a, const uint64_t* __restrict__ hash, uint32_t* __restrict__ idx,
                                  uint32_t* __restrict__ head, const uint32_t* __restrict__ flags) {
     if (!(*flags & 4u)) return;
     const int64_t n = det_count(a);
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        fix_run(a, hash, idx, head, n, i);
-}
-
-__device__ void fix_run(const CollectArgs& a, const uint64_t* hash, uint32_t* idx, uint32_t* head, int64_t n,
-                        int64_t i) {
-    if (i > 0 && hash[i] == hash[i - 1]) return;   // not a run start
-    int64_t e = i + 1;
-    while (e < n && hash[e] == hash[i]) e++;
-    bool mixed = false;
-    for (int64_t j = i + 1; j < e && !mixed; j++) mixed = key_cmp(a, idx[j], idx[i]) != 0;
-    if (!mixed) return;
-    for (int64_t j = i + 1; j < e; j++) {   // stable insertion sort by key
-        const uint32_t v = idx[j];
-        int64_t q = j - 1;
-        while (q >= i && key_cmp(a, idx[q], v) > 0) {
-            idx[q + 1] = idx[q];
-            q--;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        if (!(head[i] & 2u)) continue;
+        const int64_t e = upper_row(hash, i + 1, n, hash[i]);
+        for (int64_t j = i + 1; j < e; j++) {   // stable insertion sort by key
+            const uint32_t v = idx[j];
+            int64_t q = j - 1;
+            while (q >= i && key_cmp(a, idx[q], v) > 0) {
+                idx[q + 1] = idx[q];
+                q--;
+            }
+            idx[q + 1] = v;
         }
-        idx[q + 1] = v;
+        head[i] = 1;
+        for (int64_t j = i + 1; j < e; j++) head[j] = key_cmp(a, idx[j], idx[j - 1]) != 0;
     }
-    head[i] = 1;
-    for (int64_t j = i + 1; j < e; j++) head[j] = key_cmp(a, idx[j], idx[j - 1]) != 0;
 }
 
 __global__ void k_head_pos(CollectArgs a, const uint32_t* __restrict__ head, const uint32_t* __restrict__ group,
@@ -304,6 +325,7 @@ int collect_common(rt_scene* s, const rt_batch* b, const float* src_host, const 
     uint32_t* group = ws.is_group.as<uint32_t>();
     uint32_t* hpos = ws.is_idx.as<uint32_t>();
     hipLaunchKernelGGL(k_heads, dim3(nblk(cap)), dim3(256), 0, st, a, hs, ix, head, err);
+    hipLaunchKernelGGL(k_mark_mixed, dim3(nblk(cap)), dim3(256), 0, st, a, hs, head, err);
     hipLaunchKernelGGL(k_fix_collisions, dim3(nblk(cap)), dim3(256), 0, st, a, hs, ix, head, err);
     rc = exclusive_scan_u32(ws, head, group, cap, n_det, st);
     if (rc) return rc;
