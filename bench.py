@@ -54,10 +54,11 @@ def main():
     ap.add_argument("--stats", action="store_true", help="count traversal work (extra pass, not timed)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (counter calibration)")
-    ap.add_argument("--workload", choices=("theater", "rooms", "surrogate", "table2"), default="theater",
+    ap.add_argument("--workload", choices=("theater", "rooms", "surrogate", "table2", "sphere"), default="theater",
                     help="theater: 436k-triangle open-air theater (default); rooms: 8 rooms of 1k-200k "
                          "triangles x 8 source/receiver pairs in one batched launch with the absorption "
-                         "gradient; surrogate: late-tail MLP trained on traced rooms")
+                         "gradient; surrogate: late-tail MLP trained on traced rooms; table2: the paper's "
+                         "complexity sweep; sphere: reflecting-sphere Dirac comb vs mesh refinement")
     ap.add_argument("--rooms", type=int, default=2000, help="surrogate: training + held-out rooms")
     ap.add_argument("--epochs", type=int, default=300, help="surrogate: training epochs")
     ap.add_argument("--no-tune", action="store_true", help="rooms: skip the launch autotuner")
@@ -73,6 +74,8 @@ def main():
         return run_surrogate(args)
     if args.workload == "table2":
         return run_table2(args)
+    if args.workload == "sphere":
+        return run_sphere(args)
     return run_theater(args)
 
 
@@ -203,21 +206,35 @@ def run_theater(args):
                                       "tree_nodes": sc.n_nodes, "tree_depth": sc.depth}
     out["roofline"]["traffic"] = measured_traffic()
     # perceptive factors of the last step's IR (not timed): 500 Hz and 1 kHz octaves, every receiver
-    pr = rt.room_params(state["ir"].hist, s.fs).cpu().numpy()
+    hist = state["ir"].hist
+    pr = rt.room_params(hist, s.fs)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(5):
+        pr = rt.room_params(hist, s.fs)
+    ev[1].record()
+    torch.cuda.synchronize()
+    rp_ms = ev[0].elapsed_time(ev[1]) / 5
+    pr = pr.cpu().numpy()
     names = ("EDT_s", "T30_s", "C80_dB", "D50", "Ts_s", "SPL_dB")
+    rp_bytes = 2 * hist.numel() * 4      # two passes over the histogram (FP32)
+    out["room_params_timing"] = {"ms": rp_ms, "algorithmic_bytes": rp_bytes,
+                                 "GB_per_s": rp_bytes / (rp_ms * 1e-3) / 1e9,
+                                 "shape": list(hist.shape)}
     out["room_params_500_1k"] = {
         "receivers": [{n: (None if not np.isfinite(v) else round(float(v), 4)) for n, v in zip(names, pr[m, 3:5].mean(0))}
                       for m in range(n_rcv)],
         "note": "mean of the 500 Hz and 1 kHz octaves; the paper's Table 3 (roofed restitution of the theater, "
                 "one listener on the axis, 500-1000 Hz) lists EDT 1.85 s, T30 3.59 s, SPL -32 dB, C80 1.12 dB, "
                 "D50 47 %, Ts 117 ms: context only (different geometry, this stand-in has no roof)"}
-    # IR band error vs the oracle on a seeded image-source table of this shape
-    try:
-        out["ir_band_error"] = band_error(rt, state["scene"], s, taps)
-    except Exception as e:  # report, never hide
-        out["ir_band_error"] = "failed: %r" % (e,)
     if not args.no_cpu:
+        # CPU leg: the oracle timed on a sample of the rays, and the IR bands of
+        # a seeded image-source table of this shape checked against it
         out["cpu_baseline"] = cpu_baseline(s, args.cpu_rays)
+        try:
+            out["cpu_baseline"]["ir_band_error"] = band_error(rt, state["scene"], s, taps)
+        except Exception as e:  # report, never hide
+            out["cpu_baseline"]["ir_band_error"] = "failed: %r" % (e,)
     print(json.dumps(out), flush=True)
 
 
@@ -567,6 +584,79 @@ def run_table2(args):
            "data": "synthetic (regular tetrahedron inscribed in the unit sphere, source at its centre)",
            "config": {"workload": "paper's complexity sweep, N = M from 2^10 to 2^20, one iteration"},
            "cpu_threads": threads, "rows": rows}
+    print(json.dumps(out), flush=True)
+
+
+def run_sphere(args):
+    """The reflecting-sphere study ("Energy conservation by reflecting
+    sphere"): a 100 % reflecting unit sphere of 20 * 4^level flat facets
+    (levels 0 to 6, up to 81,920 facets), no air absorption, source and
+    receiver (r = 0.05 m) at the centre, 10^5 rays, six reflections.  An
+    exact sphere returns every ray through the centre every 2 m (a Dirac
+    comb of energy 1 per pulse); flat facets spread and lose it.  Per level:
+    energy n/N of each pulse (image sources of order k), the largest
+    relative distance error of a pulse's image sources, GPU times (tree
+    build, traversal kernel by the library's events, image-source
+    collection), and the eq. 13 range of this receiver and ray count."""
+    import torch
+
+    import paper_1811_05784_amd as rt
+    import synth
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    N, R = 100_000, 6
+    rows = []
+    for level in range(0, 7):
+        s = synth.sphere_room(level)
+        bt = []
+        for _ in range(3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            sc = rt.Scene.from_synth(s, device=dev)
+            e1.record()
+            torch.cuda.synchronize()
+            bt.append(e0.elapsed_time(e1))
+        dirs = rt.fibonacci_directions(N, device=dev)
+        tt, ct, tr = [], [], None
+        for _ in range(5):
+            ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            tr = rt.trace_rays(sc, dirs, s.rcv, R, src=s.src, kernel_events=ev)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            isrc = rt.collect_image_sources(sc, s.src, s.rcv, tr)
+            e1.record()
+            torch.cuda.synchronize()
+            tt.append(ev[0].elapsed_time(ev[1]))
+            ct.append(e0.elapsed_time(e1))
+        c = tr.counters.cpu()
+        if int(c[3]) != 0:
+            raise SystemExit("device error at level %d" % level)
+        key, cnt, pos, dist = [t.cpu().numpy() for t in isrc.valid()]
+        order = key[:, 1]
+        pulses, spread = [], []
+        for k in range(R + 1):
+            sel = order == k
+            pulses.append(float(cnt[sel].sum()) / N)
+            spread.append(float(np.abs(dist[sel] - 2 * k).max() / (2 * k)) if k and sel.any() else 0.0)
+        row = {"level": level, "facets": s.n_tri, "pulse_energy": pulses, "pulse_rel_spread": spread,
+               "image_sources": int(len(key)), "escapes": int(c[2]), "queries": int(c[1]),
+               "gpu_build_ms": sorted(bt)[1], "gpu_trace_kernel_ms": sorted(tt)[2],
+               "gpu_collect_ms": sorted(ct)[2]}
+        rows.append(row)
+        print("sphere level %d (%d facets): pulses %s trace %.3f ms" % (
+            level, s.n_tri, " ".join("%.3f" % e for e in pulses), row["gpu_trace_kernel_ms"]),
+            file=sys.stderr, flush=True)
+    r = float(synth.sphere_room(0).rcv[0, 3])
+    out = {"metric": "reflecting-sphere Dirac comb, 1e5 rays x 7 segments, traversal kernel time at 81,920 facets",
+           "value": rows[-1]["gpu_trace_kernel_ms"], "unit": "ms", "n_gpus": 1, "steps": 5, "warmup": 0,
+           "ms_per_step": rows[-1]["gpu_trace_kernel_ms"], "higher_is_better": False, "scaling": "strong",
+           "vs_baseline": None, "dtype": "f32 traversal, f64 shading",
+           "data": "synthetic (icosphere levels 0-6 projected on the unit sphere)",
+           "config": {"workload": "unit sphere, alpha = 0, source and receiver r = %g m at the centre, "
+                                  "N = 1e5, R = 6" % r},
+           "eq13_range_m": 0.5 * r * math.sqrt(N),
+           "rows": rows}
     print(json.dumps(out), flush=True)
 
 

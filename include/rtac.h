@@ -121,6 +121,11 @@ typedef struct {
                                   0..S-1 of every ray and queues the rays that continue, the second
                                   finishes them all together (long bounce chains start at once).
                                   Results are identical; overrides `rounds`                     */
+    int32_t min_beam_rays;     /* 0 = off; n >= 1: the range of the discrete model (eq. 13): a ray
+                                  stops once its travelled length reaches (r / 2) sqrt(N / n), r =
+                                  the largest receiver radius and N = the rays of the call (of the
+                                  job, in a batch); FP64, rounded to FP32.  Combined with
+                                  max_path_length by taking the smaller limit                     */
 } rt_trace_params;
 
 /*
@@ -136,8 +141,9 @@ typedef struct {
  *     ball, FP64; the sphere is transparent);
  *   - reflection: u' = u - 2 (u.n) n with the plane's unit normal,
  *     o' = o + delta u, L' = L + delta |u| (FP64, rounded to FP32);
- *   - the ray stops after segment R, once L' >= max_path_length, or when it
- *     hits nothing (open air: eliminated).
+ *   - the ray stops after segment R, once L' >= max_path_length or the
+ *     eq. 13 range (min_beam_rays), or when it hits nothing (open air:
+ *     eliminated).
  *
  *   src_host    [3] float host  source; used when origins == NULL
  *   origins     [n_rays, 3] float or NULL  per-ray start point

@@ -24,6 +24,10 @@ Each function cites the part of the paper it follows:
                          p = sqrt(E), FIR filtering over 8 octave bands, summed.
 * ``band_energy_grad``-- analytic derivative of the band energies w.r.t. the
                          per-material absorption (E is a polynomial in alpha).
+* ``range_limit``     -- maximum range of the discrete model, d <= (r/2) sqrt(N/n)
+                         (eq. 13); ``trace`` stops rays there through max_len
+                         (section "Standard algorithm": rays propagate while the
+                         travelled length satisfies it).
 
 Parity unpinned: none of the functions above; each is pinned by the tests in
 ``tests/test_oracle_*.py`` against closed forms, exact rational arithmetic,
@@ -32,6 +36,7 @@ invariants or the paper's printed parameters.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 from typing import Dict, Tuple
@@ -122,6 +127,13 @@ class OracleScene:
         p = np.empty((len(self.tri), 3))
         lib().or_scene_planes(self._h, _p(n), _p(p))
         return n, p
+
+
+def range_limit(r: float, n_rays: int, n: int = 1) -> float:
+    """Eq. 13: a beam of n >= 1 of the N emitted rays, crossing a receiver of
+    radius r, is measurable up to d = (r/2) sqrt(N/n) (the small-angle count
+    n/N ~ r^2 / (4 d^2) of eq. 12 solved for d).  FP64."""
+    return 0.5 * float(r) * math.sqrt(float(n_rays) / float(n))
 
 
 def fibonacci(n: int) -> np.ndarray:

@@ -73,6 +73,7 @@ struct TraceArgs {
     int64_t q_cap;                  // entries of q_in / q_out
     int32_t spill_thr;
     int32_t suspend_k;              // > 0: a ray about to start segment >= suspend_k goes to q_out
+    int32_t beam_n;                 // > 0: range limit of the discrete model with beams of >= beam_n rays
     // batched calls: rays of many jobs (source + receivers in one scene)
     const DevJob* jobs;
     const DevScene* scenes;
@@ -188,6 +189,13 @@ __device__ inline bool stack_pop(Stack& s, int32_t* lds, const int32_t* spill, i
     return true;
 }
 
+// Range of the discrete model (eq. 13): with receiver radius r and N rays
+// emitted, a beam of at least n rays is measurable up to d = (r / 2) sqrt(N / n).
+// FP64, rounded once to FP32 (the precision of the travelled-length limit).
+__device__ inline float beam_range(double r, int64_t n_rays, int32_t n) {
+    return (float)(0.5 * r * sqrt((double)n_rays / (double)n));
+}
+
 __device__ inline void cswap(float& ta, int32_t& ra, float& tb, int32_t& rb) {
     if (tb < ta) {
         float t = ta;
@@ -214,7 +222,13 @@ k_trace(TraceArgs a) {
     const double* pl_n = a.plane_n;
     const double* pl_p = a.plane_p;
     int32_t n_nodes = a.n_nodes, n_tri = a.n_tri, rcv_off = 0, n_rcv = a.n_rcv;
-    float max_len = a.max_len;
+    // travelled length at which a ray stops (+inf: no limit)
+    float lim = a.max_len > 0.f ? a.max_len : INFINITY;
+    if (!kBatch && a.beam_n > 0) {
+        double r_max = 0.0;
+        for (int m = 0; m < a.n_rcv; m++) r_max = fmax(r_max, rcv_s[m][3]);
+        lim = fminf(lim, beam_range(r_max, a.n_rays, a.beam_n));
+    }
 
     int32_t* spill = a.spill + ((int64_t)blockIdx.x * kBlock + tid) * a.spill_per_lane;
     const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
@@ -309,7 +323,13 @@ k_trace(TraceArgs a) {
                         n_tri = sc.n_tri;
                         rcv_off = jb.rcv_off;
                         n_rcv = jb.n_rcv;
-                        max_len = jb.max_len;
+                        lim = jb.max_len > 0.f ? jb.max_len : INFINITY;
+                        if (a.beam_n > 0) {
+                            double r_max = 0.0;
+                            for (int m = 0; m < n_rcv; m++)
+                                r_max = fmax(r_max, (double)a.rcv[4 * (int64_t)(rcv_off + m) + 3]);
+                            lim = fminf(lim, beam_range(r_max, jb.n_rays, a.beam_n));
+                        }
                     }
                     setup_ray(r);
                     cur = 0;
@@ -572,7 +592,7 @@ k_trace(TraceArgs a) {
                 r.uz = (float)(uz - 2.0 * udn * nz);
                 L = (float)Ln;
                 last_plane = hit_plane;
-                stop = (k == a.R) || (max_len > 0.f && Ln >= (double)max_len);
+                stop = (k == a.R) || Ln >= (double)lim;
                 if (a.record) {
                     float* sp = a.states + ((int64_t)ray * (R1 + 1) + k + 1) * 8;
                     sp[0] = r.ox;
@@ -844,6 +864,7 @@ int check_params(const rt_trace_params* p) {
     RT_CHECK(p->max_reflections >= 0 && p->max_reflections < 4096, RT_EINVAL,
              "max_reflections must be in [0, 4096)");
     RT_CHECK(p->suspend_after >= 0, RT_EINVAL, "suspend_after must be >= 0");
+    RT_CHECK(p->min_beam_rays >= 0, RT_EINVAL, "min_beam_rays must be >= 0");
     return RT_OK;
 }
 
@@ -893,6 +914,7 @@ extern "C" int rt_trace_rays(const rt_scene* scene, const float* src_host, const
     a.n_rcv = n_rcv;
     a.R = p->max_reflections;
     a.max_len = p->max_path_length;
+    a.beam_n = p->min_beam_rays;
     a.record = p->record_states ? 1 : 0;
     a.hit_seq = hit_seq;
     a.det = det;
@@ -1015,6 +1037,7 @@ extern "C" int rt_trace_batch(rt_batch* b, const float* rcv, const rt_trace_para
     a.n_rays = b->n_rays;
     a.rcv = rcv;
     a.R = p->max_reflections;
+    a.beam_n = p->min_beam_rays;
     a.hit_seq = hit_seq;
     a.det = det;
     a.det_cap = det_cap;

@@ -187,3 +187,26 @@ def test_batch_suspension_unchanged(rt, setup):
     assert torch.equal(a.hit_seq, s.hit_seq) and torch.equal(a.counters[:3], s.counters[:3])
     da, ds = a.detections().cpu().numpy(), s.detections().cpu().numpy()
     assert np.array_equal(da[np.lexsort(da.T[::-1])], ds[np.lexsort(ds.T[::-1])])
+
+
+def test_batch_eq13_range_equals_single(rt, setup):
+    """min_beam_rays in a batch: each job stops its rays at the eq. 13 range
+    of its own receivers and ray count, as the single-scene call does (which
+    is checked against the oracle)."""
+    rooms, scenes, jobs, b = setup
+    tr = rt.trace_batch(b, R, min_beam_rays=2)
+    full = rt.trace_batch(b, R)
+    assert int(tr.counters[1]) < int(full.counters[1])       # the range shortens the paths
+    hs = tr.hit_seq.cpu().numpy()
+    det = tr.detections().cpu().numpy()
+    for j, job in enumerate(jobs):
+        d = rt.fibonacci_directions(job["n_rays"], device=DEV)
+        one = rt.trace_rays(scenes[job["scene"]], d, job["rcv"], R, src=job["src"],
+                            max_path_length=job["max_path_length"], min_beam_rays=2)
+        lo, hi = b.ray_off[j], b.ray_off[j + 1]
+        assert np.array_equal(hs[lo:hi], one.hit_seq.cpu().numpy()), j
+        dj = det[(det[:, 0] >= lo) & (det[:, 0] < hi)].copy()
+        dj[:, 0] -= lo
+        dj[:, 2] -= b.rcv_off[j]
+        d1 = one.detections().cpu().numpy()
+        assert np.array_equal(dj[np.lexsort(dj.T[::-1])], d1[np.lexsort(d1.T[::-1])]), j

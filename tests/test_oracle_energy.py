@@ -130,3 +130,77 @@ def test_reflecting_sphere_dirac_comb(oracle_lib):
     assert np.all(kept[:, 0] >= kept[:, -1])
     assert kept[2].sum() > kept[1].sum() > kept[0].sum()
     assert spreads[0] > spreads[1] > spreads[2] and spreads[2] < 0.01
+
+
+@pytest.mark.parametrize("r,N,n", [(0.36, 1_000_000, 1), (0.2, 100_000, 1), (0.2, 100_000, 25), (0.05, 4000, 3)])
+def test_range_limit_is_where_beams_thin_to_n_rays(oracle_lib, r, N, n):
+    """Eq. 13 against the exact solid angle: at d = (r/2) sqrt(N/n) a sphere
+    of radius r subtends Omega_m = 2 pi (1 - sqrt(1 - r^2/d^2)), i.e. an
+    expected N Omega_m / (4 pi) = n (1 + n/N + ...) rays, just above n."""
+    d = oracle_lib.range_limit(r, N, n)
+    count = N * (1 - np.sqrt(1 - r * r / (d * d))) / 2
+    assert n <= count <= n * (1 + 2.0 * n / N)
+    # quadrupling the beam halves the range
+    assert oracle_lib.range_limit(r, N, 4 * n) == pytest.approx(d / 2, rel=1e-15)
+
+
+def test_range_limit_free_field_figure(oracle_lib):
+    """The energy-vs-distance figure (r = 0.36 m, N = 1e6) stays measurable up
+    to 180 m; free-field traces put about n rays through receivers placed at
+    the eq. 13 range for n."""
+    r = _golden("free_field_radius")
+    N = int(_golden("free_field_rays"))
+    assert oracle_lib.range_limit(r, N, 1) == pytest.approx(180.0, rel=1e-12)
+    s = synth.open_scene_far_triangle()
+    sc = oracle_lib.OracleScene.of(s)
+    N2, r2 = 100_000, 0.2
+    ns = np.array([1, 4, 16, 64, 256])
+    d = np.array([oracle_lib.range_limit(r2, N2, int(k)) for k in ns])
+    ax = np.array([0.48, -0.6, -0.64])                  # unit, away from the far triangle
+    rcv = np.concatenate([ax[None, :] * d[:, None], np.full((len(ns), 1), r2)], 1).astype(np.float32)
+    tr = oracle_lib.trace(sc, np.zeros(3, np.float32), oracle_lib.fibonacci(N2), rcv, 0, flags=False)
+    counts = np.array([((tr["det"][:, 0] >> np.uint32(m)) & 1).sum() for m in range(len(ns))])
+    assert np.all(np.abs(counts - ns) <= 3 * np.sqrt(ns) + 2), (counts, ns)
+
+
+def test_sphere_first_return_closed_form(oracle_lib):
+    """Faceted reflecting sphere, source and receiver at the centre: a ray
+    along u leaves through the facet plane n.x = rho minimising
+    rho / (u.n) over u.n > 0 (a convex body around the origin), reflects,
+    and passes the centre at distance 2 rho sin(theta), theta = angle(u, n);
+    so the first return is detected iff 2 rho sin(theta) <= r, and its image
+    source (the centre mirrored in the plane) lies 2 rho away."""
+    s = synth.sphere_room(2)
+    sc = oracle_lib.OracleScene.of(s)
+    N = 4000
+    dirs = oracle_lib.fibonacci(N)
+    tr = oracle_lib.trace(sc, s.src, dirs, s.rcv, 1)
+    v = s.vtx.astype(np.float64)
+    a, b, c = v[s.tri[:, 0]], v[s.tri[:, 1]], v[s.tri[:, 2]]
+    nrm = np.cross(b - a, c - a)
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    rho = (nrm * a).sum(1)
+    assert np.all(rho > 0)                             # outward normals, origin inside
+    u = dirs.astype(np.float64)
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    un = u @ nrm.T
+    t = np.where(un > 0, rho[None, :] / np.where(un > 0, un, 1.0), np.inf)
+    facet = np.argmin(t, axis=1)
+    srt = np.sort(t, axis=1)
+    clear = (srt[:, 1] - srt[:, 0]) > 1e-9 * srt[:, 0]  # exclude rays through facet edges
+    ok = clear & (tr["flags"][:, 0] == 0)
+    assert ok.mean() > 0.99
+    assert np.array_equal(tr["hit_seq"][ok, 0], facet[ok])
+    cos_t = un[np.arange(N), facet]
+    bdist = 2 * rho[facet] * np.sqrt(np.maximum(0.0, 1 - cos_t ** 2))
+    r = float(s.rcv[0, 3])
+    sure = ok & (np.abs(bdist - r) > 1e-9) & (tr["flags"][:, 1] == 0)
+    got = (tr["det"][:, 1] & 1).astype(bool)
+    assert np.array_equal(got[sure], bdist[sure] <= r)
+    assert 0 < got.sum() < N                           # some returns hit the receiver, some miss
+    det = oracle_lib.detections_from_bits(tr["det"])
+    keys = oracle_lib.image_source_keys(s.plane_id, tr["hit_seq"], det)
+    tab = oracle_lib.image_sources(sc, s.src, s.rcv, keys)
+    for key, dist in zip(tab["keys"], tab["dist"]):
+        if key[1] == 1:
+            assert dist == pytest.approx(2 * rho[key[2]], rel=1e-12)
