@@ -18,7 +18,7 @@ def _hist(seed, n_rcv, L):
     rng = np.random.default_rng(seed)
     h = np.zeros((n_rcv, 8, L), np.float32)
     for m in range(n_rcv):
-        s0 = int(rng.integers(0, L // 10))
+        s0 = int(rng.integers(0, max(1, L // 10)))
         a = rng.uniform(3.0, 40.0, size=8)
         t = np.arange(L - s0) / FS
         for b in range(8):
@@ -31,7 +31,7 @@ def _hist(seed, n_rcv, L):
     return h
 
 
-@pytest.mark.parametrize("n_rcv,L", [(1, 100), (4, 5000), (8, 96_000)])
+@pytest.mark.parametrize("n_rcv,L", [(1, 1), (1, 100), (3, 4097), (4, 5000), (8, 96_000), (32, 24_001)])
 def test_room_params_match_oracle(n_rcv, L):
     import paper_1811_05784_amd as rt
     h = _hist(n_rcv * 7 + L, n_rcv, L)
@@ -42,4 +42,6 @@ def test_room_params_match_oracle(n_rcv, L):
     rel = np.array([1e-6, 1e-6, 1e-9, 1e-9, 1e-9, 1e-9])
     tol = rel * np.maximum(np.abs(ref), 1e-12)
     assert np.all(np.abs(got - ref)[ok] <= np.broadcast_to(tol, ref.shape)[ok] + 1e-12)
-    assert ok[..., 0].any() and ok[..., 4].any()
+    assert ok[..., 4].any()
+    if L >= 1000:
+        assert ok[..., 0].any() and ok[..., 1].any()
