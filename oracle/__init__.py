@@ -24,6 +24,11 @@ Each function cites the part of the paper it follows:
                          p = sqrt(E), FIR filtering over 8 octave bands, summed.
 * ``band_energy_grad``-- analytic derivative of the band energies w.r.t. the
                          per-material absorption (E is a polynomial in alpha).
+* ``icosahedral`` /
+  ``directional``     -- source variants (section "Discrete model"): unit-sphere
+                         sampling by icosahedron subdivision, and a directional
+                         source sampled non-uniformly (footnote on directional
+                         sources), every ray carrying the same energy.
 * ``range_limit``     -- maximum range of the discrete model, d <= (r/2) sqrt(N/n)
                          (eq. 13); ``trace`` stops rays there through max_len
                          (section "Standard algorithm": rays propagate while the
@@ -134,6 +139,82 @@ def range_limit(r: float, n_rays: int, n: int = 1) -> float:
     radius r, is measurable up to d = (r/2) sqrt(N/n) (the small-angle count
     n/N ~ r^2 / (4 d^2) of eq. 12 solved for d).  FP64."""
     return 0.5 * float(r) * math.sqrt(float(n_rays) / float(n))
+
+
+def icosahedron_vertices() -> np.ndarray:
+    """The 12 vertices of the regular icosahedron (unnormalised, edge 2):
+    the cyclic placements (0, a, b), (a, b, 0), (b, 0, a) of a = +-1,
+    b = +-phi, phi the golden ratio; placements in that order, signs of
+    (a, b) in the order (-,-), (-,+), (+,-), (+,+)."""
+    phi = (1.0 + math.sqrt(5.0)) / 2.0
+    out = []
+    for place in range(3):
+        for sa in (-1.0, 1.0):
+            for sb in (-1.0, 1.0):
+                a, b = sa, sb * phi
+                out.append([(0.0, a, b), (a, b, 0.0), (b, 0.0, a)][place])
+    return np.array(out)
+
+
+def icosahedral(f: int) -> np.ndarray:
+    """[10 f^2 + 2, 3] FP32 unit directions: every face of the icosahedron
+    cut into f^2 triangles, the grid points (f-i-j) A + i B + j C pushed to
+    the unit sphere (FP64, rounded once).  Order: the 12 vertices; the f-1
+    inner points of each edge (a < b, edges in lexicographic order), from a
+    towards b; the inner points of each face (a < b < c, faces in
+    lexicographic order), by i then j."""
+    v = icosahedron_vertices()
+    n = len(v)
+    adj = [[float(((v[p] - v[q]) ** 2).sum()) < 4.5 for q in range(n)] for p in range(n)]
+    edges = [(p, q) for p in range(n) for q in range(p + 1, n) if adj[p][q]]
+    faces = [(p, q, r) for p in range(n) for q in range(p + 1, n) for r in range(q + 1, n)
+             if adj[p][q] and adj[q][r] and adj[p][r]]
+    assert len(edges) == 30 and len(faces) == 20
+    pts = [v[p] for p in range(n)]
+    for a, b in edges:
+        for q in range(1, f):
+            pts.append((f - q) * v[a] + q * v[b])
+    for a, b, c in faces:
+        for i in range(1, f - 1):
+            for j in range(1, f - i):
+                pts.append((f - i - j) * v[a] + i * v[b] + j * v[c])
+    p = np.array(pts, dtype=np.float64).reshape(-1, 3)
+    nrm = np.sqrt(p[:, 0] * p[:, 0] + p[:, 1] * p[:, 1] + p[:, 2] * p[:, 2])
+    return (p / nrm[:, None]).astype(np.float32)
+
+
+def directional(n: int, m: float, axis) -> np.ndarray:
+    """[n, 3] FP32 directions of a directional source whose radiated energy
+    per solid angle is proportional to (1 + cos theta)^m about `axis`
+    (m >= 0; m = 0 is omnidirectional).  Every ray carries energy 1/N, so
+    the pattern is the density of the rays: the Fibonacci points with
+    F_i = 1 - (2i+1)/(2n) and phi_i = i pi (3 - sqrt5) mod 2 pi, the polar
+    coordinate warped by the inverse of the pattern's distribution function
+    of cos theta, F(z) = ((1 + z)/2)^(m+1): z_i = 2 F_i^(1/(m+1)) - 1.  Local
+    frame: t1 = the unit part of h orthogonal to the axis (h = e_x, or e_y
+    when |axis_x| >= 0.9), t2 = axis x t1.  FP64, rounded once."""
+    a = np.asarray(axis, np.float32).astype(np.float64)
+    a = a / math.sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2])
+    h = np.array([1.0, 0.0, 0.0]) if abs(a[0]) < 0.9 else np.array([0.0, 1.0, 0.0])
+    t1 = h - (h[0] * a[0] + h[1] * a[1] + h[2] * a[2]) * a
+    t1 = t1 / math.sqrt(t1[0] * t1[0] + t1[1] * t1[1] + t1[2] * t1[2])
+    t2 = np.array([a[1] * t1[2] - a[2] * t1[1], a[2] * t1[0] - a[0] * t1[2], a[0] * t1[1] - a[1] * t1[0]])
+    out = np.empty((n, 3), np.float32)
+    golden = math.pi * (3.0 - math.sqrt(5.0))
+    for i in range(n):
+        F = 1.0 - (2 * i + 1) / (2.0 * n)
+        z = 2.0 * F ** (1.0 / (m + 1.0)) - 1.0
+        phi = math.fmod(i * golden, 2.0 * math.pi)
+        rho = math.sqrt(max(0.0, 1.0 - z * z))
+        x, y = rho * math.cos(phi), rho * math.sin(phi)
+        out[i] = x * t1 + y * t2 + z * a
+    return out
+
+
+def directivity(m: float, cos_theta):
+    """Energy per solid angle of the directional source relative to an
+    omnidirectional one of the same power: (m+1) (1 + cos theta)^m / 2^m."""
+    return (m + 1.0) * (1.0 + np.asarray(cos_theta, np.float64)) ** m / 2.0 ** m
 
 
 def fibonacci(n: int) -> np.ndarray:
