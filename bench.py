@@ -221,6 +221,21 @@ def run_theater(args):
     out["room_params_timing"] = {"ms": rp_ms, "algorithmic_bytes": rp_bytes,
                                  "GB_per_s": rp_bytes / (rp_ms * 1e-3) / 1e9,
                                  "shape": list(hist.shape)}
+    # source variants (not in the step): generation time of about 1e6 directions
+    sv = {}
+    for name, fn in (("icosahedral_f316", lambda: rt.icosahedral_directions(316, device=dev)),
+                     ("directional_1e6_m2", lambda: rt.directional_directions(1_000_000, 2.0, [0, 0, 1], device=dev)),
+                     ("fibonacci_1e6", lambda: rt.fibonacci_directions(1_000_000, device=dev))):
+        fn()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        for _ in range(5):
+            d = fn()
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1]) / 5
+        sv[name] = {"ms": ms, "rays": int(d.shape[0]), "GB_per_s_written": d.numel() * 4 / (ms * 1e-3) / 1e9}
+    out["source_variants"] = sv
     out["room_params_500_1k"] = {
         "receivers": [{n: (None if not np.isfinite(v) else round(float(v), 4)) for n, v in zip(names, pr[m, 3:5].mean(0))}
                       for m in range(n_rcv)],

@@ -98,6 +98,43 @@ int rt_scene_info(const rt_scene* scene, int64_t* info_host, double* diag_host);
  */
 int rt_fibonacci_directions(int64_t n, float* dirs, void* stream);
 
+/*
+ * rt_icosahedral_directions -- omnidirectional source sampled by icosahedron
+ * subdivision (section "Discrete model", one of the uniform samplings named).
+ *   f     frequency, 1 <= f <= 14000: each face is cut into f^2 triangles
+ *   dirs  [10 f^2 + 2, 3] float out (device), unit directions:
+ *         the icosahedron's vertices V_0..V_11 are the cyclic placements
+ *         (0, a, b), (a, b, 0), (b, 0, a) of a = +-1, b = +-phi (phi the golden
+ *         ratio; placements in that order, signs (-,-), (-,+), (+,-), (+,+));
+ *         edges are the vertex pairs at distance 2 (a < b, lexicographic),
+ *         faces the mutually adjacent triples (a < b < c, lexicographic).
+ *         Rows: the 12 vertices; for each edge, (f-q) V_a + q V_b for
+ *         q = 1..f-1; for each face, (f-i-j) V_a + i V_b + j V_c for i >= 1,
+ *         j >= 1, i + j <= f-1, by i then j.  Each point p is divided by
+ *         sqrt(x^2 + y^2 + z^2); FP64 without contraction, rounded once.
+ * Every ray then carries energy 1/N with N = 10 f^2 + 2.
+ */
+int rt_icosahedral_directions(int32_t f, float* dirs, void* stream);
+
+/*
+ * rt_directional_directions -- directional source sampled non-uniformly
+ * (section "Discrete model", footnote on directional sources): energy per
+ * solid angle proportional to (1 + cos theta)^m about `axis` (directivity
+ * factor m + 1 on the axis), every ray carrying the same energy 1/N, so the
+ * pattern is the density of the rays.
+ *   n          rays, 0 <= n < 2^31
+ *   m          pattern exponent, finite, >= 0 (0: omnidirectional)
+ *   axis_host  [3] float host, nonzero (normalised in FP64)
+ *   dirs       [n, 3] float out (device)
+ * Ray i: F = 1 - (2i+1)/(2n), z = 2 F^(1/(m+1)) - 1 (inverse of the
+ * distribution ((1+z)/2)^(m+1) of cos theta), phi = i pi (3 - sqrt 5) mod
+ * 2 pi, u = rho cos(phi) t1 + rho sin(phi) t2 + z axis with rho = sqrt(1 - z^2);
+ * t1 = the part of h orthogonal to the axis, normalised (h = e_x, or e_y
+ * when |axis_x| >= 0.9), t2 = axis x t1.  FP64, rounded once.
+ * Errors: RT_EINVAL (n out of range, m negative or not finite, axis zero).
+ */
+int rt_directional_directions(int64_t n, double m, const float* axis_host, float* dirs, void* stream);
+
 /* Trace options. */
 typedef struct {
     int32_t max_reflections;   /* R >= 0: segments 0..R are traced (R reflections)           */

@@ -8,4 +8,5 @@ binding (ctypes + torch tensors for device memory and streams).
 from ._lib import RtError, load  # noqa: F401
 from .api import (BandEnergy, Batch, ImageSources, ImpulseResponse, Scene, TraceResult,  # noqa: F401
                   adjoint_batch, assemble_batch, assemble_ir, band_energy_adjoint, collect_batch,
-                  collect_image_sources, fibonacci_directions, room_params, trace_batch, trace_rays, version)
+                  collect_image_sources, directional_directions, fibonacci_directions,
+                  icosahedral_directions, room_params, trace_batch, trace_rays, version)

@@ -39,6 +39,8 @@ SIGNATURES = {
     "rt_scene_destroy": (ctypes.c_int, [P]),
     "rt_scene_info": (ctypes.c_int, [P, P, P]),
     "rt_fibonacci_directions": (ctypes.c_int, [I64, P, P]),
+    "rt_icosahedral_directions": (ctypes.c_int, [I32, P, P]),
+    "rt_directional_directions": (ctypes.c_int, [I64, ctypes.c_double, P, P, P]),
     "rt_trace_rays": (ctypes.c_int, [P, P, P, P, P, P, I64, P, I32, ctypes.POINTER(TraceParams), P, P, I64, P, P,
                                      P]),
     "rt_collect_image_sources": (ctypes.c_int, [P, P, P, I32, P, I64, I32, P, I64, P, P, P, P, P, I64, P, P]),

@@ -99,6 +99,25 @@ def fibonacci_directions(n: int, device=None) -> torch.Tensor:
     return out
 
 
+def icosahedral_directions(f: int, device=None) -> torch.Tensor:
+    """rt_icosahedral_directions: the 10 f^2 + 2 grid directions of the
+    icosahedron subdivided at frequency f."""
+    dev = _dev(device)
+    out = torch.empty((10 * int(f) * int(f) + 2, 3), dtype=torch.float32, device=dev)
+    check(_lib.load().rt_icosahedral_directions(int(f), _ptr(out), _stream(dev)), "rt_icosahedral_directions")
+    return out
+
+
+def directional_directions(n: int, m: float, axis, device=None) -> torch.Tensor:
+    """rt_directional_directions: n directions of a source radiating energy
+    per solid angle proportional to (1 + cos theta)^m about `axis`."""
+    dev = _dev(device)
+    out = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    check(_lib.load().rt_directional_directions(int(n), float(m), _host_f32(axis, 3), _ptr(out), _stream(dev)),
+          "rt_directional_directions")
+    return out
+
+
 @dataclasses.dataclass
 class TraceResult:
     hit_seq: torch.Tensor          # [N, R+1] int32

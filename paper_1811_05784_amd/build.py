@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "librtac.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
-SOURCES = ["abi.hip", "sort.hip", "build.hip", "trace.hip", "collect.hip", "assemble.hip", "mlp.hip", "params.hip"]
+SOURCES = ["abi.hip", "sort.hip", "build.hip", "trace.hip", "collect.hip", "assemble.hip", "mlp.hip", "params.hip", "sources.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
