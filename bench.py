@@ -39,7 +39,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--rays", type=int, default=1_000_000)
-    ap.add_argument("--cpu-rays", type=int, default=3000, help="oracle sample size (rays)")
+    ap.add_argument("--cpu-rays", type=int, default=30000, help="oracle sample size (rays)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--leaf", type=int, default=1)
     ap.add_argument("--shade", type=int, default=0)

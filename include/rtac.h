@@ -163,6 +163,9 @@ typedef struct {
                                   the largest receiver radius and N = the rays of the call (of the
                                   job, in a batch); FP64, rounded to FP32.  Combined with
                                   max_path_length by taking the smaller limit                     */
+    int32_t xcd_pools;         /* 0 = default (on), -1 off: the ordered ray pool is cut into eighths,
+                                  one per accelerator complex (each has its own L2), which
+                                  workgroups drain first before helping the others             */
 } rt_trace_params;
 
 /*

@@ -55,6 +55,7 @@ struct TraceArgs {
     int64_t det_cap;
     unsigned long long* counters;   // [0] n_det [1] queries [2] escapes [3] error
     unsigned long long* pool;       // [0] next ray
+    unsigned long long* pool_xcd;   // NULL, or 8 counters 16 words apart: next ray of each eighth of the pool
     float* states;
     int32_t* spill;
     int32_t spill_per_lane;
@@ -83,10 +84,14 @@ struct TraceArgs {
 // queued ray: (ray, k, last plane, -) (o.x, o.y, o.z, L) (u.x, u.y, u.z, -)
 constexpr int kQueueInts = 12;
 
+constexpr int kXcd = 8;             // accelerator complexes (own L2 each); workgroup b runs on b % 8
+constexpr int kPoolWords = 32 + 16 * kXcd;
+
 __global__ void k_trace_reset(unsigned long long* counters, unsigned long long* pool, unsigned long long* stats) {
     if (threadIdx.x < 4) counters[threadIdx.x] = 0ull;
     if (stats && threadIdx.x < 4) stats[threadIdx.x] = 0ull;
-    if (threadIdx.x < 32) pool[threadIdx.x] = 0ull;   // pool counters and queue lengths of every round
+    // pool counters and queue lengths of every round, then the per-XCD counters
+    for (int i = threadIdx.x; i < kPoolWords; i += blockDim.x) pool[i] = 0ull;
 }
 
 struct Ray {
@@ -253,6 +258,12 @@ k_trace(TraceArgs a) {
     unsigned long long pool_n = a.q_in ? *a.q_in_count : (unsigned long long)a.n_rays;
     if (a.q_in && pool_n > (unsigned long long)a.q_cap) pool_n = (unsigned long long)a.q_cap;
     bool pool_empty = pool_n == 0;
+    // XCD-local ray pools: the (direction-sorted) pool is cut into eighths and
+    // a workgroup first takes rays from the eighth of its own XCD, so each L2
+    // sees one cone of directions; it then helps the others
+    const bool by_xcd = a.pool_xcd != nullptr && !a.q_in;
+    const int home = (int)(blockIdx.x % kXcd);
+    uint32_t seg_done = 0;
 
     for (;;) {
         // ---- refill idle lanes from the ray pool -----------------------------
@@ -260,13 +271,36 @@ k_trace(TraceArgs a) {
         const int n_idle = __popcll(idle);
         if (!pool_empty && n_idle > 0 && (n_idle >= a.fetch_thr || n_idle == kWave)) {
             const int leader = __ffsll((long long)idle) - 1;
-            unsigned long long base = 0;
-            if (lane == leader) base = atomicAdd(a.pool, (unsigned long long)n_idle);
-            base = __shfl(base, leader);
-            if (base + (unsigned long long)n_idle >= pool_n) pool_empty = true;
-            if (status == kIdle) {
+            unsigned long long base = 0, hi = pool_n;   // this refill may take pool positions [base, hi)
+            if (by_xcd) {
+                if (lane == leader) {
+                    base = ~0ull;
+                    for (int t = 0; t < kXcd; t++) {
+                        const int sg = (home + t) % kXcd;
+                        if ((seg_done >> sg) & 1u) continue;
+                        const unsigned long long lo = pool_n * (unsigned long long)sg / kXcd;
+                        const unsigned long long shi = pool_n * (unsigned long long)(sg + 1) / kXcd;
+                        const unsigned long long b = lo + atomicAdd(a.pool_xcd + 16 * sg, (unsigned long long)n_idle);
+                        if (b < shi) {
+                            base = b;
+                            hi = shi;
+                            break;
+                        }
+                        seg_done |= 1u << sg;
+                    }
+                }
+                base = __shfl(base, leader);
+                hi = __shfl(hi, leader);
+                seg_done = __shfl(seg_done, leader);
+                if (base == ~0ull) pool_empty = true;
+            } else {
+                if (lane == leader) base = atomicAdd(a.pool, (unsigned long long)n_idle);
+                base = __shfl(base, leader);
+                if (base + (unsigned long long)n_idle >= pool_n) pool_empty = true;
+            }
+            if (status == kIdle && base != ~0ull) {
                 const unsigned long long my = base + (unsigned long long)__popcll(idle & lt_mask);
-                if (my < pool_n) {
+                if (my < hi) {
                     if (kBatch && !a.q_in) {
                         const int64_t g = a.order ? (int64_t)a.order[my] : (int64_t)my;
                         const DevJob& jb = a.jobs[job_of_ray(a.jobs, a.n_jobs, g)];
@@ -845,6 +879,7 @@ int run_trace(rt_scene* ws, TraceArgs& a, const rt_trace_params* p, int depth, i
     if (p->kernel_event_start) RT_HIP(hipEventRecord((hipEvent_t)p->kernel_event_start, st));
     for (int rd = 0; rd < rounds; rd++) {
         a.pool = pool + rd;
+        a.pool_xcd = rd == 0 && p->xcd_pools >= 0 ? pool + 32 : nullptr;
         a.q_in = rd == 0 ? nullptr : qbuf[(rd - 1) & 1];
         a.q_in_count = rd == 0 ? nullptr : pool + 16 + (rd - 1);
         a.q_out = rd + 1 < rounds ? qbuf[rd & 1] : nullptr;
@@ -865,6 +900,7 @@ int check_params(const rt_trace_params* p) {
              "max_reflections must be in [0, 4096)");
     RT_CHECK(p->suspend_after >= 0, RT_EINVAL, "suspend_after must be >= 0");
     RT_CHECK(p->min_beam_rays >= 0, RT_EINVAL, "min_beam_rays must be >= 0");
+    RT_CHECK(p->xcd_pools >= -1 && p->xcd_pools <= 0, RT_EINVAL, "xcd_pools must be 0 or -1");
     return RT_OK;
 }
 
@@ -887,7 +923,7 @@ extern "C" int rt_trace_rays(const rt_scene* scene, const float* src_host, const
     RT_CHECK(n_rays == 0 || (dirs && hit_seq), RT_EINVAL, "rt_trace_rays: dirs/hit_seq is NULL");
     hipStream_t st = (hipStream_t)stream;
     rt_scene* s = const_cast<rt_scene*>(scene);
-    if (s->ws.trace_pool.ensure(32 * sizeof(unsigned long long))) return RT_ENOMEM;
+    if (s->ws.trace_pool.ensure(kPoolWords * sizeof(unsigned long long))) return RT_ENOMEM;
     unsigned long long* pool = s->ws.trace_pool.as<unsigned long long>();
     hipLaunchKernelGGL(k_trace_reset, dim3(1), dim3(64), 0, st, (unsigned long long*)counters, pool,
                        (unsigned long long*)p->stats);
@@ -1029,7 +1065,7 @@ extern "C" int rt_trace_batch(rt_batch* b, const float* rcv, const rt_trace_para
     RT_CHECK(det_cap >= 0 && (det_cap == 0 || det), RT_EINVAL, "rt_trace_batch: det is NULL");
     hipStream_t st = (hipStream_t)stream;
     rt_scene* s = b->ws_owner;
-    if (s->ws.trace_pool.ensure(32 * sizeof(unsigned long long))) return RT_ENOMEM;
+    if (s->ws.trace_pool.ensure(kPoolWords * sizeof(unsigned long long))) return RT_ENOMEM;
     unsigned long long* pool = s->ws.trace_pool.as<unsigned long long>();
     hipLaunchKernelGGL(k_trace_reset, dim3(1), dim3(64), 0, st, (unsigned long long*)counters, pool,
                        (unsigned long long*)p->stats);
