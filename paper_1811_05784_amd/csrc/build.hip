@@ -40,15 +40,15 @@ __host__ __device__ inline float funord(uint32_t u) {
     return __builtin_bit_cast(float, b);
 }
 
-// bounds[0..5] = vertex box (min xyz ordered, max xyz ordered),
-// bounds[6..11] = centroid box; info[0] = error bits, info[1] = max material.
-// Bounds are reduced in LDS first: one atomic per workgroup and bound.
+// Per workgroup: part[14 b + 0..5] = vertex box (min xyz ordered, max xyz
+// ordered), [6..11] = centroid box, [12] = error bits, [13] = max material;
+// k_prep_reduce folds the workgroups' values (no contended global atomics).
 __global__ void __launch_bounds__(256) k_tri_prep(const float* __restrict__ vtx, int64_t nv,
                                                   const int3* __restrict__ tri, int64_t nt,
                                                   const int32_t* __restrict__ material,
                                                   const int32_t* __restrict__ plane_id, float* __restrict__ tri_box,
-                                                  float* __restrict__ centroid, uint32_t* __restrict__ bounds,
-                                                  uint32_t* __restrict__ info, int32_t* __restrict__ prep) {
+                                                  float* __restrict__ centroid, uint32_t* __restrict__ part,
+                                                  int32_t* __restrict__ prep) {
     __shared__ uint32_t sb[12];
     __shared__ uint32_t s_err, s_mat;
     const int tid = threadIdx.x;
@@ -142,13 +142,41 @@ __global__ void __launch_bounds__(256) k_tri_prep(const float* __restrict__ vtx,
         atomicMax(&s_mat, mat_l);
     }
     __syncthreads();
-    if (tid < 12) {
-        if ((tid % 6) < 3) atomicMin(&bounds[tid], sb[tid]);
-        else atomicMax(&bounds[tid], sb[tid]);
-    }
-    if (tid == 0) {
-        if (s_err) atomicOr(&info[0], s_err);
-        atomicMax(&info[1], s_mat);
+    uint32_t* pb = part + 14 * (int64_t)blockIdx.x;
+    if (tid < 12) pb[tid] = sb[tid];
+    if (tid == 12) pb[12] = s_err;
+    if (tid == 13) pb[13] = s_mat;
+}
+
+// bounds[0..11] and info[0..1] from the per-workgroup values of k_tri_prep
+// (one workgroup; min / max / or in a fixed order).
+__global__ void __launch_bounds__(256) k_prep_reduce(const uint32_t* __restrict__ part, int64_t nb,
+                                                     uint32_t* __restrict__ bounds, uint32_t* __restrict__ info) {
+    __shared__ uint32_t red[14][256 / kWave];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+    uint32_t v[14];
+    for (int k = 0; k < 14; k++) v[k] = (k < 12 && (k % 6) < 3) ? 0xFFFFFFFFu : 0u;
+    for (int64_t b = tid; b < nb; b += 256)
+        for (int k = 0; k < 14; k++) {
+            const uint32_t x = part[14 * b + k];
+            v[k] = k == 12 ? (v[k] | x) : ((k < 12 && (k % 6) < 3) ? (x < v[k] ? x : v[k]) : (x > v[k] ? x : v[k]));
+        }
+    for (int off = kWave / 2; off > 0; off >>= 1)
+        for (int k = 0; k < 14; k++) {
+            const uint32_t x = __shfl_down(v[k], off);
+            v[k] = k == 12 ? (v[k] | x) : ((k < 12 && (k % 6) < 3) ? (x < v[k] ? x : v[k]) : (x > v[k] ? x : v[k]));
+        }
+    if (lane == 0)
+        for (int k = 0; k < 14; k++) red[k][w] = v[k];
+    __syncthreads();
+    if (tid < 14) {
+        uint32_t r = red[tid][0];
+        for (int j = 1; j < 256 / kWave; j++) {
+            const uint32_t x = red[tid][j];
+            r = tid == 12 ? (r | x) : ((tid < 12 && (tid % 6) < 3) ? (x < r ? x : r) : (x > r ? x : r));
+        }
+        if (tid < 12) bounds[tid] = r;
+        else info[tid - 12] = r;
     }
 }
 
@@ -427,16 +455,25 @@ __device__ inline uint32_t emit4_one(int64_t i, const int32_t* __restrict__ left
     return (uint32_t)(depth_in[i] / 2 + 1);
 }
 
+// Flagged binary nodes, listed in the order of their 4-wide node index.
+__global__ void k_list4(int64_t n_in, const uint32_t* __restrict__ flag, const uint32_t* __restrict__ index,
+                        int32_t* __restrict__ list) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_in && flag[i]) list[index[i]] = (int32_t)i;
+}
+
+// One thread per 4-wide node (the count index[n_in] is read on the device).
 __global__ void k_emit4(int64_t n_in, const int32_t* __restrict__ left, const int32_t* __restrict__ right,
                         const int32_t* __restrict__ first, const int32_t* __restrict__ last,
-                        const uint32_t* __restrict__ flag, const uint32_t* __restrict__ index,
+                        const int32_t* __restrict__ list, const uint32_t* __restrict__ index,
                         const int32_t* __restrict__ depth_in, const float* __restrict__ box_in,
                         const float* __restrict__ tri_box, const uint32_t* __restrict__ order, int32_t leaf_size,
                         Node4* __restrict__ nodes, uint32_t* __restrict__ info) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n4 = (int64_t)index[n_in];
     uint32_t d = 0;
-    if (i < n_in && flag[i])
-        d = emit4_one(i, left, right, first, last, index, depth_in, box_in, tri_box, order, leaf_size, nodes);
+    if (j < n4)
+        d = emit4_one(list[j], left, right, first, last, index, depth_in, box_in, tri_box, order, leaf_size, nodes);
     // tree depth: one atomic per wavefront
     for (int off = kWave / 2; off > 0; off >>= 1) {
         const uint32_t o = __shfl_down(d, off);
@@ -561,20 +598,22 @@ extern "C" int rt_build_tree(const float* vtx, int64_t n_vtx, const int32_t* tri
     float* cen = tmp.get<float>(3 * nt);
     uint32_t* bounds = tmp.get<uint32_t>(12);
     uint32_t* info = tmp.get<uint32_t>(4);
+    uint32_t* prep_part = tmp.get<uint32_t>(14 * (int64_t)blocks(nt));
     int32_t* prep = tmp.get<int32_t>(nt);
     uint64_t* codes0 = tmp.get<uint64_t>(nt);
     uint64_t* codes1 = tmp.get<uint64_t>(nt);
     uint32_t* ord0 = tmp.get<uint32_t>(nt);
     uint32_t* ord1 = tmp.get<uint32_t>(nt);
     if (!s->plane_n || !s->plane_p || !s->plane_mat || !s->tri_plane || !s->tri_rec || !s->nodes || !tri_box ||
-        !cen || !bounds || !info || !prep || !codes0 || !codes1 || !ord0 || !ord1) {
+        !cen || !bounds || !info || !prep_part || !prep || !codes0 || !codes1 || !ord0 || !ord1) {
         set_error("rt_build_tree: out of device memory");
         return fail(RT_ENOMEM);
     }
     hipLaunchKernelGGL(k_init_bounds, dim3(1), dim3(64), 0, st, bounds, info);
     hipLaunchKernelGGL(k_fill_i32, dim3(blocks(nt)), dim3(256), 0, st, prep, nt, INT32_MAX);
     hipLaunchKernelGGL(k_tri_prep, dim3(blocks(nt)), dim3(256), 0, st, vtx, n_vtx, (const int3*)tri, nt, material,
-                       plane_id, tri_box, cen, bounds, info, prep);
+                       plane_id, tri_box, cen, prep_part, prep);
+    hipLaunchKernelGGL(k_prep_reduce, dim3(1), dim3(256), 0, st, prep_part, (int64_t)blocks(nt), bounds, info);
     hipLaunchKernelGGL(k_plane_table, dim3(blocks(nt)), dim3(256), 0, st, vtx, (const int3*)tri, nt, material, prep,
                        s->plane_n, s->plane_p, s->plane_mat);
     hipLaunchKernelGGL(k_coplanar, dim3(blocks(nt)), dim3(256), 0, st, vtx, n_vtx, (const int3*)tri, nt, material,
@@ -599,8 +638,9 @@ extern "C" int rt_build_tree(const float* vtx, int64_t n_vtx, const int32_t* tri
         float* box_in = tmp.get<float>(6 * n_in);
         uint32_t* flag = tmp.get<uint32_t>(n_in);
         uint32_t* index = tmp.get<uint32_t>(n_in + 1);
+        int32_t* list4 = tmp.get<int32_t>(n_in);
         if (!left || !right || !first || !last || !par_in || !par_leaf || !depth || !box_in || !flag ||
-            !index) {
+            !index || !list4) {
             set_error("rt_build_tree: out of device memory");
             return fail(RT_ENOMEM);
         }
@@ -640,7 +680,8 @@ extern "C" int rt_build_tree(const float* vtx, int64_t n_vtx, const int32_t* tri
                            depth);
         rc = exclusive_scan_u32(s->ws, flag, index, n_in, nullptr, st);
         if (rc) return fail(rc);
-        hipLaunchKernelGGL(k_emit4, dim3(blocks(n_in)), dim3(256), 0, st, n_in, left, right, first, last, flag,
+        hipLaunchKernelGGL(k_list4, dim3(blocks(n_in)), dim3(256), 0, st, n_in, flag, index, list4);
+        hipLaunchKernelGGL(k_emit4, dim3(blocks(n_in)), dim3(256), 0, st, n_in, left, right, first, last, list4,
                            index, depth, box_in, tri_box, order, leaf, s->nodes, info);
         hipLaunchKernelGGL(k_copy_u32, dim3(1), dim3(1), 0, st, index + n_in, n4_dev);
     }

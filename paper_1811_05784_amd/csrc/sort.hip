@@ -14,8 +14,8 @@ namespace rtac {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kItems = 16;
-constexpr int kTile = kThreads * kItems;   // 4096 keys per workgroup
+constexpr int kItems = 4;
+constexpr int kTile = kThreads * kItems;   // 1024 keys per workgroup
 constexpr int kWaves = kThreads / kWave;
 
 __device__ inline int64_t count_of(const int64_t* n_dev, int64_t cap) {
