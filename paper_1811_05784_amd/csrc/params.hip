@@ -27,6 +27,7 @@ constexpr int kPW = kPT / kWave;
 constexpr int kPItems = 16;                // bins per thread
 constexpr int64_t kChunk = (int64_t)kPT * kPItems;
 constexpr int kNSum = 11;                  // regression sums (2 x 5) + lowest dB
+constexpr double kRatio36 = 2.5118864315095795e-4;   // 10^-3.6: a bin this far down is below -36 dB
 
 struct ChunkSums {
     double h, sh;            // sum H, sum s H (global bin index s)
@@ -198,7 +199,14 @@ __global__ void __launch_bounds__(kPT) k_rp_edc(const float* __restrict__ hist, 
         const int64_t s = i0 + j;
         if (s >= B.s0 && s <= B.last) {
             const double edc = B.tot - before;
-            const double db = 10.0 * log10(edc / B.tot);
+            const double ratio = edc / B.tot;
+            if (!(ratio >= kRatio36)) {
+                // below -36 dB: outside both windows; only `lowest dB <= -35` matters
+                rs[10] = fmin(rs[10], -1000.0);
+                before += v[j];
+                continue;
+            }
+            const double db = 10.0 * log10(ratio);
             const double x = (double)(s - B.s0) / fs;
             if (db < rs[10]) rs[10] = db;
             if (db <= 0.0 && db >= -10.0) {
