@@ -166,6 +166,9 @@ typedef struct {
     int32_t xcd_pools;         /* 0 = default (on), -1 off: the ordered ray pool is cut into eighths,
                                   one per accelerator complex (each has its own L2), which
                                   workgroups drain first before helping the others             */
+    int32_t coop_queries;      /* 0 = default (on), -1 off: once every ray has been handed out, a
+                                  wavefront left with a single query in flight searches it with
+                                  all 64 lanes, breadth first (same nearest hit)                */
 } rt_trace_params;
 
 /*

@@ -18,6 +18,12 @@
 // finished wait until enough of the wavefront is finished, then shade
 // together: the chosen triangle's plane crossing, receiver tests and the
 // reflection are evaluated in FP64 and rounded once to FP32.
+//
+// Once every ray has been handed out, the launch ends with the longest
+// bounce chains, often one per wavefront.  A wavefront left with a single
+// query in flight then searches it with all 64 lanes, breadth first over a
+// frontier of tree nodes in LDS, which takes about as many steps as the tree
+// is deep instead of one node per step (same nearest hit).
 #include "common.h"
 
 namespace rtac {
@@ -75,6 +81,7 @@ struct TraceArgs {
     int32_t spill_thr;
     int32_t suspend_k;              // > 0: a ray about to start segment >= suspend_k goes to q_out
     int32_t beam_n;                 // > 0: range limit of the discrete model with beams of >= beam_n rays
+    int32_t coop;                   // nonzero: a wavefront left with one query searches it with all lanes
     // batched calls: rays of many jobs (source + receivers in one scene)
     const DevJob* jobs;
     const DevScene* scenes;
@@ -404,6 +411,175 @@ k_trace(TraceArgs a) {
         if (__ballot(status != kIdle) == 0ull) {
             if (pool_empty) break;
             continue;
+        }
+
+        // ---- one query left in the wavefront: search it with every lane -------
+        // Breadth first over a frontier of inner nodes kept in the wavefront's
+        // LDS stack area (the owner's own stack is dropped, the other lanes'
+        // are empty): each step every lane expands one frontier node, tests
+        // the leaves it reaches and the wavefront keeps the nearest hit (exact
+        // ties to the lowest triangle id), so the result is the owner's own
+        // walk's, in about tree-depth steps instead of one node per step.
+        if (!kBatch && a.coop && pool_empty) {
+            const uint64_t act = __ballot(status == kQuery);
+            if (__popcll(act) == 1 && __ballot(status == kDone) == 0ull) {
+                const int owner = __ffsll((long long)act) - 1;
+                // wave-uniform copies of the owner's query (scalar registers)
+                auto rdf = [owner](float x) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), owner)); };
+                Ray q;
+                q.ox = rdf(r.ox);
+                q.oy = rdf(r.oy);
+                q.oz = rdf(r.oz);
+                q.ux = rdf(r.ux);
+                q.uy = rdf(r.uy);
+                q.uz = rdf(r.uz);
+                setup_ray(q);
+                const int32_t qlp = __builtin_amdgcn_readlane(last_plane, owner);
+                float bt = rdf(best_t);
+                int32_t bid = __builtin_amdgcn_readlane(best_id, owner), bj = __builtin_amdgcn_readlane(best_j, owner);
+                // frontier: refs in slots 0..7, entry distances in slots 8..15 of the wave's columns
+                int32_t* fref = lds_stack + (tid - lane);
+                float* ft = reinterpret_cast<float*>(lds_stack + 8 * kBlock + (tid - lane));
+                auto fat = [](int k) { return (k >> 6) * kBlock + (k & (kWave - 1)); };
+                constexpr int kCoopCap = 8 * kWave;
+                int nf = 1;
+                if (lane == 0) {
+                    fref[0] = 0;
+                    ft[0] = 0.f;
+                }
+                bool ok = true;
+                int csteps = 0;
+                while (nf > 0) {
+                    if (++csteps > a.max_steps) {
+                        ok = false;
+                        break;
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    const int take = nf < kWave ? nf : kWave;
+                    const int base = nf - take;   // the most recent entries, deepest first
+                    int32_t item = -1;
+                    float it = INFINITY;
+                    if (lane < take) {
+                        item = fref[fat(base + lane)];
+                        it = ft[fat(base + lane)];
+                    }
+                    nf = base;
+                    float tn[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
+                    int32_t rf[4] = {kEmpty, kEmpty, kEmpty, kEmpty};
+                    float lt = bt;
+                    int32_t lid = bid, lj = bj;
+                    bool bad = item >= n_nodes;
+                    if (item >= 0 && item < n_nodes && it <= bt) {
+                        const float4* np = reinterpret_cast<const float4*>(nodes + item);
+                        const float4 lx = np[0], hx = np[1], ly = np[2], hy = np[3], lz = np[4], hz = np[5];
+                        const int4 ch = reinterpret_cast<const int4*>(np)[6];
+                        const float tlim = bt;
+#define RT_SLAB(S, LX, HX, LY, HY, LZ, HZ, CH)                                          \
+    {                                                                                    \
+        const float t0x = (LX - q.ox) * q.ix, t1x = (HX - q.ox) * q.ix;                  \
+        const float t0y = (LY - q.oy) * q.iy, t1y = (HY - q.oy) * q.iy;                  \
+        const float t0z = (LZ - q.oz) * q.iz, t1z = (HZ - q.oz) * q.iz;                  \
+        const float tmin = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)),               \
+                                 fmaxf(fminf(t0z, t1z), 0.f));                           \
+        float tmax = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z));    \
+        tmax *= 1.00000036f;                                                             \
+        const bool h = (CH != kEmpty) && tmin <= tmax && tmin <= tlim;                   \
+        tn[S] = h ? tmin : INFINITY;                                                     \
+        rf[S] = h ? CH : kEmpty;                                                         \
+    }
+                        RT_SLAB(0, lx.x, hx.x, ly.x, hy.x, lz.x, hz.x, ch.x)
+                        RT_SLAB(1, lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, ch.y)
+                        RT_SLAB(2, lx.z, hx.z, ly.z, hy.z, lz.z, hz.z, ch.z)
+                        RT_SLAB(3, lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, ch.w)
+#undef RT_SLAB
+#pragma unroll
+                        for (int sl = 0; sl < 4; sl++) {
+                            if (rf[sl] < 0 && rf[sl] != kEmpty) {
+                                const int32_t first = leaf_first(rf[sl]), cnt = leaf_count(rf[sl]);
+                                rf[sl] = kEmpty;
+                                if (first + cnt > n_tri) {
+                                    bad = true;
+                                } else {
+                                    for (int i = 0; i < cnt; i++) {
+                                        const int32_t j = first + i;
+                                        const float4 v0 = tri[3 * j], v1 = tri[3 * j + 1], v2 = tri[3 * j + 2];
+                                        if (__float_as_int(v0.w) == qlp) continue;
+                                        const float t = watertight(q, v0, v1, v2);
+                                        const int32_t id = __float_as_int(v1.w);
+                                        if (t > 0.f && (t < lt || (t == lt && id < lid))) {
+                                            lt = t;
+                                            lid = id;
+                                            lj = j;
+                                        }
+                                    }
+                                }
+                            }
+                        }
+                    }
+                    if (__ballot(bad)) {
+                        ok = false;
+                        break;
+                    }
+                    // nearest hit of the wavefront: (t, id) lexicographic minimum
+                    for (int off = kWave / 2; off > 0; off >>= 1) {
+                        const float ot = __shfl_xor(lt, off);
+                        const int32_t oid = __shfl_xor(lid, off), oj = __shfl_xor(lj, off);
+                        if (ot < lt || (ot == lt && oid < lid)) {
+                            lt = ot;
+                            lid = oid;
+                            lj = oj;
+                        }
+                    }
+                    bt = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(lt)));
+                    bid = __builtin_amdgcn_readfirstlane(lid);
+                    bj = __builtin_amdgcn_readfirstlane(lj);
+                    // children that can still hold a nearer or equal hit join the frontier
+                    int cnt = 0;
+#pragma unroll
+                    for (int sl = 0; sl < 4; sl++) cnt += (rf[sl] >= 0 && tn[sl] <= bt) ? 1 : 0;
+                    int incl = cnt;
+                    for (int off = 1; off < kWave; off <<= 1) {
+                        const int x = __shfl_up(incl, off);
+                        if (lane >= off) incl += x;
+                    }
+                    const int total = __builtin_amdgcn_readlane(incl, kWave - 1);
+                    if (nf + total > kCoopCap) {
+                        ok = false;
+                        break;
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    int at = nf + incl - cnt;
+                    // far children first, so that the nearest are taken next
+#pragma unroll
+                    for (int sl = 3; sl >= 0; sl--) {
+                        if (rf[sl] >= 0 && tn[sl] <= bt) {
+                            fref[fat(at)] = rf[sl];
+                            ft[fat(at)] = tn[sl];
+                            at++;
+                        }
+                    }
+                    nf += total;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                if (lane == owner) {
+                    best_t = bt;
+                    best_id = bid;
+                    best_j = bj;
+                    st = Stack{0, 0, 0};
+                    if (ok) {
+                        status = kDone;
+                    } else {
+                        cur = 0;   // fall back: the owner's own walk from the root, bounded by the hit so far
+                        steps = 0;
+                    }
+                }
+            }
         }
 
         // ---- traverse until enough lanes have finished their query -----------
@@ -901,6 +1077,7 @@ int check_params(const rt_trace_params* p) {
     RT_CHECK(p->suspend_after >= 0, RT_EINVAL, "suspend_after must be >= 0");
     RT_CHECK(p->min_beam_rays >= 0, RT_EINVAL, "min_beam_rays must be >= 0");
     RT_CHECK(p->xcd_pools >= -1 && p->xcd_pools <= 0, RT_EINVAL, "xcd_pools must be 0 or -1");
+    RT_CHECK(p->coop_queries >= -1 && p->coop_queries <= 0, RT_EINVAL, "coop_queries must be 0 or -1");
     return RT_OK;
 }
 
@@ -951,6 +1128,7 @@ extern "C" int rt_trace_rays(const rt_scene* scene, const float* src_host, const
     a.R = p->max_reflections;
     a.max_len = p->max_path_length;
     a.beam_n = p->min_beam_rays;
+    a.coop = p->coop_queries >= 0 ? 1 : 0;
     a.record = p->record_states ? 1 : 0;
     a.hit_seq = hit_seq;
     a.det = det;
@@ -1074,6 +1252,7 @@ extern "C" int rt_trace_batch(rt_batch* b, const float* rcv, const rt_trace_para
     a.rcv = rcv;
     a.R = p->max_reflections;
     a.beam_n = p->min_beam_rays;
+    a.coop = p->coop_queries >= 0 ? 1 : 0;
     a.hit_seq = hit_seq;
     a.det = det;
     a.det_cap = det_cap;

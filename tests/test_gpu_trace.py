@@ -224,10 +224,15 @@ def _sorted_det(tr):
                                          ("c2", 20, 50_000, dict(suspend_after=3)),
                                          ("c2", 20, 50_000, dict(suspend_after=20)),
                                          ("c2", 20, 50_000, dict(rounds=3, spill_threshold=40)),
-                                         ("c3", 60, 200_000, dict(suspend_after=2))])
+                                         ("c3", 60, 200_000, dict(suspend_after=2)),
+                                         ("c1", 20, 10_000, dict(coop_queries=-1)),
+                                         ("c2", 20, 50_000, dict(coop_queries=-1)),
+                                         ("c3", 60, 1_000_000, dict(coop_queries=-1)),
+                                         ("c3", 60, 1_000_000, dict(coop_queries=-1, xcd_pools=-1))])
 def test_scheduling_leaves_results_unchanged(rt, scenes, name, R, n, kw):
-    """Suspension into a second launch and continuation rounds reorder work
-    only: hit sequences, detections and counters are identical."""
+    """Suspension into a second launch, continuation rounds, per-XCD pools and
+    single queries searched by whole wavefronts reorder work only: hit
+    sequences, detections and counters are identical."""
     s, sc = scenes[name]
     dirs = rt.fibonacci_directions(n, device="cuda:0")
     mpl = s.max_path_length if name == "c3" else 0.0
