@@ -168,7 +168,8 @@ typedef struct {
                                   workgroups drain first before helping the others             */
     int32_t coop_queries;      /* 0 = default (on), -1 off: once every ray has been handed out, a
                                   wavefront left with a single query in flight searches it with
-                                  all 64 lanes, breadth first (same nearest hit)                */
+                                  all 64 lanes, breadth first (two queries: 32 lanes each; same
+                                  nearest hit)                                                  */
 } rt_trace_params;
 
 /*

@@ -20,10 +20,11 @@
 // reflection are evaluated in FP64 and rounded once to FP32.
 //
 // Once every ray has been handed out, the launch ends with the longest
-// bounce chains, often one per wavefront.  A wavefront left with a single
-// query in flight then searches it with all 64 lanes, breadth first over a
-// frontier of tree nodes in LDS, which takes about as many steps as the tree
-// is deep instead of one node per step (same nearest hit).
+// bounce chains, often one or two per wavefront.  A wavefront left with a
+// single query in flight then searches it with all 64 lanes (two queries:
+// 32 lanes each), breadth first over a frontier of tree nodes in LDS, which
+// takes about as many steps as the tree is deep instead of one node per step
+// (same nearest hit).
 #include "common.h"
 
 namespace rtac {
@@ -576,6 +577,168 @@ k_trace(TraceArgs a) {
                         status = kDone;
                     } else {
                         cur = 0;   // fall back: the owner's own walk from the root, bounded by the hit so far
+                        steps = 0;
+                    }
+                }
+            } else if (__popcll(act) == 2 && __ballot(status == kDone) == 0ull) {
+                // two queries left: each half of the wavefront searches one of them the same way
+                const int g = lane >> 5, li = lane & 31;
+                const int own0 = __ffsll((long long)act) - 1;
+                const int own1 = __ffsll((long long)(act & (act - 1))) - 1;
+                const int mo = g ? own1 : own0;
+                Ray q;
+                q.ox = __shfl(r.ox, mo);
+                q.oy = __shfl(r.oy, mo);
+                q.oz = __shfl(r.oz, mo);
+                q.ux = __shfl(r.ux, mo);
+                q.uy = __shfl(r.uy, mo);
+                q.uz = __shfl(r.uz, mo);
+                setup_ray(q);
+                const int32_t qlp = __shfl(last_plane, mo);
+                float bt = __shfl(best_t, mo);
+                int32_t bid = __shfl(best_id, mo), bj = __shfl(best_j, mo);
+                // per half: refs in slots 0..7, entry distances in slots 8..15 of its 32 columns
+                int32_t* fref = lds_stack + (tid - lane) + 32 * g;
+                float* ft = reinterpret_cast<float*>(lds_stack + 8 * kBlock + (tid - lane) + 32 * g);
+                auto fat = [](int k) { return (k >> 5) * kBlock + (k & 31); };
+                constexpr int kCap2 = 8 * 32;
+                int nf = 1;
+                if (li == 0) {
+                    fref[0] = 0;
+                    ft[0] = 0.f;
+                }
+                bool ok = true;
+                int csteps = 0;
+                while (__ballot(nf > 0) != 0ull) {
+                    if (++csteps > a.max_steps) {
+                        ok = false;
+                        break;
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    const int take = nf < 32 ? nf : 32;
+                    const int base = nf - take;
+                    int32_t item = -1;
+                    float it = INFINITY;
+                    if (li < take) {
+                        item = fref[fat(base + li)];
+                        it = ft[fat(base + li)];
+                    }
+                    nf = base;
+                    float tn[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
+                    int32_t rf[4] = {kEmpty, kEmpty, kEmpty, kEmpty};
+                    float lt = bt;
+                    int32_t lid = bid, lj = bj;
+                    bool bad = item >= n_nodes;
+                    if (item >= 0 && item < n_nodes && it <= bt) {
+                        const float4* np = reinterpret_cast<const float4*>(nodes + item);
+                        const float4 lx = np[0], hx = np[1], ly = np[2], hy = np[3], lz = np[4], hz = np[5];
+                        const int4 ch = reinterpret_cast<const int4*>(np)[6];
+                        const float tlim = bt;
+#define RT_SLAB(S, LX, HX, LY, HY, LZ, HZ, CH)                                          \
+    {                                                                                    \
+        const float t0x = (LX - q.ox) * q.ix, t1x = (HX - q.ox) * q.ix;                  \
+        const float t0y = (LY - q.oy) * q.iy, t1y = (HY - q.oy) * q.iy;                  \
+        const float t0z = (LZ - q.oz) * q.iz, t1z = (HZ - q.oz) * q.iz;                  \
+        const float tmin = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)),               \
+                                 fmaxf(fminf(t0z, t1z), 0.f));                           \
+        float tmax = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z));    \
+        tmax *= 1.00000036f;                                                             \
+        const bool h = (CH != kEmpty) && tmin <= tmax && tmin <= tlim;                   \
+        tn[S] = h ? tmin : INFINITY;                                                     \
+        rf[S] = h ? CH : kEmpty;                                                         \
+    }
+                        RT_SLAB(0, lx.x, hx.x, ly.x, hy.x, lz.x, hz.x, ch.x)
+                        RT_SLAB(1, lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, ch.y)
+                        RT_SLAB(2, lx.z, hx.z, ly.z, hy.z, lz.z, hz.z, ch.z)
+                        RT_SLAB(3, lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, ch.w)
+#undef RT_SLAB
+#pragma unroll
+                        for (int sl = 0; sl < 4; sl++) {
+                            if (rf[sl] < 0 && rf[sl] != kEmpty) {
+                                const int32_t first = leaf_first(rf[sl]), cnt = leaf_count(rf[sl]);
+                                rf[sl] = kEmpty;
+                                if (first + cnt > n_tri) {
+                                    bad = true;
+                                } else {
+                                    for (int i = 0; i < cnt; i++) {
+                                        const int32_t j = first + i;
+                                        const float4 v0 = tri[3 * j], v1 = tri[3 * j + 1], v2 = tri[3 * j + 2];
+                                        if (__float_as_int(v0.w) == qlp) continue;
+                                        const float t = watertight(q, v0, v1, v2);
+                                        const int32_t id = __float_as_int(v1.w);
+                                        if (t > 0.f && (t < lt || (t == lt && id < lid))) {
+                                            lt = t;
+                                            lid = id;
+                                            lj = j;
+                                        }
+                                    }
+                                }
+                            }
+                        }
+                    }
+                    if (__ballot(bad)) {
+                        ok = false;
+                        break;
+                    }
+                    // nearest hit of each half: (t, id) lexicographic minimum over its 32 lanes
+                    for (int off = 16; off > 0; off >>= 1) {
+                        const float ot = __shfl_xor(lt, off);
+                        const int32_t oid = __shfl_xor(lid, off), oj = __shfl_xor(lj, off);
+                        if (ot < lt || (ot == lt && oid < lid)) {
+                            lt = ot;
+                            lid = oid;
+                            lj = oj;
+                        }
+                    }
+                    bt = lt;
+                    bid = lid;
+                    bj = lj;
+                    int cnt = 0;
+#pragma unroll
+                    for (int sl = 0; sl < 4; sl++) cnt += (rf[sl] >= 0 && tn[sl] <= bt) ? 1 : 0;
+                    int incl = cnt;
+                    for (int off = 1; off < 32; off <<= 1) {
+                        const int x = __shfl_up(incl, off);
+                        if (li >= off) incl += x;
+                    }
+                    const int total = __shfl(incl, (lane & 32) + 31);
+                    if (__ballot(nf + total > kCap2) != 0ull) {
+                        ok = false;
+                        break;
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    int at = nf + incl - cnt;
+#pragma unroll
+                    for (int sl = 3; sl >= 0; sl--) {
+                        if (rf[sl] >= 0 && tn[sl] <= bt) {
+                            fref[fat(at)] = rf[sl];
+                            ft[fat(at)] = tn[sl];
+                            at++;
+                        }
+                    }
+                    nf += total;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                // each owner takes its half's result (an owner may sit in either half)
+                const float bt0 = __shfl(bt, 0), bt1 = __shfl(bt, 32);
+                const int32_t bid0 = __shfl(bid, 0), bid1 = __shfl(bid, 32);
+                const int32_t bj0 = __shfl(bj, 0), bj1 = __shfl(bj, 32);
+                if (lane == own0 || lane == own1) {
+                    const bool first = lane == own0;
+                    best_t = first ? bt0 : bt1;
+                    best_id = first ? bid0 : bid1;
+                    best_j = first ? bj0 : bj1;
+                    st = Stack{0, 0, 0};
+                    if (ok) {
+                        status = kDone;
+                    } else {
+                        cur = 0;
                         steps = 0;
                     }
                 }
