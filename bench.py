@@ -64,7 +64,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="rooms: skip the launch autotuner")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (the ray set would be split "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (the ray set would be split "
               "by ray id across GPUs with the scene replicated; not implemented). Use --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
