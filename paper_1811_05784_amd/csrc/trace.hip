@@ -1157,7 +1157,9 @@ namespace {
 // fill, launches.  `ws` is the scene whose workspace holds the scratch.
 int run_trace(rt_scene* ws, TraceArgs& a, const rt_trace_params* p, int depth, int64_t max_steps, int64_t n_rays,
               int32_t* hit_seq, const float* dirs, const float* origins, const float* bounds, hipStream_t st) {
-    const int occ = p->waves_per_simd == 5 || p->waves_per_simd == 6 || p->waves_per_simd == 8 ? p->waves_per_simd : 4;
+    // 5 waves per SIMD by default: a 96-register budget spills a little, but the busy phase is bound by
+    // the latency of dependent node fetches and gains more from the fifth wavefront than it loses
+    const int occ = p->waves_per_simd == 4 || p->waves_per_simd == 6 || p->waves_per_simd == 8 ? p->waves_per_simd : 5;
     const int bpc = p->blocks_per_cu > 0 ? p->blocks_per_cu : occ;
     int64_t nblk = (int64_t)device_sm_count() * bpc;
     const int64_t need = (n_rays + kBlock - 1) / kBlock;
