@@ -1170,7 +1170,9 @@ int run_trace(rt_scene* ws, TraceArgs& a, const rt_trace_params* p, int depth, i
     a.spill = ws->ws.stack_spill.as<int32_t>();
     a.spill_per_lane = spill_n;
     a.fetch_thr = p->fetch_threshold > 0 ? p->fetch_threshold : 16;
-    a.shade_thr = p->shade_threshold > 0 ? p->shade_threshold : 8;
+    // shading batches: with one segment per ray a lane stops after it, so larger batches only save
+    // shading rounds; with several, finished lanes should not wait long for the next segment
+    a.shade_thr = p->shade_threshold > 0 ? p->shade_threshold : (p->max_reflections == 0 ? 48 : 16);
     a.max_steps = max_steps > 0x7FFFFFFF ? 0x7FFFFFFF : (int32_t)max_steps;
     a.order = nullptr;
     a.stats = (unsigned long long*)p->stats;
