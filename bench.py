@@ -52,6 +52,8 @@ def main():
     ap.add_argument("--suspend", type=int, default=0,
                     help="queue rays continuing past this segment for a second launch (0 = off)")
     ap.add_argument("--stats", action="store_true", help="count traversal work (extra pass, not timed)")
+    ap.add_argument("--no-copy-bw", action="store_true",
+                    help="skip the device-copy bandwidth measurement (profiling runs: it adds copy kernels)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (counter calibration)")
     ap.add_argument("--workload", choices=("theater", "rooms", "surrogate", "table2", "sphere"), default="theater",
@@ -205,6 +207,10 @@ def run_theater(args):
                                       "triangles": st[2] / queries, "spills": st[3] / queries,
                                       "tree_nodes": sc.n_nodes, "tree_depth": sc.depth}
     out["roofline"]["traffic"] = measured_traffic()
+    if not args.no_copy_bw:
+        copy = copy_bandwidth_gbs(dev)
+        out["roofline"]["copy_GB_per_s"] = copy
+        out["roofline"]["frac_of_copy"] = achieved / copy
     # perceptive factors of the last step's IR (not timed): 500 Hz and 1 kHz octaves, every receiver
     hist = state["ir"].hist
     pr = rt.room_params(hist, s.fs)
@@ -251,6 +257,24 @@ def run_theater(args):
         except Exception as e:  # report, never hide
             out["cpu_baseline"]["ir_band_error"] = "failed: %r" % (e,)
     print(json.dumps(out), flush=True)
+
+
+def copy_bandwidth_gbs(dev, nbytes=1 << 30, reps=10):
+    """Device-to-device copy rate on this GPU (bytes read + bytes written per
+    second), the practical HBM ceiling next to the 8 TB/s data-sheet peak."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(reps):
+        b.copy_(a)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / reps
+    del a, b
+    return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
 def measured_traffic():
@@ -688,10 +712,23 @@ def cpu_baseline(s, n_cpu):
                       threads=threads)
     dt = time.perf_counter() - t0
     q = int(tr["tests"] // s.n_tri)          # every brute-force query tests all triangles once
+    # the same oracle on one thread, over every k-th ray of the sample (spread
+    # over all directions; about a third of the all-core leg's time)
+    k = max(1, 3 * threads)
+    sub = np.ascontiguousarray(dirs[::k])
+    n1 = len(sub)
+    t0 = time.perf_counter()
+    tr1 = oracle.trace(sc, s.src, sub, s.rcv, s.max_reflections, max_len=s.max_path_length, flags=False,
+                       threads=1)
+    dt1 = time.perf_counter() - t0
+    q1 = int(tr1["tests"] // s.n_tri)
     return {"value": q / dt, "unit": "rays·bounces/s", "cores": threads, "kind": "oracle",
             "sample": "%d of the 1e6 Fibonacci rays (seeded choice), full trajectories, FP64 brute force over "
                       "all %d triangles; %d queries in %.1f s" % (n_cpu, s.n_tri, q, dt),
-            "triangle_tests_per_s": tr["tests"] / dt}
+            "triangle_tests_per_s": tr["tests"] / dt,
+            "one_core": {"value": q1 / dt1, "triangle_tests_per_s": tr1["tests"] / dt1,
+                         "sample": "every %d-th ray of the sample (%d rays), %d queries in %.1f s"
+                                   % (k, n1, q1, dt1)}}
 
 
 if __name__ == "__main__":

@@ -1295,7 +1295,9 @@ extern "C" int rt_trace_rays(const rt_scene* scene, const float* src_host, const
     a.R = p->max_reflections;
     a.max_len = p->max_path_length;
     a.beam_n = p->min_beam_rays;
-    a.coop = p->coop_queries >= 0 ? 1 : 0;
+    // the statistics count the per-lane traversal only: requesting them turns
+    // the cooperative search off, so that every step of every query is counted
+    a.coop = p->coop_queries >= 0 && !p->stats ? 1 : 0;
     a.record = p->record_states ? 1 : 0;
     a.hit_seq = hit_seq;
     a.det = det;
@@ -1419,7 +1421,7 @@ extern "C" int rt_trace_batch(rt_batch* b, const float* rcv, const rt_trace_para
     a.rcv = rcv;
     a.R = p->max_reflections;
     a.beam_n = p->min_beam_rays;
-    a.coop = p->coop_queries >= 0 ? 1 : 0;
+    a.coop = p->coop_queries >= 0 && !p->stats ? 1 : 0;
     a.hit_seq = hit_seq;
     a.det = det;
     a.det_cap = det_cap;

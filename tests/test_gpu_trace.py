@@ -243,6 +243,26 @@ def test_scheduling_leaves_results_unchanged(rt, scenes, name, R, n, kw):
     assert np.array_equal(_sorted_det(a), _sorted_det(b))
 
 
+@pytest.mark.parametrize("name,R,n", [("c2", 20, 20_000), ("c3", 60, 20_000)])
+def test_traversal_statistics(rt, scenes, name, R, n):
+    """A call with traversal statistics gives the same results, and its counts
+    are consistent: every query that hits a triangle visits the root, at least
+    one leaf and tests at least one triangle."""
+    s, sc = scenes[name]
+    dirs = rt.fibonacci_directions(n, device="cuda:0")
+    mpl = s.max_path_length if name == "c3" else 0.0
+    a = rt.trace_rays(sc, dirs, s.rcv, R, src=s.src, max_path_length=mpl)
+    st = torch.full((4,), -1, dtype=torch.int64, device="cuda:0")
+    b = rt.trace_rays(sc, dirs, s.rcv, R, src=s.src, max_path_length=mpl, stats=st)
+    assert torch.equal(a.hit_seq, b.hit_seq) and torch.equal(a.counters[:3], b.counters[:3])
+    nodes, leaves, tris, spills = st.cpu().tolist()
+    hits = int(b.counters[1]) - int(b.counters[2])
+    _say("stats %s: queries %d hits %d nodes %d leaves %d tris %d spills %d"
+         % (name, int(b.counters[1]), hits, nodes, leaves, tris, spills))
+    assert hits > 0 and nodes >= hits and leaves >= hits and tris >= hits and spills >= 0
+    assert tris <= leaves * sc.leaf_size
+
+
 @pytest.mark.parametrize("k", [1, 16, 91])
 def test_tetra_one_iteration_matches_oracle(rt, oracle_lib, k):
     """The complexity study's workload ("Tree-base acceleration", Table 2):
