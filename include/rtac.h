@@ -279,7 +279,7 @@ int rt_band_energy_adjoint(const rt_scene* scene, const int32_t* is_key, const i
 /*
  * Batches: many jobs -- a source with its own Fibonacci rays and receivers in
  * one of several scenes (rooms of uneven size) -- traced by one persistent
- * launch (spec add-on; each job follows the same definitions as
+ * launch (each job follows the same definitions as
  * rt_trace_rays, rt_collect_image_sources, rt_assemble_ir and
  * rt_band_energy_adjoint).  Rays of job j are global ids ray_off_j ..
  * ray_off_j + n_rays_j - 1 (jobs in order), receivers of job j are global rows
