@@ -142,7 +142,8 @@ typedef struct {
     int32_t record_states;     /* nonzero: write each segment's input state to `states`        */
     int32_t fetch_threshold;   /* 0 = default; lanes idle before a wave fetches new rays       */
     int32_t shade_threshold;   /* 0 = default (16; 48 when max_reflections = 0); finished queries
-                                  before a wave shades them                                     */
+                                  before a wave shades them.  With reflections this is for a full
+                                  wave and scales with the lanes still working (at least 1)     */
     int32_t blocks_per_cu;     /* 0 = default; persistent workgroups per compute unit          */
     int32_t keep_order;        /* 0: rays are handed to wavefronts sorted by a Morton key of
                                   their direction (and origin) for coherence; 1: in index order */

@@ -24,7 +24,12 @@
 // single query in flight then searches it with all 64 lanes (two queries:
 // 32 lanes each), breadth first over a frontier of tree nodes in LDS, which
 // takes about as many steps as the tree is deep instead of one node per step
-// (same nearest hit).
+// (same nearest hit).  A wavefront shades its finished queries in groups to
+// spread the FP64 shading over many lanes; with reflections the group size is
+// a share of the lanes still working (16 of 64 by default), so that once the
+// pool is empty and the wavefront holds only the rays it already has, no chain
+// waits for the slowest query beside it (single-segment queries end at their
+// shading, so there the group stays fixed).
 #include "common.h"
 
 namespace rtac {
@@ -68,6 +73,7 @@ struct TraceArgs {
     int32_t spill_per_lane;
     int32_t fetch_thr;
     int32_t shade_thr;
+    int32_t scale_shade;            // nonzero: shade_thr applies to a full wavefront, scaled by its working lanes
     int32_t max_steps;
     const uint32_t* order;          // pool index -> ray id (NULL: identity)
     unsigned long long* stats;      // NULL or [4]
@@ -746,10 +752,19 @@ k_trace(TraceArgs a) {
         }
 
         // ---- traverse until enough lanes have finished their query -----------
+        // With reflections the shade threshold is a share of the working lanes
+        // (lanes only go from query to done in this loop, so it is fixed here):
+        // a full wavefront shades its finished queries in groups, one that has
+        // run out of rays still shades as soon as that share is done.
+        int shade_at = a.shade_thr;
+        if (a.scale_shade) {
+            const int working = __popcll(__ballot(status != kIdle));
+            shade_at = max(1, (shade_at * working + kWave - 1) / kWave);
+        }
         for (;;) {
             const uint64_t q = __ballot(status == kQuery);
             if (q == 0ull) break;
-            if (__popcll(__ballot(status == kDone)) >= a.shade_thr) break;
+            if (__popcll(__ballot(status == kDone)) >= shade_at) break;
             if (status != kQuery) continue;
             bool have = true;
             if (++steps > a.max_steps) {
@@ -1173,6 +1188,7 @@ int run_trace(rt_scene* ws, TraceArgs& a, const rt_trace_params* p, int depth, i
     // shading batches: with one segment per ray a lane stops after it, so larger batches only save
     // shading rounds; with several, finished lanes should not wait long for the next segment
     a.shade_thr = p->shade_threshold > 0 ? p->shade_threshold : (p->max_reflections == 0 ? 48 : 16);
+    a.scale_shade = p->max_reflections > 0 ? 1 : 0;
     a.max_steps = max_steps > 0x7FFFFFFF ? 0x7FFFFFFF : (int32_t)max_steps;
     a.order = nullptr;
     a.stats = (unsigned long long*)p->stats;
