@@ -243,6 +243,43 @@ def test_scheduling_leaves_results_unchanged(rt, scenes, name, R, n, kw):
     assert np.array_equal(_sorted_det(a), _sorted_det(b))
 
 
+@pytest.mark.parametrize("name,R,n", [("c1", 20, 300), ("c2", 50, 3_000), ("c3", 60, 5_000)])
+def test_cooperative_search_small_calls(rt, scenes, name, R, n):
+    """With few rays per wavefront the pool is empty at once, and many
+    wavefronts end with one or two queries searched by all their lanes: the
+    results equal those of the per-lane walk."""
+    s, sc = scenes[name]
+    dirs = rt.fibonacci_directions(n, device="cuda:0")
+    mpl = s.max_path_length if name == "c3" else 0.0
+    a = rt.trace_rays(sc, dirs, s.rcv, R, src=s.src, max_path_length=mpl, coop_queries=-1)
+    b = rt.trace_rays(sc, dirs, s.rcv, R, src=s.src, max_path_length=mpl)
+    assert torch.equal(a.hit_seq, b.hit_seq)
+    assert torch.equal(a.counters[:3], b.counters[:3]) and int(b.counters[3]) == 0
+    assert np.array_equal(_sorted_det(a), _sorted_det(b))
+
+
+def test_cooperative_search_grazing_rays(rt, scenes):
+    """Rays skimming the jittered floor of the 100k-triangle box within the
+    jitter band cross many leaf boxes at once (wide frontiers for the
+    breadth-first search of the last queries).  Results equal those of the
+    per-lane walk."""
+    s, sc = scenes["c2"]
+    rng = np.random.default_rng(77)
+    n = 2_000
+    org = np.stack([rng.uniform(1, 9, n), rng.uniform(1, 6, n), rng.uniform(0.005, 0.04, n)], 1)
+    phi = rng.uniform(0, 2 * np.pi, n)
+    d = np.stack([np.cos(phi), np.sin(phi), rng.uniform(-0.004, 0.001, n)], 1)
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    org_t = torch.as_tensor(org.astype(np.float32), device="cuda:0")
+    dirs = torch.as_tensor(d.astype(np.float32), device="cuda:0")
+    a = rt.trace_rays(sc, dirs, s.rcv, 6, origins=org_t, coop_queries=-1)
+    b = rt.trace_rays(sc, dirs, s.rcv, 6, origins=org_t)
+    assert torch.equal(a.hit_seq, b.hit_seq)
+    assert torch.equal(a.counters[:3], b.counters[:3]) and int(b.counters[3]) == 0
+    assert np.array_equal(_sorted_det(a), _sorted_det(b))
+    assert int((a.hit_seq[:, 0] >= 0).sum()) > n // 2
+
+
 @pytest.mark.parametrize("name,R,n", [("c2", 20, 20_000), ("c3", 60, 20_000)])
 def test_traversal_statistics(rt, scenes, name, R, n):
     """A call with traversal statistics gives the same results, and its counts
