@@ -14,6 +14,7 @@ from __future__ import annotations
 
 import ctypes
 import math
+import sys
 from typing import Dict, List, Optional, Sequence
 
 import numpy as np
@@ -256,5 +257,5 @@ def train(net: Mlp, x, tgt, mask, epochs: int = 200, batch: int = 256, lr: float
         hist.append(float(a[0] / max(float(a[1]), 1.0)))
         if log_every and (ep % log_every == 0 or ep == epochs - 1):
             v = " held-out %.4f" % eval_loss(net, *val) if val is not None else ""
-            print("epoch %d loss %.4f dB^2%s" % (ep, hist[-1], v), flush=True)
+            print("epoch %d loss %.4f dB^2%s" % (ep, hist[-1], v), file=sys.stderr, flush=True)
     return hist
