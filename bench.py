@@ -530,6 +530,11 @@ def run_surrogate(args):
     torch.cuda.synchronize()
     big_ms = e0.elapsed_time(e1) / 10
     big_tflops = 2 * big_b * macs / (big_ms * 1e-3) / 1e12
+    # bytes each layer must move: its BF16 input and its output (BF16 hidden, FP32 last) and weights
+    ws = sg.WIDTHS
+    big_bytes = sum(big_b * i * 2 + big_b * o * (4 if li == len(ws) - 2 else 2) + i * o * 2
+                    for li, (i, o) in enumerate(zip(ws[:-1], ws[1:])))
+    big_gbs = big_bytes / (big_ms * 1e-3) / 1e9
     del big, xl, yl
     out = {
         "metric": "late-tail surrogate: speed-up of 8 bounces + MLP over the 60-bounce trace; RMS dB error",
@@ -549,7 +554,10 @@ def run_surrogate(args):
         "roofline": {"bound": "mfma", "achieved": tflops, "peak": 2500.0, "unit": "TFLOP/s",
                      "frac": tflops / 2500.0, "traffic": None, "kernel": "MLP train step (batch 256)",
                      "step_ms": step_ms},
-        "mlp_forward_batch_65536": {"ms": big_ms, "TFLOP_per_s": big_tflops, "frac_of_bf16_peak": big_tflops / 2500.0},
+        "mlp_forward_batch_65536": {"ms": big_ms, "TFLOP_per_s": big_tflops, "frac_of_bf16_peak": big_tflops / 2500.0,
+                                    "algorithmic_bytes": big_bytes, "GB_per_s": big_gbs,
+                                    "frac_of_hbm_peak": big_gbs / HBM_PEAK_GBS,
+                                    "note": "128 FLOP per byte at width 256, under the BF16 ridge (~312): HBM-bound"},
     }
     print(json.dumps(out), flush=True)
 

@@ -79,6 +79,68 @@ def _margin_rows(theta, widths, x, n_keep, margin=0.03):
     return x[idx[:n_keep]]
 
 
+def test_large_batch_forward_rows(sg):
+    """Each output row depends on its input row alone, through the same MFMA
+    sequence at any batch size: the first and last 256 rows of a ragged
+    batch of 65,600 (last row tile partly full, 1,026 workgroups per hidden
+    layer) equal, bit for bit, the batch-256 forward pass of those rows."""
+    widths = sg.WIDTHS
+    theta = synth.mlp_init(11, widths, bias_std=0.1)
+    B = 65_600
+    x = synth.mlp_inputs(12, B, widths[0])
+    big = sg.Mlp(theta, widths, max_batch=B, device=DEV)
+    small = sg.Mlp(theta, widths, max_batch=256, device=DEV)
+    xb = _bf16(x)
+    y = big.forward(xb)
+    for lo in (0, B - 256):
+        ys = small.forward(xb[lo:lo + 256].contiguous())
+        assert torch.equal(y[lo:lo + 256], ys), lo
+
+
+def test_large_batch_single_layer_matches_oracle(sg):
+    """One 128 -> 1024 layer at batch 32,768 (8,192 output tiles): sampled rows
+    within the exact-layout tolerance of the FP64 oracle."""
+    widths = (128, 1024)
+    theta = synth.mlp_init(13, widths, bias_std=0.5)
+    B = 32_768
+    x = synth.mlp_inputs(14, B, widths[0])
+    net = sg.Mlp(theta, widths, max_batch=B, device=DEV)
+    y = net.forward(_bf16(x)).cpu().numpy().astype(np.float64)
+    rows = np.random.default_rng(15).choice(B, 512, replace=False)
+    ref = omlp.forward(theta.astype(np.float64), widths, x[rows].astype(np.float64))[-1]
+    assert np.abs(y[rows] - ref).max() <= 1e-5 * np.abs(ref).max()
+
+
+def test_large_batch_backward_matches_oracle(sg):
+    """Backward at batch 16,384 (weight gradients summed over 16,384 rows,
+    input gradients of 16,384 x 256).  Nonnegative weights and inputs keep
+    every unit active (no ReLU can flip)."""
+    widths = (512, 256, 256)
+    B = 16_384
+    theta = np.abs(synth.mlp_init(16, widths, bias_std=0.1))
+    x = np.abs(synth.mlp_inputs(17, B, widths[0]))
+    rng = np.random.default_rng(18)
+    ref_y = omlp.forward(theta.astype(np.float64), widths, x.astype(np.float64))[-1]
+    tgt = (ref_y + np.sqrt((ref_y ** 2).mean()) * rng.standard_normal(ref_y.shape)).astype(np.float32)
+    mask = (rng.uniform(size=tgt.shape) < 0.8).astype(np.float32)
+    net = sg.Mlp(theta, widths, max_batch=B, device=DEV)
+    xb = _bf16(x)
+    y = net.forward(xb)
+    lt = net.backward(xb, y, torch.as_tensor(tgt, device=DEV), torch.as_tensor(mask, device=DEV))
+    S, msum = lt.cpu().numpy()
+    Lref, gref = omlp.backward(theta.astype(np.float64), widths, x.astype(np.float64), tgt.astype(np.float64),
+                               mask.astype(np.float64))
+    assert msum == mask.sum()
+    assert S / msum == pytest.approx(Lref, rel=2e-2)
+    g = net.grad.cpu().numpy().astype(np.float64) / msum
+    off = 0
+    for i, j in zip(widths[:-1], widths[1:]):
+        for n in (i * j, j):
+            a, b = g[off:off + n], gref[off:off + n]
+            assert np.linalg.norm(a - b) / np.linalg.norm(b) <= 2e-2
+            off += n
+
+
 @pytest.mark.parametrize("widths,batch,positive", [((128, 64), 50, False), ((128, 64, 64, 128), 60, False),
                                                    ((512, 256, 256, 256, 1024), 100, True)])
 def test_backward_matches_oracle(sg, widths, batch, positive):
