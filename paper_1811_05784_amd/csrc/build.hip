@@ -340,31 +340,95 @@ struct SegBox {
     float4 lo, hi;
 };
 
-__global__ void k_seg_leaves(int64_t n, const uint32_t* __restrict__ order, const float* __restrict__ tri_box,
-                             SegBox* __restrict__ lvl0) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
-    const float* b = tri_box + 6 * (int64_t)order[j];
-    lvl0[j] = SegBox{make_float4(b[0], b[1], b[2], 0.f), make_float4(b[3], b[4], b[5], 0.f)};
-}
-
-__global__ void k_seg_up(int64_t n_child, const SegBox* __restrict__ child, SegBox* __restrict__ parent) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t n_par = (n_child + 1) / 2;
-    if (i >= n_par) return;
-    SegBox a = child[2 * i];
-    if (2 * i + 1 < n_child) {
-        const SegBox b = child[2 * i + 1];
-        a.lo = make_float4(fminf(a.lo.x, b.lo.x), fminf(a.lo.y, b.lo.y), fminf(a.lo.z, b.lo.z), 0.f);
-        a.hi = make_float4(fmaxf(a.hi.x, b.hi.x), fmaxf(a.hi.y, b.hi.y), fmaxf(a.hi.z, b.hi.z), 0.f);
-    }
-    parent[i] = a;
-}
-
 struct SegLevels {
     const SegBox* lvl[32];
     int n_levels;
 };
+
+// Level l of the segment tree has ceil(n / 2^l) entries; entry i covers
+// entries 2i and 2i+1 (if present) of level l-1.
+struct SegOut {
+    SegBox* lvl[32];
+    int n_levels;
+};
+
+__device__ inline void seg_merge(float (&a)[6], const float* b) {
+    for (int c = 0; c < 3; c++) {
+        a[c] = fminf(a[c], b[c]);
+        a[3 + c] = fmaxf(a[3 + c], b[3 + c]);
+    }
+}
+__device__ inline void seg_put(SegBox* dst, const float (&a)[6]) {
+    *dst = SegBox{make_float4(a[0], a[1], a[2], 0.f), make_float4(a[3], a[4], a[5], 0.f)};
+}
+
+// Levels 0..kSegBlockLevels of the segment tree for 2^kSegBlockLevels
+// consecutive leaves per workgroup (1024 threads): every entry of those levels
+// depends on that range only, so each level is formed in LDS after one barrier.
+constexpr int kSegBlockLevels = 11;
+constexpr int kSegBlockLeaves = 1 << kSegBlockLevels;
+__global__ __launch_bounds__(1024) void k_seg_block(int64_t n, const uint32_t* __restrict__ order,
+                                                   const float* __restrict__ tri_box, SegOut seg) {
+    __shared__ float sb[1024][6];
+    const int t = threadIdx.x;
+    const int64_t b = blockIdx.x;
+    float a[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    bool have = false;
+    for (int q = 0; q < 2; q++) {
+        const int64_t j = b * kSegBlockLeaves + 2 * t + q;
+        if (j < n) {
+            const float* tb = tri_box + 6 * (int64_t)order[j];
+            float e[6];
+            for (int c = 0; c < 6; c++) e[c] = tb[c];
+            seg_put(seg.lvl[0] + j, e);
+            seg_merge(a, e);
+            have = true;
+        }
+    }
+    if (seg.n_levels > 1 && have) seg_put(seg.lvl[1] + (b * (kSegBlockLeaves / 2) + t), a);
+    for (int c = 0; c < 6; c++) sb[t][c] = a[c];
+    for (int l = 2; l <= kSegBlockLevels && l < seg.n_levels; l++) {
+        __syncthreads();
+        const int cnt = kSegBlockLeaves >> l;
+        const int64_t wl = (n + ((int64_t)1 << l) - 1) >> l;
+        const int64_t wp = (n + ((int64_t)1 << (l - 1)) - 1) >> (l - 1);
+        bool ok = false;
+        float e[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+        if (t < cnt) {
+            const int64_t gi = b * cnt + t;
+            if (gi < wl) {
+                seg_merge(e, sb[2 * t]);
+                if (2 * gi + 1 < wp) seg_merge(e, sb[2 * t + 1]);
+                seg_put(seg.lvl[l] + gi, e);
+                ok = true;
+            }
+        }
+        __syncthreads();
+        if (ok)
+            for (int c = 0; c < 6; c++) sb[t][c] = e[c];
+    }
+}
+
+// Levels above kSegBlockLevels: one workgroup, a barrier between levels.
+__global__ __launch_bounds__(1024) void k_seg_top(int64_t n, SegOut seg) {
+    const int t = threadIdx.x;
+    for (int l = kSegBlockLevels + 1; l < seg.n_levels; l++) {
+        const int64_t wl = (n + ((int64_t)1 << l) - 1) >> l;
+        const int64_t wp = (n + ((int64_t)1 << (l - 1)) - 1) >> (l - 1);
+        for (int64_t i = t; i < wl; i += blockDim.x) {
+            const SegBox c0 = seg.lvl[l - 1][2 * i];
+            float e[6] = {c0.lo.x, c0.lo.y, c0.lo.z, c0.hi.x, c0.hi.y, c0.hi.z};
+            if (2 * i + 1 < wp) {
+                const SegBox c1 = seg.lvl[l - 1][2 * i + 1];
+                const float f[6] = {c1.lo.x, c1.lo.y, c1.lo.z, c1.hi.x, c1.hi.y, c1.hi.z};
+                seg_merge(e, f);
+            }
+            seg_put(seg.lvl[l] + i, e);
+        }
+        __threadfence_block();
+        __syncthreads();
+    }
+}
 
 __global__ void k_node_boxes(int64_t n_in, const int32_t* __restrict__ first, const int32_t* __restrict__ last,
                              SegLevels seg, float* __restrict__ box_in) {
@@ -668,19 +732,18 @@ extern "C" int rt_build_tree(const float* vtx, int64_t n_vtx, const int32_t* tri
             return fail(RT_ENOMEM);
         }
         {
-            int64_t off = 0, w = nt;
+            SegOut segw;
+            segw.n_levels = seg.n_levels;
+            int64_t off = 0;
             for (int lv = 0; lv < seg.n_levels; lv++) {
+                segw.lvl[lv] = segbuf + off;
                 seg.lvl[lv] = segbuf + off;
-                if (lv == 0) {
-                    hipLaunchKernelGGL(k_seg_leaves, dim3(blocks(nt)), dim3(256), 0, st, nt, order, tri_box,
-                                       segbuf);
-                } else {
-                    hipLaunchKernelGGL(k_seg_up, dim3(blocks((w + 1) / 2)), dim3(256), 0, st, w,
-                                       seg.lvl[lv - 1], segbuf + off);
-                    w = (w + 1) / 2;
-                }
-                off += w;
+                off += (nt + ((int64_t)1 << lv) - 1) >> lv;
             }
+            hipLaunchKernelGGL(k_seg_block, dim3((unsigned)((nt + kSegBlockLeaves - 1) / kSegBlockLeaves)), dim3(1024),
+                               0, st, nt, order, tri_box, segw);
+            if (seg.n_levels > kSegBlockLevels + 1)
+                hipLaunchKernelGGL(k_seg_top, dim3(1), dim3(1024), 0, st, nt, segw);
         }
         hipLaunchKernelGGL(k_node_boxes, dim3(blocks(n_in)), dim3(256), 0, st, n_in, first, last, seg, box_in);
         hipLaunchKernelGGL(k_flag4, dim3(blocks(n_in)), dim3(256), 0, st, n_in, first, last, par_in, leaf, flag,
