@@ -118,19 +118,35 @@ __global__ void k_bin_sum(IsArgs a, const uint64_t* __restrict__ skey, const uin
 }
 
 // band_energy[r, b] = sum over bins (FP64 tree reduction, fixed order).
-__global__ void __launch_bounds__(1024) k_band_energy(const float* __restrict__ hist, int64_t L,
-                                                      float* __restrict__ out) {
-    __shared__ double red[1024];
-    const float* h = hist + (int64_t)blockIdx.x * L;
+// Band energies: each signal is cut into kBandChunks chunks (one workgroup
+// each, so the whole GPU works on the 8 n_rcv signals), summed in FP64 in a
+// fixed order; k_band_final adds a signal's chunk sums in order.
+constexpr int kBandChunks = 16;
+__global__ void __launch_bounds__(256) k_band_partial(const float* __restrict__ hist, int64_t L,
+                                                      double* __restrict__ part) {
+    __shared__ double red[256];
+    const int64_t sig = blockIdx.y;
+    const int c = blockIdx.x;
+    const int64_t len = (L + kBandChunks - 1) / kBandChunks;
+    const int64_t lo = c * len, hi = lo + len < L ? lo + len : L;
+    const float* h = hist + sig * L;
     double s = 0.0;
-    for (int64_t i = threadIdx.x; i < L; i += 1024) s += (double)h[i];
+    for (int64_t i = lo + threadIdx.x; i < hi; i += 256) s += (double)h[i];
     red[threadIdx.x] = s;
     __syncthreads();
-    for (int off = 512; off > 0; off >>= 1) {
+    for (int off = 128; off > 0; off >>= 1) {
         if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[blockIdx.x] = (float)red[0];
+    if (threadIdx.x == 0) part[sig * kBandChunks + c] = red[0];
+}
+
+__global__ void k_band_final(const double* __restrict__ part, int64_t n_sig, float* __restrict__ out) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_sig) return;
+    double a = 0.0;
+    for (int c = 0; c < kBandChunks; c++) a += part[s * kBandChunks + c];
+    out[s] = (float)a;
 }
 
 // ---------------------------------------------------------------------------
@@ -508,7 +524,14 @@ int assemble_common(const rt_scene* scene, const rt_batch* bt, const int32_t* is
     const int64_t hn = (int64_t)n_rcv * 8 * L;
     hipLaunchKernelGGL(k_fill_f32, dim3(nblk(hn)), dim3(256), 0, st, hist, hn, 0.f);
     hipLaunchKernelGGL(k_bin_sum, dim3(nblk_gs(cap)), dim3(256), 0, st, a, which ? k1 : k0, which ? v1 : v0, E, hist);
-    hipLaunchKernelGGL(k_band_energy, dim3(n_rcv * 8), dim3(1024), 0, st, hist, L, band_energy);
+    {
+        const int64_t n_sig = (int64_t)n_rcv * 8;
+        if (ws.band_partial.ensure(sizeof(double) * (size_t)n_sig * kBandChunks)) return RT_ENOMEM;
+        double* part = ws.band_partial.as<double>();
+        hipLaunchKernelGGL(k_band_partial, dim3(kBandChunks, (unsigned)n_sig), dim3(256), 0, st, hist, L, part);
+        hipLaunchKernelGGL(k_band_final, dim3((unsigned)((n_sig + 255) / 256)), dim3(256), 0, st, part, n_sig,
+                           band_energy);
+    }
     if (K >= kFirFftMinK && K <= kFftN / 2) {
         // long filters: overlap-save FFT convolution
         if (ws.fir_twiddle.ensure(sizeof(float2) * kFftN) || ws.fir_spec.ensure(sizeof(float2) * 8 * kFftN))

@@ -68,7 +68,7 @@ struct Workspace {
     Buf sort_keys[2], sort_vals[2], sort_hist, scan_tmp;
     Buf stack_spill, trace_pool;
     Buf is_hash, is_idx, is_flags, is_group, coll_err;
-    Buf asm_key, asm_idx, asm_energy, asm_partial, asm_pressure, fir_twiddle, fir_spec;
+    Buf asm_key, asm_idx, asm_energy, asm_partial, asm_pressure, fir_twiddle, fir_spec, band_partial;
     Buf generic[4];
     void release_all();
 };
