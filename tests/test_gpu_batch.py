@@ -210,3 +210,51 @@ def test_batch_eq13_range_equals_single(rt, setup):
         dj[:, 2] -= b.rcv_off[j]
         d1 = one.detections().cpu().numpy()
         assert np.array_equal(dj[np.lexsort(dj.T[::-1])], d1[np.lexsort(d1.T[::-1])]), j
+
+
+def test_rooms_full_size_sampled(rt, oracle_lib):
+    """The benchmarked batch at full size: 8 rooms of 976-177,356 triangles,
+    8 source/receiver pairs each, 2e5 rays per pair (1.28e7 rays), R = 50, in
+    one persistent launch with the tuned settings.  In every room, 6 rays of
+    one pair (seeded) are traced by the oracle from the same FP32 directions:
+    each hit sequence equals the oracle's or first differs at a flagged query,
+    detections equal on unflagged agreeing rays."""
+    rooms = synth.batched_rooms(seed=4)
+    R, T, c = rooms[0].max_reflections, rooms[0].ir_seconds, rooms[0].c
+    scenes = [rt.Scene.from_synth(r, device=DEV) for r in rooms]
+    jobs = []
+    for i, r in enumerate(rooms):
+        for p in range(len(r.src)):
+            jobs.append(dict(scene=i, src=r.src[p], rcv=r.rcv[p:p + 1], n_rays=r.n_rays,
+                             max_path_length=c * T + float(r.rcv[p, 3])))
+    b = rt.Batch(scenes, jobs, device=DEV)
+    tr = rt.trace_batch(b, R, det_cap=2 * b.n_rays, waves_per_simd=4, blocks_per_cu=8, fetch_threshold=16,
+                        shade_threshold=16)
+    det = tr.detections().cpu().numpy()
+    rng = np.random.default_rng(404)
+    checked = flagged = differing = 0
+    for i, r in enumerate(rooms):
+        j = i * len(r.src) + int(rng.integers(len(r.src)))
+        job = jobs[j]
+        lo = b.ray_off[j]
+        idx = np.sort(rng.choice(job["n_rays"], 6, replace=False))
+        dirs = rt.fibonacci_directions(job["n_rays"], device=DEV).cpu().numpy()[idx]
+        ref = oracle_lib.trace(oracle_lib.OracleScene.of(r), job["src"], np.ascontiguousarray(dirs), job["rcv"], R,
+                               max_len=job["max_path_length"])
+        hs = tr.hit_seq[torch.as_tensor(lo + idx, device=DEV)].cpu().numpy()
+        diff = (hs != ref["hit_seq"]).any(axis=1)
+        for q in np.nonzero(diff)[0]:
+            k = int(np.argmax(hs[q] != ref["hit_seq"][q]))
+            assert ref["flags"][q, : k + 1].any(), "room %d job %d ray %d: unflagged divergence" % (i, j, idx[q])
+        good = ~diff & ~ref["flags"].any(axis=1)
+        sel = np.isin(det[:, 0], lo + idx)
+        gbits = np.zeros((len(idx), R + 1), np.uint32)
+        rows = np.searchsorted(lo + idx, det[sel, 0])
+        rcv_local = det[sel, 2] - b.rcv_off[j]
+        np.bitwise_or.at(gbits, (rows, det[sel, 1]), (np.uint32(1) << rcv_local.astype(np.uint32)))
+        assert np.array_equal(gbits[good], ref["det"][good])
+        checked += len(idx)
+        flagged += int(ref["flags"].any(axis=1).sum())
+        differing += int(diff.sum())
+    _say("rooms full size: %d rays checked, %d differing (all at flagged queries), %d flagged, queries %d" % (
+        checked, differing, flagged, int(tr.counters[1])))
