@@ -197,29 +197,32 @@ def test_band_energy_autograd_and_finite_differences(rt, c1):
     assert np.allclose(grad, fd, rtol=1e-2, atol=1e-2 * scale)
 
 
-def test_theater_full_size_image_sources_and_bands(rt, oracle_lib):
-    """Collection and assembly on the benchmarked trace (436,120 triangles,
-    10^6 rays, R = 60, 8 receivers), through properties that hold at any size:
-    counts add up to the detections, keys are distinct, every position is the
-    source mirrored (FP64) through its key's planes taken from the mesh, every
-    distance is that position's distance to its receiver's centre, and the
-    band energies are the sums over the table of n/N e^(-beta d) prod(1 - alpha)
-    over the sources that arrive within the response (1e-4 relative)."""
-    s = synth.theater_c3()
-    sc = rt.Scene.from_synth(s, device="cuda:0")
-    N, R = s.n_rays, s.max_reflections
+def _full_size_tables(rt, oracle_lib, s, sc, R, mpl, mirror_rows, seed):
+    """Trace every ray of the configuration, collect and assemble, then check
+    properties that hold at any size: counts add up to the detections, keys
+    are distinct, the positions of `mirror_rows` seeded rows (all rows if
+    None) are the source mirrored (FP64) through their keys' planes taken from
+    the mesh, distances match positions, and the band energies are the sums
+    over the table of n/N e^(-beta d) prod(1 - alpha) over the sources that
+    arrive within the response (1e-4 relative).  Returns (n_is, n_det, max rel)."""
+    N = s.n_rays
     dirs = rt.fibonacci_directions(N, device="cuda:0")
-    tr = rt.trace_rays(sc, dirs, s.rcv, R, src=s.src, max_path_length=s.max_path_length, det_cap=6 * N)
+    tr = rt.trace_rays(sc, dirs, s.rcv, R, src=s.src, max_path_length=mpl, det_cap=6 * N)
     isrc = rt.collect_image_sources(sc, s.src, s.rcv, tr)
     key, cnt, pos, dist = [t.cpu().numpy() for t in isrc.valid()]
     assert int(cnt.sum()) == int(tr.counters[0]) and len(key) > 10_000
-    rows = {tuple(int(v) for v in r[: 2 + r[1]]) for r in key}
-    assert len(rows) == len(key)
+    kk = key[:, 1].astype(np.int64)
+    width = 2 + int(kk.max())
+    trimmed = np.where(np.arange(width)[None, :] < (2 + kk)[:, None], key[:, :width], -2)
+    assert len(np.unique(trimmed, axis=0)) == len(key)
     pn, pp = oracle_lib.OracleScene.of(s).planes()
     rcv = s.rcv.astype(np.float64)
     src = np.asarray(s.src, np.float64)
     scale = float(np.abs(pos).max())
-    for r, p, d in zip(key, pos, dist):
+    rows = np.arange(len(key)) if mirror_rows is None else \
+        np.random.default_rng(seed).choice(len(key), mirror_rows, replace=False)
+    for i in rows:
+        r, p, d = key[i], pos[i], dist[i]
         m, k = int(r[0]), int(r[1])
         x = src.copy()
         for j in range(k):
@@ -230,18 +233,37 @@ def test_theater_full_size_image_sources_and_bands(rt, oracle_lib):
     taps = synth.octave_fir_taps(4095)
     ir = rt.assemble_ir(sc, isrc, N, len(s.rcv), s.alpha, s.beta, s.c, s.fs, s.ir_len, taps)
     mop = material_of_plane(s)
-    alpha = np.asarray(s.alpha, np.float64)
+    one_minus = np.vstack([1.0 - np.asarray(s.alpha, np.float64), np.ones((1, 8))])   # last row: no plane
     beta = np.asarray(s.beta, np.float64)
     want = np.zeros((len(s.rcv), 8))
-    for r, n, d in zip(key, cnt, dist):
-        m, k = int(r[0]), int(r[1])
-        if int(np.floor(d * s.fs / s.c)) >= s.ir_len:
-            continue
-        e = n / N * np.exp(-beta * d)
-        for j in range(k):
-            e = e * (1.0 - alpha[mop[int(r[2 + j])]])
-        want[m] += e
+    inside = np.floor(dist * s.fs / s.c) < s.ir_len
+    for c0 in range(0, len(key), 50_000):
+        sl = slice(c0, c0 + 50_000)
+        pl = key[sl, 2:2 + R].astype(np.int64)
+        live = np.arange(pl.shape[1])[None, :] < kk[sl, None]
+        mat = np.where(live, mop[np.where(live, pl, 0)], len(one_minus) - 1)
+        e = (cnt[sl] / N)[:, None] * np.exp(-beta[None, :] * dist[sl, None]) * one_minus[mat].prod(axis=1)
+        e[~inside[sl]] = 0.0
+        np.add.at(want, key[sl, 0], e)
     got = ir.band_energy.cpu().numpy().astype(np.float64)
+    rel = float(np.max(np.abs(got - want) / np.maximum(want, 1e-30)))
     assert np.all(np.abs(got - want) <= 1e-4 * np.abs(want) + 1e-30)
-    _say("theater full size: %d image sources, %d detections, band energies max rel %.1e" % (
-        len(key), int(cnt.sum()), float(np.max(np.abs(got - want) / np.maximum(want, 1e-30)))))
+    return len(key), int(cnt.sum()), rel
+
+
+def test_theater_full_size_image_sources_and_bands(rt, oracle_lib):
+    """The benchmarked trace (436,120 triangles, 10^6 rays, R = 60, 8
+    receivers, 2 s response): every image-source row checked."""
+    s = synth.theater_c3()
+    sc = rt.Scene.from_synth(s, device="cuda:0")
+    n_is, n_det, rel = _full_size_tables(rt, oracle_lib, s, sc, s.max_reflections, s.max_path_length, None, 0)
+    _say("theater full size: %d image sources, %d detections, band energies max rel %.1e" % (n_is, n_det, rel))
+
+
+def test_jittered_box_full_size_image_sources_and_bands(rt, oracle_lib, c2):
+    """The 100k-triangle jittered box at full size (10^6 rays, R = 50, 3
+    receivers, 1 s response, plane id = triangle id): 3,000 seeded rows
+    mirrored, every row in the band energies."""
+    s, sc = c2
+    n_is, n_det, rel = _full_size_tables(rt, oracle_lib, s, sc, s.max_reflections, s.max_path_length, 3_000, 22)
+    _say("jittered box full size: %d image sources, %d detections, band energies max rel %.1e" % (n_is, n_det, rel))
