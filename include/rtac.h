@@ -154,7 +154,8 @@ typedef struct {
     int32_t rounds;            /* 0 = default (1); kernel launches: once the ray pool is empty,
                                   a wavefront with few rays left hands them to the next launch  */
     int32_t spill_threshold;   /* 0 = default; most rays a wavefront may still hold to hand over */
-    int32_t waves_per_simd;    /* 0 = default (5); register budget of the trace kernel: 4, 5, 6, 8  */
+    int32_t waves_per_simd;    /* 0 = default (5 for rt_trace_rays, 4 for rt_trace_batch); register
+                                  budget of the trace kernel: 4, 5, 6, 8                         */
     void* kernel_event_start;  /* NULL or a hipEvent_t: recorded on `stream` just before the first
                                   traversal-kernel launch (after ray ordering and output fill)  */
     void* kernel_event_stop;   /* NULL or a hipEvent_t: recorded just after the last one        */

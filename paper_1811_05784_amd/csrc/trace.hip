@@ -6,7 +6,8 @@
 // after a reflection it starts the next segment's nearest-hit query at once,
 // and when its ray stops it takes a new ray from a global pool (one atomic
 // per wavefront for all idle lanes).  Nothing round-trips to the host between
-// bounces and the ray state never goes back to HBM.
+// bounces and no ray state is stored between segments (the register spills
+// of the tightest register budget aside).
 //
 // Nearest hit (section "Standard algorithm": 0 <= lambda, mu, lambda + mu <= 1,
 // delta > 0 minimal) walks the 4-wide tree with an ordered short stack (16
@@ -14,7 +15,9 @@
 // conservative slab test for the child boxes (Williams et al.'s test, which
 // the paper uses to sort rays into daughter boxes) and the watertight FP32
 // ray/triangle test of Woop, Benthin and Wald (2013): shared edges are never
-// missed, exact ties go to the lowest triangle id.  Lanes whose query is
+// missed, and exact ties among the triangles a query tests go to the lowest
+// triangle id (a box whose FP32 entry distance rounds just above a tie can be
+// culled once its twin is found).  Lanes whose query is
 // finished wait until enough of the wavefront is finished, then shade
 // together: the chosen triangle's plane crossing, receiver tests and the
 // reflection are evaluated in FP64 and rounded once to FP32.
@@ -1172,9 +1175,12 @@ namespace {
 // fill, launches.  `ws` is the scene whose workspace holds the scratch.
 int run_trace(rt_scene* ws, TraceArgs& a, const rt_trace_params* p, int depth, int64_t max_steps, int64_t n_rays,
               int32_t* hit_seq, const float* dirs, const float* origins, const float* bounds, hipStream_t st) {
-    // 5 waves per SIMD by default: a 96-register budget spills a little, but the busy phase is bound by
-    // the latency of dependent node fetches and gains more from the fifth wavefront than it loses
-    const int occ = p->waves_per_simd == 4 || p->waves_per_simd == 6 || p->waves_per_simd == 8 ? p->waves_per_simd : 5;
+    // Single scene: 5 waves per SIMD by default; a 96-register budget spills a little, but the busy
+    // phase is bound by the latency of dependent node fetches and gains more from the fifth wavefront
+    // than it loses.  Batched: 4, since that instance keeps a per-lane scene view and at 96 registers
+    // spills in its node loop (5 and 6 waves are 42 % and 67 % slower on the 8-room batch).
+    const int wps = p->waves_per_simd;
+    const int occ = (wps == 4 || wps == 5 || wps == 6 || wps == 8) ? wps : (a.jobs ? 4 : 5);
     const int bpc = p->blocks_per_cu > 0 ? p->blocks_per_cu : occ;
     int64_t nblk = (int64_t)device_sm_count() * bpc;
     const int64_t need = (n_rays + kBlock - 1) / kBlock;
