@@ -100,9 +100,10 @@ void Buf::release() {
 void Workspace::release_all() {
     for (auto* b : {&sort_keys[0], &sort_keys[1], &sort_vals[0], &sort_vals[1], &sort_hist, &scan_tmp,
                     &stack_spill, &trace_pool, &is_hash, &is_idx, &is_flags, &is_group, &coll_err, &asm_key,
-                    &asm_idx, &asm_energy, &asm_partial, &asm_pressure, &fir_twiddle, &fir_spec, &generic[0], &generic[1], &generic[2],
-                    &generic[3]})
+                    &asm_idx, &asm_energy, &asm_partial, &asm_pressure, &fir_twiddle, &fir_spec, &band_partial,
+                    &generic[0], &generic[1], &generic[2], &generic[3]})
         b->release();
+    fir_twiddle_done = nullptr;
 }
 
 int device_sm_count() {

@@ -545,7 +545,14 @@ int assemble_common(const rt_scene* scene, const rt_batch* bt, const int32_t* is
         }
         float2* tw = ws.fir_twiddle.as<float2>();
         float2* spec = ws.fir_spec.as<float2>();
-        hipLaunchKernelGGL(k_fft_twiddles, dim3(kFftN / 256), dim3(256), 0, st, tw);
+        // the twiddle table is a constant: computed once per workspace buffer, outside stream
+        // capture (a captured launch only runs when the graph is replayed)
+        if (ws.fir_twiddle_done != (const void*)tw) {
+            hipLaunchKernelGGL(k_fft_twiddles, dim3(kFftN / 256), dim3(256), 0, st, tw);
+            hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+            if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone)
+                ws.fir_twiddle_done = tw;
+        }
         hipLaunchKernelGGL(k_fir_spectrum, dim3(8), dim3(kFftThreads), fshm, st, fir, K, tw, spec);
         const int64_t B = kFftN - K + 1;
         const int64_t n_seg = (L + B - 1) / B;

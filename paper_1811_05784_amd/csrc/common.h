@@ -69,6 +69,7 @@ struct Workspace {
     Buf stack_spill, trace_pool;
     Buf is_hash, is_idx, is_flags, is_group, coll_err;
     Buf asm_key, asm_idx, asm_energy, asm_partial, asm_pressure, fir_twiddle, fir_spec, band_partial;
+    const void* fir_twiddle_done = nullptr;   // fir_twiddle's address once its table has been computed
     Buf generic[4];
     void release_all();
 };

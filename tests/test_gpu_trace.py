@@ -243,6 +243,37 @@ def test_scheduling_leaves_results_unchanged(rt, scenes, name, R, n, kw):
     assert np.array_equal(_sorted_det(a), _sorted_det(b))
 
 
+def test_trace_rays_graph_replay_matches_eager(rt, scenes):
+    """rt_trace_rays captured in a HIP graph (reset, ray ordering, -1 fill of
+    the hit rows, traversal): every replay, after eager work has zeroed the
+    rows, equals the eager call."""
+    s, sc = scenes["c2"]
+    n, R = 50_000, 20
+    dirs = rt.fibonacci_directions(n, device="cuda:0")
+    rcv = torch.as_tensor(s.rcv, device="cuda:0")
+    tr = rt.trace_rays(sc, dirs, rcv, R, src=s.src, det_cap=8 * n)
+    torch.cuda.synchronize()
+    ref_hs, ref_c, ref_det = tr.hit_seq.clone(), tr.counters[:3].clone(), _sorted_det(tr)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        rt.trace_rays(sc, dirs, rcv, R, src=s.src, out=tr, check_capacity=False)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        rt.trace_rays(sc, dirs, rcv, R, src=s.src, out=tr, check_capacity=False)
+    for rep in range(3):
+        tr.hit_seq.zero_()
+        _ = torch.randn(1000, device="cuda:0").sum()     # eager work between replays
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(tr.hit_seq, ref_hs), rep
+        assert torch.equal(tr.counters[:3], ref_c) and int(tr.counters[3]) == 0, rep
+        assert np.array_equal(_sorted_det(tr), ref_det), rep
+
+
 @pytest.mark.parametrize("name,R,n", [("c1", 20, 300), ("c2", 50, 3_000), ("c3", 60, 5_000)])
 def test_cooperative_search_small_calls(rt, scenes, name, R, n):
     """With few rays per wavefront the pool is empty at once, and many
