@@ -474,53 +474,57 @@ __global__ void k_flag4(int64_t n_in, const int32_t* __restrict__ first, const i
 }
 
 // Writes the 4-wide node of flagged binary node i; returns its depth level.
+// Its slots are the two children, each replaced by its own two children when
+// it is an inner node larger than a leaf: with eA, eB those two choices the
+// slot refs have closed forms, so every slot's loads can be in flight at once.
 __device__ inline uint32_t emit4_one(int64_t i, const int32_t* __restrict__ left, const int32_t* __restrict__ right,
                                      const int32_t* __restrict__ first, const int32_t* __restrict__ last,
                                      const uint32_t* __restrict__ index, const int32_t* __restrict__ depth_in,
                                      const float* __restrict__ box_in, const float* __restrict__ tri_box,
                                      const uint32_t* __restrict__ order, int32_t leaf_size, Node4* __restrict__ nodes) {
-    int32_t slot_ref[4];
-    float slot_box[4][6];
-    int ns = 0;
-    auto add = [&](int32_t c) {
-        float* b = slot_box[ns];
-        if (c < 0) {
-            const uint32_t t = order[~c];
-            for (int a = 0; a < 6; a++) b[a] = tri_box[6 * (int64_t)t + a];
-            slot_ref[ns] = leaf_ref(~c, 1);
-        } else {
-            for (int a = 0; a < 6; a++) b[a] = box_in[6 * (int64_t)c + a];
-            const int32_t sz = last[c] - first[c] + 1;
-            slot_ref[ns] = sz <= leaf_size ? leaf_ref(first[c], sz) : (int32_t)index[c];
-        }
-        ns++;
-    };
-    const int32_t ch[2] = {left[i], right[i]};
-    for (int q = 0; q < 2; q++) {
-        const int32_t c = ch[q];
-        if (c < 0 || node_size(first, last, c) <= leaf_size) {
-            add(c);
-        } else {
-            add(left[c]);
-            add(right[c]);
-        }
-    }
+    const int32_t c0 = left[i], c1 = right[i];
+    const bool eA = c0 >= 0 && node_size(first, last, c0) > leaf_size;
+    const bool eB = c1 >= 0 && node_size(first, last, c1) > leaf_size;
+    const int32_t a0 = eA ? left[c0] : c0, a1 = eA ? right[c0] : 0;
+    const int32_t b0 = eB ? left[c1] : c1, b1 = eB ? right[c1] : 0;
+    int32_t ref[4];
+    bool use[4];
+    ref[0] = a0;
+    use[0] = true;
+    ref[1] = eA ? a1 : b0;
+    use[1] = true;
+    ref[2] = eA ? b0 : b1;
+    use[2] = eA || eB;
+    ref[3] = b1;
+    use[3] = eA && eB;
     Node4 nd;
-    for (int s = 0; s < 4; s++) {
-        if (s < ns) {
-            nd.lox[s] = slot_box[s][0];
-            nd.loy[s] = slot_box[s][1];
-            nd.loz[s] = slot_box[s][2];
-            nd.hix[s] = slot_box[s][3];
-            nd.hiy[s] = slot_box[s][4];
-            nd.hiz[s] = slot_box[s][5];
-            nd.child[s] = slot_ref[s];
+#pragma unroll
+    for (int sl = 0; sl < 4; sl++) {
+        float bx[6];
+        int32_t child = kEmpty;
+        if (use[sl]) {
+            const int32_t c = ref[sl];
+            if (c < 0) {
+                const uint32_t t = order[~c];
+                for (int q = 0; q < 6; q++) bx[q] = tri_box[6 * (int64_t)t + q];
+                child = leaf_ref(~c, 1);
+            } else {
+                for (int q = 0; q < 6; q++) bx[q] = box_in[6 * (int64_t)c + q];
+                const int32_t sz = last[c] - first[c] + 1;
+                child = sz <= leaf_size ? leaf_ref(first[c], sz) : (int32_t)index[c];
+            }
         } else {
-            nd.lox[s] = nd.loy[s] = nd.loz[s] = INFINITY;
-            nd.hix[s] = nd.hiy[s] = nd.hiz[s] = -INFINITY;
-            nd.child[s] = kEmpty;
+            bx[0] = bx[1] = bx[2] = INFINITY;
+            bx[3] = bx[4] = bx[5] = -INFINITY;
         }
-        nd.pad[s] = 0;
+        nd.lox[sl] = bx[0];
+        nd.loy[sl] = bx[1];
+        nd.loz[sl] = bx[2];
+        nd.hix[sl] = bx[3];
+        nd.hiy[sl] = bx[4];
+        nd.hiz[sl] = bx[5];
+        nd.child[sl] = child;
+        nd.pad[sl] = 0;
     }
     nodes[index[i]] = nd;
     return (uint32_t)(depth_in[i] / 2 + 1);
