@@ -180,6 +180,16 @@ __global__ void k_head_pos(CollectArgs a, const uint32_t* __restrict__ head, con
         if (head[i]) hpos[group[i]] = (uint32_t)i;
 }
 
+// Every entry of the first n_is rows (R + 2 entries each) set to -1 with
+// contiguous stores; k_emit then writes only the (receiver, k, planes) prefix.
+__global__ void k_pad_rows(int32_t* __restrict__ is_key, int64_t row_len, const int64_t* __restrict__ n_is,
+                           int64_t is_cap) {
+    const int64_t ng = *n_is < is_cap ? *n_is : is_cap;
+    const int64_t total = ng * row_len;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x)
+        is_key[i] = -1;
+}
+
 struct EmitArgs {
     const double* pn;
     const double* pp;
@@ -209,8 +219,7 @@ __device__ void emit_one(const CollectArgs& a, const EmitArgs& e, const uint32_t
     int32_t ray, k, m;
     int32_t* row = e.is_key + g * (int64_t)(a.R1 + 1);
     if (!det_row(a, d, ray, k, m)) {
-        for (int j = 0; j < a.R1 + 1; j++) row[j] = -1;
-        e.is_count[g] = (int32_t)(p1 - p0);
+        e.is_count[g] = (int32_t)(p1 - p0);   // the row stays -1 (k_pad_rows)
         e.is_pos[3 * g] = e.is_pos[3 * g + 1] = e.is_pos[3 * g + 2] = 0.0;
         e.is_dist[g] = __longlong_as_double(0x7FF8000000000000ll);
         return;
@@ -239,7 +248,7 @@ __device__ void emit_one(const CollectArgs& a, const EmitArgs& e, const uint32_t
         y -= 2.0 * h * ny;
         z -= 2.0 * h * nz;
     }
-    for (int j = k; j < a.R1 - 1; j++) row[2 + j] = -1;   // row holds R + 2 = R1 + 1 entries
+    // entries 2 + k .. R + 1 keep the -1 written by k_pad_rows
     e.is_count[g] = (int32_t)(p1 - p0);
     e.is_pos[3 * g] = x;
     e.is_pos[3 * g + 1] = y;
@@ -342,6 +351,8 @@ int collect_common(rt_scene* s, const rt_batch* b, const float* src_host, const 
     e.is_pos = is_pos;
     e.is_dist = is_dist;
     e.is_cap = is_cap;
+    hipLaunchKernelGGL(k_pad_rows, dim3((unsigned)(device_sm_count() * 8)), dim3(256), 0, st, is_key,
+                       (int64_t)(a.R1 + 1), n_is, is_cap);
     hipLaunchKernelGGL(k_emit, dim3(nblk(cap)), dim3(256), 0, st, a, e, ix, hpos, n_is);
     RT_HIP(hipGetLastError());
     return RT_OK;
