@@ -67,6 +67,30 @@ __device__ inline int32_t plane_at(const CollectArgs& a, int32_t m, int32_t ray,
     return (t >= 0 && t < a.n_tri) ? a.tri_plane[t] : -1;
 }
 
+// The triangle-to-plane table of receiver row m's scene.
+__device__ inline void scene_planes(const CollectArgs& a, int32_t m, const int32_t*& tp, int32_t& nt) {
+    if (a.rcv_job) {
+        const DevScene& sc = a.scenes[a.jobs[a.rcv_job[m]].scene];
+        tp = sc.tri_plane;
+        nt = sc.n_tri;
+    } else {
+        tp = a.tri_plane;
+        nt = a.n_tri;
+    }
+}
+
+// Plane ids of hits j0 .. j0 + C - 1 of a ray (-1 past k or for an invalid
+// triangle), every load of the chunk in flight together.
+template <int C>
+__device__ inline void planes_of(const CollectArgs& a, const int32_t* tp, int32_t nt, int32_t ray, int32_t j0,
+                                 int32_t k, int32_t (&p)[C]) {
+    int32_t t[C];
+#pragma unroll
+    for (int q = 0; q < C; q++) t[q] = j0 + q < k ? a.hit_seq[(int64_t)ray * a.R1 + j0 + q] : -1;
+#pragma unroll
+    for (int q = 0; q < C; q++) p[q] = (t[q] >= 0 && t[q] < nt) ? tp[t[q]] : -1;
+}
+
 __global__ void k_hash(CollectArgs a, uint64_t mask, uint64_t* __restrict__ hash, uint32_t* __restrict__ err) {
     const int64_t n = det_count(a);
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -77,10 +101,19 @@ __global__ void k_hash(CollectArgs a, uint64_t mask, uint64_t* __restrict__ hash
             continue;
         }
         uint64_t h = mix64(0x9E3779B97F4A7C15ull ^ ((uint64_t)(uint32_t)m << 32 | (uint32_t)k));
-        for (int j = 0; j < k; j++) {
-            const int32_t p = plane_at(a, m, ray, j);
-            if (p < 0) atomicOr(err, 2u);
-            h = mix64(h + 0x632BE59BD9B4E019ull * (uint64_t)(uint32_t)(p + 1));
+        const int32_t* tp;
+        int32_t nt;
+        scene_planes(a, m, tp, nt);
+        for (int j0 = 0; j0 < k; j0 += 8) {
+            int32_t p[8];
+            planes_of<8>(a, tp, nt, ray, j0, k, p);
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                if (j0 + q < k) {
+                    if (p[q] < 0) atomicOr(err, 2u);
+                    h = mix64(h + 0x632BE59BD9B4E019ull * (uint64_t)(uint32_t)(p[q] + 1));
+                }
+            }
         }
         hash[i] = h & mask;
     }
@@ -237,16 +270,35 @@ __device__ void emit_one(const CollectArgs& a, const EmitArgs& e, const uint32_t
         pn = a.scenes[jb.scene].plane_n;
         pp = a.scenes[jb.scene].plane_p;
     }
-    for (int j = 0; j < k; j++) {
-        const int32_t p = plane_at(a, m, ray, j);
-        row[2 + j] = p;
-        if (p < 0) continue;
-        const double nx = pn[3 * (int64_t)p], ny = pn[3 * (int64_t)p + 1], nz = pn[3 * (int64_t)p + 2];
-        const double h = (x - pp[3 * (int64_t)p]) * nx + (y - pp[3 * (int64_t)p + 1]) * ny +
-                         (z - pp[3 * (int64_t)p + 2]) * nz;
-        x -= 2.0 * h * nx;
-        y -= 2.0 * h * ny;
-        z -= 2.0 * h * nz;
+    const int32_t* tp;
+    int32_t nt;
+    scene_planes(a, m, tp, nt);
+    for (int j0 = 0; j0 < k; j0 += 4) {
+        // plane ids, normals and points of four hits fetched together, then mirrored in order
+        int32_t p[4];
+        planes_of<4>(a, tp, nt, ray, j0, k, p);
+        double n[4][3], o[4][3];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const bool ok = p[q] >= 0;
+            for (int c = 0; c < 3; c++) {
+                n[q][c] = ok ? pn[3 * (int64_t)p[q] + c] : 0.0;
+                o[q][c] = ok ? pp[3 * (int64_t)p[q] + c] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            if (j0 + q < k) {
+                row[2 + j0 + q] = p[q];
+                if (p[q] >= 0) {
+                    const double nx = n[q][0], ny = n[q][1], nz = n[q][2];
+                    const double h = (x - o[q][0]) * nx + (y - o[q][1]) * ny + (z - o[q][2]) * nz;
+                    x -= 2.0 * h * nx;
+                    y -= 2.0 * h * ny;
+                    z -= 2.0 * h * nz;
+                }
+            }
+        }
     }
     // entries 2 + k .. R + 1 keep the -1 written by k_pad_rows
     e.is_count[g] = (int32_t)(p1 - p0);
