@@ -77,14 +77,22 @@ __global__ void k_is_energy(IsArgs a, double* __restrict__ E, uint64_t* __restri
         const MatView mv = mat_view(a, ok ? m : 0);
         const double base = (double)a.count[i] / (double)mv.n_rays;
         for (int b = 0; b < 8; b++) e[b] = base * exp(-(double)a.beta[b] * d);
-        for (int j = 0; ok && j < k; j++) {
-            const int32_t p = row[2 + j];
-            if (p < 0 || p >= mv.n_tri) {
-                ok = false;
-                break;
+        // planes and their materials fetched eight at a time, factors applied in order (a row
+        // with an invalid plane is dropped from the histogram, whatever its factors)
+        for (int j0 = 0; ok && j0 < k; j0 += 8) {
+            int32_t p[8], mt[8];
+#pragma unroll
+            for (int q = 0; q < 8; q++) p[q] = j0 + q < k ? row[2 + j0 + q] : 0;
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                const bool valid = p[q] >= 0 && p[q] < mv.n_tri;
+                if (j0 + q < k && !valid) ok = false;
+                mt[q] = (j0 + q < k && valid) ? mv.mat_off + mv.plane_mat[p[q]] : -1;
             }
-            const int32_t mat = mv.mat_off + mv.plane_mat[p];
-            for (int b = 0; b < 8; b++) e[b] *= 1.0 - (double)a.alpha[8 * mat + b];
+#pragma unroll
+            for (int q = 0; q < 8; q++)
+                if (mt[q] >= 0)
+                    for (int b = 0; b < 8; b++) e[b] *= 1.0 - (double)a.alpha[8 * mt[q] + b];
         }
         for (int b = 0; b < 8; b++) E[8 * i + b] = e[b];
         const double sb = floor(d * a.fs / a.c);
