@@ -15,6 +15,8 @@
 // and the signal window (sqrt applied on load) are staged in LDS; the window
 // is stored 20 floats per 16 samples so that the 64 lanes of one B fragment
 // hit 64 different banks.
+#include <initializer_list>
+
 #include "common.h"
 
 namespace rtac {
@@ -481,6 +483,27 @@ IsArgs make_is_args(const rt_scene* s, const int32_t* is_key, const int32_t* is_
     return a;
 }
 
+constexpr int kMaxDevices = 64;
+
+// Raises the dynamic-LDS limit of the given kernels on the current device, once
+// per device (the attribute belongs to each device's copy of the code object).
+// false, with the error message set, when a HIP call fails.
+bool raise_lds_limit(bool* done, std::initializer_list<const void*> kernels, int bytes) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess && dev >= 0 && dev < kMaxDevices && done[dev]) return true;
+    for (const void* k : kernels) {
+        if (e != hipSuccess) break;
+        e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    }
+    if (e != hipSuccess) {
+        set_error("rt_assemble_ir: raising the LDS limit to %d bytes failed: %s", bytes, hipGetErrorString(e));
+        return false;
+    }
+    if (dev >= 0 && dev < kMaxDevices) done[dev] = true;
+    return true;
+}
+
 }  // namespace
 
 }  // namespace rtac
@@ -544,13 +567,10 @@ int assemble_common(const rt_scene* scene, const rt_batch* bt, const int32_t* is
         // long filters: overlap-save FFT convolution
         if (ws.fir_twiddle.ensure(sizeof(float2) * kFftN) || ws.fir_spec.ensure(sizeof(float2) * 8 * kFftN))
             return RT_ENOMEM;
-        static bool fft_attr_set = false;
         const size_t fshm = sizeof(float2) * kFftN;
-        if (!fft_attr_set) {
-            hipFuncSetAttribute((const void*)k_fir_spectrum, hipFuncAttributeMaxDynamicSharedMemorySize, (int)fshm);
-            hipFuncSetAttribute((const void*)k_fir_fft, hipFuncAttributeMaxDynamicSharedMemorySize, (int)fshm);
-            fft_attr_set = true;
-        }
+        static bool fft_attr_set[kMaxDevices] = {};
+        if (!raise_lds_limit(fft_attr_set, {(const void*)k_fir_spectrum, (const void*)k_fir_fft}, (int)fshm))
+            return RT_EHIP;
         float2* tw = ws.fir_twiddle.as<float2>();
         float2* spec = ws.fir_spec.as<float2>();
         // the twiddle table is a constant: computed once per workspace buffer, outside stream
@@ -572,11 +592,8 @@ int assemble_common(const rt_scene* scene, const rt_batch* bt, const int32_t* is
         const int W = kFirOut + 4 * Smax + 16;
         const size_t shm = sizeof(float) * ((size_t)Kpad + (size_t)((W >> 4) + 2) * 20);
         RT_CHECK(shm <= 160 * 1024, RT_EINVAL, "rt_assemble_ir: FIR taps too long for LDS");
-        static bool attr_set = false;
-        if (!attr_set) {
-            hipFuncSetAttribute((const void*)k_fir_mfma, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-            attr_set = true;
-        }
+        static bool attr_set[kMaxDevices] = {};
+        if (!raise_lds_limit(attr_set, {(const void*)k_fir_mfma}, 160 * 1024)) return RT_EHIP;
         dim3 grid((unsigned)((L + kFirOut - 1) / kFirOut), (unsigned)(n_rcv * 8));
         hipLaunchKernelGGL(k_fir_mfma, grid, dim3(256), shm, st, hist, fir, K, L, band_ir);
     }
