@@ -788,6 +788,14 @@ k_trace(TraceArgs a) {
             const float4* np = reinterpret_cast<const float4*>(nodes + cur);
             const float4 lx = np[0], hx = np[1], ly = np[2], hy = np[3], lz = np[4], hz = np[5];
             const int4 ch = reinterpret_cast<const int4*>(np)[6];
+            // once the pool is empty: touch the node on top of the stack along with
+            // this one, so that the pop after a step whose children all miss finds
+            // its node in the cache (a step that pops pushes nothing)
+            int32_t touch = 0;
+            if (pool_empty && st.cnt > 0) {
+                const int32_t top = lds_stack[((st.base + st.cnt - 1) & (kRing - 1)) * kBlock + tid];
+                if (top >= 0 && top < n_nodes) touch = reinterpret_cast<const int32_t*>(nodes + top)[0];
+            }
             const float tlim = best_t;
             float tn[4];
             int32_t rf[4];
@@ -873,6 +881,7 @@ k_trace(TraceArgs a) {
                 have = stack_pop(st, lds_stack, spill, tid, cur);
             }
             if (!have) status = kDone;
+            asm volatile("" ::"v"(touch));   // keeps the touch load
         }
 
         // ---- shade the finished queries (FP64), record, reflect ---------------
