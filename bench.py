@@ -182,7 +182,7 @@ def run_theater(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 traversal, f64 shading/image sources, f32 MFMA FIR",
+        "dtype": "f32 traversal, f64 shading/image sources, f32 FFT FIR",
         "data": "synthetic (seeded theater stand-in for the 436k-face mesh; Fibonacci rays)",
         "config": {"workload": "open-air theater 436,120 tris, 1e6 rays, R=60, 8 receivers r=2 m, 2 s IR "
                                "@48 kHz, 8 bands, K=4095", "n_tri": s.n_tri, "rays": args.rays,
@@ -745,7 +745,11 @@ def cpu_baseline(s, n_cpu):
                        threads=1)
     dt1 = time.perf_counter() - t0
     q1 = int(tr1["tests"] // s.n_tri)
+    host = oracle.host_cpus()
     return {"value": q / dt, "unit": "rays·bounces/s", "cores": threads, "kind": "oracle",
+            "host": {"nproc": host["affinity"], "cpu_count": host["cpu_count"],
+                     "note": "threads = the process's CPU share (affinity, OMP_NUM_THREADS, at most 16 "
+                             "per GPU on a shared node)"},
             "sample": "%d of the 1e6 Fibonacci rays (seeded choice), full trajectories, FP64 brute force over "
                       "all %d triangles; %d queries in %.1f s" % (n_cpu, s.n_tri, q, dt),
             "triangle_tests_per_s": tr["tests"] / dt,

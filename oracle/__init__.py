@@ -9,6 +9,7 @@ Each function cites the part of the paper it follows:
 * ``fibonacci``       -- omnidirectional source, unit-sphere sampling by
                          Fibonacci's rule (section "Discrete model").
 * ``trace`` /
+  ``trace_from`` /
   ``query_batch``     -- brute-force nearest hit over all triangles with the
                          parametric conditions 0 <= lambda, mu; lambda + mu <= 1;
                          delta > 0 minimal (section "Standard algorithm"),
@@ -88,6 +89,8 @@ def lib():
         L.or_query_batch.argtypes = [P, P, P, P, P, i64, P, i32, dbl, dbl, i32, i32, P, P, P, P, P]
         L.or_trace.restype = i64
         L.or_trace.argtypes = [P, P, P, i64, P, i32, i32, dbl, dbl, i32, i32, P, P, P, P]
+        L.or_trace_from.restype = i64
+        L.or_trace_from.argtypes = [P, P, i64, P, i32, i32, dbl, dbl, i32, i32, P, P, P, P]
         L.or_image_positions.argtypes = [P, P, P, P, i64, P]
         L.or_fir_same.argtypes = [P, i64, i64, P, i32, P, i32]
         _lib = L
@@ -98,8 +101,25 @@ def _p(a):
     return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
 
 
+def host_cpus() -> Dict[str, int]:
+    """What the host offers this process: logical CPUs of the machine, CPUs in
+    the process's affinity mask, and the thread share it is granted
+    (OMP_NUM_THREADS when set, at most 16: the share of one GPU's host on a
+    shared GPU node)."""
+    total = os.cpu_count() or 1
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = total
+    share = affinity
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        share = min(share, int(env))
+    return {"cpu_count": total, "affinity": affinity, "threads": max(1, min(16, share))}
+
+
 def default_threads() -> int:
-    return max(1, min(16, os.cpu_count() or 1))
+    return host_cpus()["threads"]
 
 
 class OracleScene:
@@ -266,6 +286,28 @@ def trace(sc: OracleScene, src, dirs, rcv, max_reflections: int, max_len: float 
     tests = lib().or_trace(sc._h, _p(src), _p(dirs), n, _p(rcv), len(rcv), max_reflections,
                            float(max_len), float(eps), int(flags), threads or default_threads(),
                            _p(hs), _p(det), _p(fl), _p(st))
+    assert tests >= 0
+    return dict(hit_seq=hs, det=det, flags=fl, states=st, tests=tests)
+
+
+def trace_from(sc: OracleScene, start, rcv, max_reflections: int, max_len: float = 0.0,
+               eps: float = DEFAULT_EPS, flags: bool = True, states: bool = False,
+               threads: int = 0) -> Dict[str, np.ndarray]:
+    """The propagation of ``trace`` continued from per-ray FP64 states
+    start [N, 8] = (o, u, L, last plane), such as ``trace(states=True)``'s row
+    after a reflection: segment 0 here is the ray's next segment (section
+    "Standard algorithm": the iteration only carries the ray's position,
+    direction and travelled length from one reflection to the next)."""
+    start = np.ascontiguousarray(start, np.float64).reshape(-1, 8)
+    rcv = np.ascontiguousarray(rcv, np.float32).reshape(-1, 4)
+    n, R1 = len(start), max_reflections + 1
+    hs = np.empty((n, R1), np.int32)
+    det = np.empty((n, R1), np.uint32)
+    fl = np.empty((n, R1), np.uint32)
+    st = np.empty((n, R1 + 1, 8)) if states else None
+    tests = lib().or_trace_from(sc._h, _p(start), n, _p(rcv), len(rcv), max_reflections, float(max_len),
+                                float(eps), int(flags), threads or default_threads(), _p(hs), _p(det), _p(fl),
+                                _p(st))
     assert tests >= 0
     return dict(hit_seq=hs, det=det, flags=fl, states=st, tests=tests)
 

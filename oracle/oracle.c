@@ -408,6 +408,7 @@ typedef struct {
     const or_scene* s;
     const float* src;
     const float* dirs;
+    const double* start;   /* [N, 8] per-ray start state (o, u, L, last plane) or NULL */
     const float* rcv;
     int n_rcv, R, want_flags;
     double max_len, eps;
@@ -420,10 +421,23 @@ typedef struct {
 static void tr_item(void* vc, int64_t i, int64_t* tests) {
     tr_ctx* c = (tr_ctx*)vc;
     const int R1 = c->R + 1;
-    double o[3] = {c->src[0], c->src[1], c->src[2]};
-    double u[3] = {c->dirs[3 * i], c->dirs[3 * i + 1], c->dirs[3 * i + 2]};
-    double L = 0.0;
+    double o[3], u[3], L = 0.0;
     int lp = -1;
+    if (c->start) {
+        /* resumed ray: its state after an earlier call's last reflection */
+        const double* st0 = &c->start[8 * i];
+        for (int a = 0; a < 3; a++) {
+            o[a] = st0[a];
+            u[a] = st0[3 + a];
+        }
+        L = st0[6];
+        lp = (int)st0[7];
+    } else {
+        for (int a = 0; a < 3; a++) {
+            o[a] = c->src[a];
+            u[a] = c->dirs[3 * i + a];
+        }
+    }
     for (int k = 0; k < R1; k++) {
         c->hit_seq[i * R1 + k] = -1;
         if (c->det) c->det[i * R1 + k] = 0;
@@ -464,7 +478,18 @@ int64_t or_trace(const or_scene* s, const float* src, const float* dirs, int64_t
                  int n_rcv, int R, double max_len, double eps, int want_flags, int nthreads, int32_t* hit_seq,
                  uint32_t* det, uint32_t* flags, double* states) {
     if (n_rcv > 32 || R < 0) return -1;
-    tr_ctx c = {s, src, dirs, rcv, n_rcv, R, want_flags, max_len, eps, hit_seq, det, flags, states};
+    tr_ctx c = {s, src, dirs, NULL, rcv, n_rcv, R, want_flags, max_len, eps, hit_seq, det, flags, states};
+    return run_pool(n_rays, nthreads, 8, tr_item, &c);
+}
+
+/* The same propagation loop continued from per-ray FP64 states start[N, 8] =
+ * (o, u, L, last plane), e.g. rows of an earlier call's `states` taken after
+ * its last reflection: segment 0 of this call is the next segment of that ray. */
+int64_t or_trace_from(const or_scene* s, const double* start, int64_t n_rays, const float* rcv, int n_rcv, int R,
+                      double max_len, double eps, int want_flags, int nthreads, int32_t* hit_seq, uint32_t* det,
+                      uint32_t* flags, double* states) {
+    if (n_rcv > 32 || R < 0) return -1;
+    tr_ctx c = {s, NULL, NULL, start, rcv, n_rcv, R, want_flags, max_len, eps, hit_seq, det, flags, states};
     return run_pool(n_rays, nthreads, 8, tr_item, &c);
 }
 
