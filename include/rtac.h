@@ -414,6 +414,25 @@ int rt_edc_db(const float* hist, int64_t rows, int32_t bins, float floor_db, flo
  */
 int rt_room_params(const float* hist, int32_t n_rcv, int64_t L, float fs, double* params, void* stream);
 
+/*
+ * rt_room_params_noalloc -- rt_room_params for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, kernels and results as
+ * rt_room_params (bit for bit); no hipMalloc, hipFree or other allocating
+ * call is made.  Its scratch (chunk sums, chunk prefixes, per-band facts and
+ * regression sums: 128 bytes per (receiver, band, chunk of 4096 bins) plus 48
+ * bytes per (receiver, band)) lives in a fixed 4 MiB device array, one copy
+ * per GPU, held until the process ends; its address is looked up on the
+ * first call on each device: up to 520,192 bins with 32 receivers, or
+ * 2,093,056 bins with 8.  Larger requests return RT_ECAPACITY with a message
+ * before any device call.
+ * Every scratch element is written before it is read in a call, so nothing
+ * needs clearing between calls.  All calls on one GPU share the array: calls
+ * that overlap in time on that GPU (two streams, two threads) race and must
+ * be serialised by the caller.
+ */
+int rt_room_params_noalloc(const float* hist, int32_t n_rcv, int64_t L, float fs, double* params, void* stream);
+
 /* Test hook for the exact-grouping path of rt_collect_image_sources: keep
  * only the low `bits` bits (1..64, default 32) of the 64-bit key hash so that
  * distinct keys collide.  Process-wide; not thread-safe with concurrent

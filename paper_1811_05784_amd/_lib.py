@@ -66,6 +66,7 @@ SIGNATURES = {
     "rt_hist_features": (ctypes.c_int, [P, I64, F32, F32, F32, P, P]),
     "rt_edc_db": (ctypes.c_int, [P, I64, I32, F32, P, P]),
     "rt_room_params": (ctypes.c_int, [P, I32, I64, F32, P, P]),
+    "rt_room_params_noalloc": (ctypes.c_int, [P, I32, I64, F32, P, P]),
     "rt_debug_set_hash_bits": (ctypes.c_int, [ctypes.c_int]),
     "rt_last_error": (ctypes.c_char_p, []),
     "rt_version": (ctypes.c_char_p, []),

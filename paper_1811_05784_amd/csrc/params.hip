@@ -18,6 +18,7 @@
 #include "common.h"
 
 #include <cmath>
+#include <mutex>
 
 namespace rtac {
 namespace {
@@ -284,31 +285,107 @@ __global__ void __launch_bounds__(kWave) k_rp_final(int64_t L, int64_t nc, doubl
 
 using namespace rtac;
 
-extern "C" int rt_room_params(const float* hist, int32_t n_rcv, int64_t L, float fs, double* params, void* stream) {
-    RT_CHECK(n_rcv >= 0 && L >= 1 && fs > 0.f, RT_EINVAL, "rt_room_params: bad sizes");
-    RT_CHECK(n_rcv == 0 || (hist && params), RT_EINVAL, "rt_room_params: null argument");
-    if (n_rcv == 0) return RT_OK;
+namespace rtac {
+namespace {
+
+// Scratch of one call: chunk sums, chunk prefixes, band facts, pass-2 sums.
+struct RpScratch {
+    size_t b_cs, b_pre, b_bi, b_part;
+    size_t total() const { return b_cs + b_pre + b_bi + b_part; }
+};
+
+RpScratch rp_scratch_size(int64_t nb, int64_t nc) {
+    RpScratch s;
+    s.b_cs = sizeof(ChunkSums) * nb * nc;
+    s.b_pre = sizeof(double) * nb * nc;
+    s.b_bi = sizeof(BandInfo) * nb;
+    s.b_part = sizeof(double) * kNSum * nb * nc;
+    return s;
+}
+
+int rp_check(const float* hist, int32_t n_rcv, int64_t L, float fs, double* params, const char* who) {
+    RT_CHECK(n_rcv >= 0 && L >= 1 && fs > 0.f, RT_EINVAL, "%s: bad sizes", who);
+    RT_CHECK(n_rcv == 0 || (hist && params), RT_EINVAL, "%s: null argument", who);
+    const int64_t nc = (L + kChunk - 1) / kChunk;
+    RT_CHECK((int64_t)n_rcv * 8 * nc < ((int64_t)1 << 31), RT_EINVAL, "%s: histogram too large", who);
+    return RT_OK;
+}
+
+// The four passes on a scratch area of rp_scratch_size(n_rcv * 8, chunks) bytes.
+void rp_launch(const float* hist, int32_t n_rcv, int64_t L, float fs, double* params, char* ws, hipStream_t st) {
     const int64_t nb = (int64_t)n_rcv * 8;
     const int64_t nc = (L + kChunk - 1) / kChunk;
-    RT_CHECK(nb * nc < ((int64_t)1 << 31), RT_EINVAL, "rt_room_params: histogram too large");
     const int64_t n80 = (int64_t)std::floor(0.08 * (double)fs + 0.5);
     const int64_t n50 = (int64_t)std::floor(0.05 * (double)fs + 0.5);
-    hipStream_t st = (hipStream_t)stream;
-    // stream-ordered scratch: chunk sums, chunk prefixes, band facts, pass-2 sums
-    const size_t b_cs = sizeof(ChunkSums) * nb * nc, b_pre = sizeof(double) * nb * nc;
-    const size_t b_bi = sizeof(BandInfo) * nb, b_part = sizeof(double) * kNSum * nb * nc;
-    char* ws = nullptr;
-    RT_HIP(hipMallocAsync((void**)&ws, b_cs + b_pre + b_bi + b_part, st));
+    const RpScratch sz = rp_scratch_size(nb, nc);
     ChunkSums* cs = reinterpret_cast<ChunkSums*>(ws);
-    double* pre = reinterpret_cast<double*>(ws + b_cs);
-    BandInfo* bi = reinterpret_cast<BandInfo*>(ws + b_cs + b_pre);
-    double* part = reinterpret_cast<double*>(ws + b_cs + b_pre + b_bi);
+    double* pre = reinterpret_cast<double*>(ws + sz.b_cs);
+    BandInfo* bi = reinterpret_cast<BandInfo*>(ws + sz.b_cs + sz.b_pre);
+    double* part = reinterpret_cast<double*>(ws + sz.b_cs + sz.b_pre + sz.b_bi);
+    // every scratch element is written before it is read within the call
     hipLaunchKernelGGL(k_rp_chunks, dim3((unsigned)(nb * nc)), dim3(kPT), 0, st, hist, L, nc, cs);
     hipLaunchKernelGGL(k_rp_band, dim3((unsigned)nb), dim3(kWave), 0, st, hist, L, nc, n50, n80, cs, pre, bi);
     hipLaunchKernelGGL(k_rp_edc, dim3((unsigned)(nb * nc)), dim3(kPT), 0, st, hist, L, nc, (double)fs, pre, bi, part);
     hipLaunchKernelGGL(k_rp_final, dim3((unsigned)nb), dim3(kWave), 0, st, L, nc, (double)fs, bi, part, params);
+}
+
+// Fixed scratch of rt_room_params_noalloc: one copy per GPU, held until the
+// process ends.  Host code reaches it only through the per-device address
+// returned by hipGetSymbolAddress (the symbol itself is a host-side stand-in).
+constexpr size_t kRpScratchMax = (size_t)4 << 20;
+static __device__ __align__(256) unsigned char scratch[kRpScratchMax];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of this device's copy of `scratch`, looked up once per device (with
+// that device current: the caller's).
+int rp_scratch_ptr(char** out) {
+    int dev = 0;
+    RT_HIP(hipGetDevice(&dev));
+    RT_CHECK(dev >= 0 && dev < kMaxDevices, RT_EINVAL, "rt_room_params_noalloc: device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        RT_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        RT_CHECK(p != nullptr, RT_EHIP, "rt_room_params_noalloc: no device address for the scratch array");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = static_cast<char*>(g_scratch_ptr[dev]);
+    return RT_OK;
+}
+
+}  // namespace
+}  // namespace rtac
+
+using namespace rtac;
+
+extern "C" int rt_room_params(const float* hist, int32_t n_rcv, int64_t L, float fs, double* params, void* stream) {
+    if (int rc = rp_check(hist, n_rcv, L, fs, params, "rt_room_params")) return rc;
+    if (n_rcv == 0) return RT_OK;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t bytes = rp_scratch_size((int64_t)n_rcv * 8, (L + kChunk - 1) / kChunk).total();
+    char* ws = nullptr;
+    RT_HIP(hipMallocAsync((void**)&ws, bytes, st));
+    rp_launch(hist, n_rcv, L, fs, params, ws, st);
     const hipError_t le = hipGetLastError();
     RT_HIP(hipFreeAsync(ws, st));
     RT_HIP(le);
+    return RT_OK;
+}
+
+extern "C" int rt_room_params_noalloc(const float* hist, int32_t n_rcv, int64_t L, float fs, double* params,
+                                      void* stream) {
+    if (int rc = rp_check(hist, n_rcv, L, fs, params, "rt_room_params_noalloc")) return rc;
+    const size_t bytes = rp_scratch_size((int64_t)n_rcv * 8, (L + kChunk - 1) / kChunk).total();
+    RT_CHECK(bytes <= kRpScratchMax, RT_ECAPACITY,
+             "rt_room_params_noalloc: %d receivers x %lld bins need %zu bytes of scratch, above the fixed %zu",
+             n_rcv, (long long)L, bytes, kRpScratchMax);
+    if (n_rcv == 0) return RT_OK;
+    char* ws = nullptr;
+    if (int rc = rp_scratch_ptr(&ws)) return rc;
+    rp_launch(hist, n_rcv, L, fs, params, ws, (hipStream_t)stream);
+    RT_HIP(hipGetLastError());
     return RT_OK;
 }

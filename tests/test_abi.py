@@ -57,6 +57,27 @@ def test_argument_validation_without_device(lib):
     assert lib.rt_scene_destroy(None) == 0
 
 
+def test_room_params_noalloc_rejects_requests_above_its_scratch(lib):
+    """The no-allocation entry point's fixed scratch holds 4 MiB: 128 bytes per
+    (receiver, band, chunk of 4096 bins) plus 48 per (receiver, band).  A
+    larger request returns RT_ECAPACITY before any device call (host-side
+    check), so no device is needed; skipped where a GPU is visible, since an
+    accepted request would then launch on these stand-in pointers."""
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("host-only check; a GPU is visible")
+    buf = (ctypes.c_double * 8)()
+    p = ctypes.cast(buf, ctypes.c_void_p)
+    for n_rcv, L in [(32, 127 * 4096 + 1), (8, 511 * 4096 + 1), (1, 1 << 26)]:
+        nc = -(-L // 4096)
+        assert n_rcv * 8 * (nc * 128 + 48) > 4 << 20
+        assert lib.rt_room_params_noalloc(p, n_rcv, L, 48000.0, p, None) == -3
+        assert b"scratch" in lib.rt_last_error()
+    assert lib.rt_room_params_noalloc(None, 1, 10, 48000.0, None, None) == -1
+    assert lib.rt_room_params_noalloc(p, -1, 10, 48000.0, p, None) == -1
+    assert lib.rt_room_params_noalloc(p, 0, 10, 48000.0, p, None) == 0
+
+
 def test_product_path_fails_loudly_without_library(tmp_path, monkeypatch):
     from paper_1811_05784_amd import _lib
     monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
