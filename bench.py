@@ -424,7 +424,7 @@ def run_rooms(args):
         "metric": "rays·bounces/s, 8 rooms x 8 pairs in one batched launch, IR + absorption gradient",
         "value": queries / (ms * 1e-3), "unit": "rays·bounces/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32 traversal, f64 shading/image sources/gradient, f32 MFMA FIR",
+        "vs_baseline": None, "dtype": "f32 traversal, f64 shading/image sources/gradient, f32 FFT FIR",
         "data": "synthetic (seeded watertight lattice rooms; Fibonacci rays per pair)",
         "config": {"workload": "8 rooms %s tris, 64 pairs x 2e5 rays, R=50, 1 s IR @48 kHz, 8 bands, K=4095, "
                                "grad over %d alpha" % ([sc.n_tri for sc in scenes], b.n_mat * 8),

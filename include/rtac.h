@@ -55,10 +55,11 @@ typedef struct {
  * into two daughter boxes down to leaves of one element; built once, in
  * O(M log M), before any ray is traced).
  *
- * The tree is a binary radix tree over the 63-bit Morton codes of the
- * triangle centroids (each split separates the elements of one Morton
- * prefix: a spatial median split cycling through the axes), collapsed into
- * a 4-wide tree for traversal.  Nearest hits do not depend on the tree.
+ * The tree is a binary radix tree over the 30-bit Morton codes (10 bits
+ * per axis) of the triangle centroids (each split separates the elements of
+ * one Morton prefix: a spatial median split cycling through the axes),
+ * collapsed into a 4-wide tree for traversal.  Nearest hits do not depend on
+ * the tree.
  *
  *   vtx       [n_vtx, 3] float   vertex coordinates (m)
  *   tri       [n_tri, 3] int32   vertex indices of each flat triangle
@@ -74,7 +75,8 @@ typedef struct {
  *   out_scene receives the scene handle (host pointer).
  * Errors: RT_EINVAL (index out of range, plane group not coplanar or of mixed
  * material, n_tri < 1), RT_EDEGENERATE (zero-area triangle, NaN/Inf vertex),
- * RT_ENOMEM, RT_EHIP.  Synchronises `stream` once.
+ * RT_ENOMEM, RT_EHIP.  Synchronises `stream` twice (validation and the
+ * reference count, then the tree facts).
  */
 int rt_build_tree(const float* vtx, int64_t n_vtx, const int32_t* tri, int64_t n_tri,
                   const int32_t* material, const int32_t* plane_id, const rt_build_params* params,
@@ -85,7 +87,9 @@ int rt_scene_destroy(rt_scene* scene);
 
 /* Host-side facts about a built scene: info_host[0] = n_tri, [1] = number of
  * materials (max material + 1), [2] = 4-wide tree nodes, [3] = tree depth,
- * [4] = leaf size; diag_host[0] = bounding-box diagonal D (m). */
+ * [4] = leaf size, [5] = references (triangle records of the tree, >= n_tri:
+ * thin triangles are cut into several); diag_host[0] = bounding-box
+ * diagonal D (m). */
 int rt_scene_info(const rt_scene* scene, int64_t* info_host, double* diag_host);
 
 /*
@@ -154,8 +158,7 @@ typedef struct {
     int32_t rounds;            /* 0 = default (1); kernel launches: once the ray pool is empty,
                                   a wavefront with few rays left hands them to the next launch  */
     int32_t spill_threshold;   /* 0 = default; most rays a wavefront may still hold to hand over */
-    int32_t waves_per_simd;    /* 0 = default (5 for rt_trace_rays, 4 for rt_trace_batch); register
-                                  budget of the trace kernel: 4, 5, 6, 8                         */
+    int32_t waves_per_simd;    /* 0 = default (4); register budget of the trace kernel: 4, 5, 6, 8 */
     void* kernel_event_start;  /* NULL or a hipEvent_t: recorded on `stream` just before the first
                                   traversal-kernel launch (after ray ordering and output fill)  */
     void* kernel_event_stop;   /* NULL or a hipEvent_t: recorded just after the last one        */
@@ -175,6 +178,10 @@ typedef struct {
                                   wavefront left with a single query in flight searches it with
                                   all 64 lanes, breadth first (two queries: 32 lanes each; same
                                   nearest hit)                                                  */
+    const int32_t* record_rows; /* NULL: with record_states, ray i writes row i of `states`; else
+                                  device int32[n_rays] (global ray ids in a batch): ray i writes
+                                  row record_rows[i] (< 0: not recorded), so a few rays of a large
+                                  launch can be recorded without changing the launch            */
 } rt_trace_params;
 
 /*
@@ -184,7 +191,10 @@ typedef struct {
  *   - nearest hit: minimal delta > 0 of o + delta u over the triangles with
  *     0 <= lambda, mu and lambda + mu <= 1, skipping the plane of the previous
  *     reflection; exact FP32 ties go to the lowest triangle id (watertight
- *     FP32 ray/triangle test, 4-wide tree traversal);
+ *     FP32 ray/triangle test, 4-wide tree traversal; a box is culled only
+ *     when its FP32 entry distance exceeds the best hit by more than 2^-20
+ *     relative, so the rule holds whatever the search order, except for
+ *     near-grazing hits whose FP32 distance is off by more than 13 roundings);
  *   - detection: receiver m is crossed when the segment [0, delta_hit]
  *     (unbounded on escape) comes within its radius of its centre (closed
  *     ball, FP64; the sphere is transparent);
@@ -210,6 +220,9 @@ typedef struct {
  *   states      [n_rays, R+2, 8] float or NULL   when record_states: input state
  *                                           (o, u, L, last plane as int bits) of each
  *                                           segment, and after the last reflection
+ *                                           (rows as selected by record_rows)
+ * The travelled length is carried in FP64 from segment to segment (it is
+ * rounded to FP32 only where it is recorded).
  * The counters are overwritten (not accumulated).
  */
 int rt_trace_rays(const rt_scene* scene, const float* src_host, const float* origins, const float* dirs,
@@ -309,9 +322,10 @@ int rt_batch_info(const rt_batch* batch, int64_t* info_host);
 
 /* One persistent launch over every ray of every job.  rcv [total_rcv, 4];
  * hit_seq [total_rays, R+1]; det rows are (global ray, k, global receiver);
- * counters as in rt_trace_rays.  record_states is not supported. */
+ * counters as in rt_trace_rays; states as in rt_trace_rays, indexed by global
+ * ray id (or by record_rows), NULL unless record_states. */
 int rt_trace_batch(rt_batch* batch, const float* rcv, const rt_trace_params* params, int32_t* hit_seq, int32_t* det,
-                   int64_t det_cap, int64_t* counters, void* stream);
+                   int64_t det_cap, int64_t* counters, float* states, void* stream);
 
 /* Image sources of all jobs: keys start with the global receiver row; the
  * position mirrors the job's source in its scene's planes. */

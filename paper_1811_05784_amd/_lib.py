@@ -27,7 +27,7 @@ class TraceParams(ctypes.Structure):
                 ("keep_order", I32), ("stats", P), ("rounds", I32), ("spill_threshold", I32),
                 ("waves_per_simd", I32), ("kernel_event_start", P),
                 ("kernel_event_stop", P), ("suspend_after", I32), ("min_beam_rays", I32),
-                ("xcd_pools", I32), ("coop_queries", I32)]
+                ("xcd_pools", I32), ("coop_queries", I32), ("record_rows", P)]
 
 
 class Job(ctypes.Structure):
@@ -52,7 +52,7 @@ SIGNATURES = {
     "rt_batch_create": (ctypes.c_int, [P, I32, P, I32, P, ctypes.POINTER(P)]),
     "rt_batch_destroy": (ctypes.c_int, [P]),
     "rt_batch_info": (ctypes.c_int, [P, P]),
-    "rt_trace_batch": (ctypes.c_int, [P, P, ctypes.POINTER(TraceParams), P, P, I64, P, P]),
+    "rt_trace_batch": (ctypes.c_int, [P, P, ctypes.POINTER(TraceParams), P, P, I64, P, P, P]),
     "rt_collect_batch": (ctypes.c_int, [P, P, P, I32, P, I64, P, P, P, P, P, I64, P, P]),
     "rt_assemble_batch": (ctypes.c_int, [P, P, P, P, P, I64, I32, P, P, F32, F32, I64, P, I32, P, P, P, P, P]),
     "rt_adjoint_batch": (ctypes.c_int, [P, P, P, P, P, I64, I32, P, P, F32, F32, I64, P, P, P]),

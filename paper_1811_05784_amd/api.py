@@ -64,10 +64,10 @@ class Scene:
             check(lib.rt_build_tree(_ptr(self.vtx), self.vtx.shape[0], _ptr(self.tri), self.tri.shape[0],
                                     _ptr(self.material), _ptr(self.plane_id), ctypes.byref(prm),
                                     _stream(self.device), ctypes.byref(self._h)), "rt_build_tree")
-        info = (ctypes.c_int64 * 5)()
+        info = (ctypes.c_int64 * 6)()
         diag = (ctypes.c_double * 1)()
         check(lib.rt_scene_info(self._h, info, diag), "rt_scene_info")
-        self.n_tri, self.n_mat, self.n_nodes, self.depth, self.leaf_size = [int(v) for v in info]
+        self.n_tri, self.n_mat, self.n_nodes, self.depth, self.leaf_size, self.n_ref = [int(v) for v in info]
         self.diag = float(diag[0])
 
     @classmethod
@@ -140,9 +140,12 @@ def trace_rays(scene: Scene, dirs: torch.Tensor, rcv, max_reflections: int, src=
                check_errors: bool = True, keep_order: bool = False,
                stats: Optional[torch.Tensor] = None, rounds: int = 0, spill_threshold: int = 0,
                waves_per_simd: int = 0, kernel_events=None, suspend_after: int = 0,
-               min_beam_rays: int = 0, xcd_pools: int = 0, coop_queries: int = 0) -> TraceResult:
+               min_beam_rays: int = 0, xcd_pools: int = 0, coop_queries: int = 0,
+               record_rows=None) -> TraceResult:
     """rt_trace_rays.  With check_capacity the call synchronises, and re-runs
     with a larger detection buffer if the first one overflowed.
+    record_rows: with record_states, an int32 [n] map ray -> row of `states`
+    (-1: not recorded); states then has max(record_rows) + 1 rows.
     min_beam_rays: n >= 1 stops each ray at the eq. 13 range (r/2) sqrt(N/n)
     of the largest receiver radius r and the N rays of the call.
     kernel_events: optional (start, stop) torch.cuda.Event pair (timing
@@ -157,6 +160,10 @@ def trace_rays(scene: Scene, dirs: torch.Tensor, rcv, max_reflections: int, src=
     spl = None if start_plane is None else _to_dev(start_plane, torch.int32, dev)
     sln = None if start_len is None else _to_dev(start_len, torch.float32, dev)
     src_h = _host_f32(src if src is not None else [0, 0, 0], 3)
+    rrows = None if record_rows is None else _to_dev(record_rows, torch.int32, dev)
+    if rrows is not None:
+        assert rrows.shape == (n,)
+    n_rec = n if rrows is None else (int(rrows.max().item()) + 1 if n else 0)
     if det_cap is None:
         det_cap = max(4 * n, 1024)
     if out is None:
@@ -164,13 +171,13 @@ def trace_rays(scene: Scene, dirs: torch.Tensor, rcv, max_reflections: int, src=
             hit_seq=torch.empty((n, R1), dtype=torch.int32, device=dev),
             det=torch.empty((det_cap, 3), dtype=torch.int32, device=dev),
             counters=torch.zeros(4, dtype=torch.int64, device=dev),
-            states=torch.full((n, R1 + 1, 8), float("nan"), dtype=torch.float32, device=dev) if record_states
-            else None,
+            states=torch.full((max(n_rec, 0), R1 + 1, 8), float("nan"), dtype=torch.float32, device=dev)
+            if record_states else None,
             max_reflections=max_reflections)
     prm = TraceParams(int(max_reflections), float(max_path_length), int(bool(record_states)), int(fetch_threshold),
                       int(shade_threshold), int(blocks_per_cu), int(bool(keep_order)), _ptr(stats),
                       int(rounds), int(spill_threshold), int(waves_per_simd), *_event_ptrs(kernel_events),
-                      int(suspend_after), int(min_beam_rays), int(xcd_pools), int(coop_queries))
+                      int(suspend_after), int(min_beam_rays), int(xcd_pools), int(coop_queries), _ptr(rrows))
     with torch.cuda.device(dev):
         check(lib.rt_trace_rays(scene.handle, src_h, _ptr(org), _ptr(dirs), _ptr(spl), _ptr(sln), n, _ptr(rcv_t),
                                 rcv_t.shape[0], ctypes.byref(prm), _ptr(out.hit_seq), _ptr(out.det),
@@ -187,7 +194,7 @@ def trace_rays(scene: Scene, dirs: torch.Tensor, rcv, max_reflections: int, src=
                               keep_order=keep_order, stats=stats, rounds=rounds,
                               spill_threshold=spill_threshold, waves_per_simd=waves_per_simd,
                               suspend_after=suspend_after, min_beam_rays=min_beam_rays, xcd_pools=xcd_pools,
-                              coop_queries=coop_queries)
+                              coop_queries=coop_queries, record_rows=rrows)
     return out
 
 
@@ -391,33 +398,43 @@ class Batch:
 
 
 def trace_batch(b: Batch, max_reflections: int, det_cap: Optional[int] = None, out: Optional[TraceResult] = None,
-                check_capacity: bool = True, min_beam_rays: int = 0, **tune) -> TraceResult:
+                check_capacity: bool = True, min_beam_rays: int = 0, record_rows=None, **tune) -> TraceResult:
     """rt_trace_batch.  min_beam_rays as in trace_rays, per job (its rays and
-    its receivers)."""
+    its receivers).  record_rows: int32 [total rays] map global ray -> row of
+    the recorded states (-1: not recorded), or None (no states)."""
     lib = _lib.load()
     dev = b.device
     R1 = max_reflections + 1
+    rrows = None if record_rows is None else _to_dev(record_rows, torch.int32, dev)
     if det_cap is None:
         det_cap = max(2 * b.n_rays, 1024)
     if out is None:
+        states = None
+        if rrows is not None:
+            assert rrows.shape == (b.n_rays,)
+            states = torch.full((int(rrows.max().item()) + 1, R1 + 1, 8), float("nan"), dtype=torch.float32,
+                                device=dev)
         out = TraceResult(hit_seq=torch.empty((b.n_rays, R1), dtype=torch.int32, device=dev),
                           det=torch.empty((det_cap, 3), dtype=torch.int32, device=dev),
-                          counters=torch.zeros(4, dtype=torch.int64, device=dev), states=None,
+                          counters=torch.zeros(4, dtype=torch.int64, device=dev), states=states,
                           max_reflections=max_reflections)
-    prm = TraceParams(int(max_reflections), 0.0, 0, int(tune.get("fetch_threshold", 0)),
+    prm = TraceParams(int(max_reflections), 0.0, int(rrows is not None), int(tune.get("fetch_threshold", 0)),
                       int(tune.get("shade_threshold", 0)), int(tune.get("blocks_per_cu", 0)), 1, None,
                       int(tune.get("rounds", 0)), int(tune.get("spill_threshold", 0)),
                       int(tune.get("waves_per_simd", 0)), *_event_ptrs(tune.get("kernel_events")),
-                      int(tune.get("suspend_after", 0)), int(min_beam_rays), int(tune.get("xcd_pools", 0)), 0)
+                      int(tune.get("suspend_after", 0)), int(min_beam_rays), int(tune.get("xcd_pools", 0)), 0,
+                      _ptr(rrows))
     with torch.cuda.device(dev):
         check(lib.rt_trace_batch(b.handle, _ptr(b.rcv), ctypes.byref(prm), _ptr(out.hit_seq), _ptr(out.det),
-                                 out.det.shape[0], _ptr(out.counters), _stream(dev)), "rt_trace_batch")
+                                 out.det.shape[0], _ptr(out.counters), _ptr(out.states), _stream(dev)),
+              "rt_trace_batch")
     if check_capacity:
         c = out.counters.cpu()
         if int(c[3]) != 0:
             raise _lib.RtError("rt_trace_batch: device error word %d" % int(c[3]))
         if int(c[0]) > out.det.shape[0]:
-            return trace_batch(b, max_reflections, det_cap=int(c[0]) + 1024, min_beam_rays=min_beam_rays, **tune)
+            return trace_batch(b, max_reflections, det_cap=int(c[0]) + 1024, min_beam_rays=min_beam_rays,
+                               record_rows=rrows, **tune)
     return out
 
 

@@ -147,6 +147,7 @@ extern "C" int rt_scene_info(const rt_scene* s, int64_t* info, double* diag) {
         info[2] = s->n_nodes;
         info[3] = s->depth;
         info[4] = s->leaf_size;
+        info[5] = s->n_ref;
     }
     if (diag) diag[0] = s->diag;
     return RT_OK;

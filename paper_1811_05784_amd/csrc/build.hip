@@ -9,8 +9,18 @@
 // that traversal sees a 4-wide tree with 128-byte nodes (one cache line per
 // node on gfx950).  Subtrees of at most `leaf_size` triangles become leaves.
 //
-// Everything per triangle that traversal and shading need is re-laid out in
-// tree order (48 B per triangle) so a leaf is a contiguous range.
+// Before the tree is built, thin triangles are cut into references (early
+// split clipping, Ernst and Greiner 2007): a triangle whose bounding box has
+// more than kEscTau times the surface of the triangle itself is cut into k
+// slabs along the longest side of its box, and each reference carries the
+// box of its piece only.  Fans of sliver triangles (a ring mesh around its
+// centre) otherwise give hundreds of overlapping boxes around one point, and
+// a query through that point tests every one of them.  A triangle may thus
+// sit in several leaves; nearest hits do not change (the same triangle is
+// tested again at the same distance).
+//
+// Everything per reference that traversal and shading need is re-laid out in
+// tree order (48 B per reference) so a leaf is a contiguous range.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -250,9 +260,11 @@ __device__ inline uint64_t spread21(uint64_t x) {
     return x;
 }
 
-// 30-bit Morton code of the centroid, quantised to 2^10 cells per axis on a
-// cube spanning the centroid box (equal cells on every axis; equal codes are
-// ordered by triangle index).  Ten bits per axis sort in four 8-bit passes;
+// 30-bit Morton code of the centre of a reference's box, quantised to 2^10
+// cells per axis on a cube spanning the scene box (equal cells on every axis;
+// equal codes are ordered by reference index).  Box centres split sliver
+// triangles' boxes better than triangle centroids do (fewer node visits per
+// query on the theater and the jittered box).  Ten bits per axis sort in four 8-bit passes;
 // on the workloads here (436k-triangle theater, 2^20-triangle tetrahedron,
 // lattice rooms up to 177k triangles) the trees trace as fast as with 16
 // bits per axis and six passes.  A small dense object in a large empty box
@@ -260,23 +272,177 @@ __device__ inline uint64_t spread21(uint64_t x) {
 // but gives looser boxes.
 constexpr int kMortonBits = 10;
 constexpr float kMortonMax = (float)((1 << kMortonBits) - 1);
-__global__ void k_morton(const float* __restrict__ centroid, int64_t nt, const uint32_t* __restrict__ bounds,
+__global__ void k_morton(const float* __restrict__ ref_box, int64_t nr, const uint32_t* __restrict__ bounds,
                          uint64_t* __restrict__ code) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nt) return;
+    if (i >= nr) return;
     float lo[3], ext = 0.f;
     for (int c = 0; c < 3; c++) {
-        lo[c] = funord(bounds[6 + c]);
-        ext = fmaxf(ext, funord(bounds[9 + c]) - lo[c]);
+        lo[c] = funord(bounds[c]);
+        ext = fmaxf(ext, funord(bounds[3 + c]) - lo[c]);
     }
     const float scale = ext > 0.f ? kMortonMax / ext : 0.f;
     uint64_t q[3];
     for (int c = 0; c < 3; c++) {
-        float f = (centroid[3 * i + c] - lo[c]) * scale;
+        const float centre = 0.5f * (ref_box[6 * i + c] + ref_box[6 * i + 3 + c]);
+        float f = (centre - lo[c]) * scale;
         f = fminf(fmaxf(f, 0.f), kMortonMax);
         q[c] = (uint64_t)f;
     }
     code[i] = (spread21(q[0]) << 2) | (spread21(q[1]) << 1) | spread21(q[2]);
+}
+
+// ---------------------------------------------------------------------------
+// early split clipping
+// ---------------------------------------------------------------------------
+constexpr double kEscTau = 8.0;   // box surface / (2 x triangle area) above which a triangle is cut
+constexpr int kEscMax = 64;       // most references per triangle
+
+// The triangle's vertices in FP64, or false when its indices or coordinates
+// are invalid (reported by the validation; it then gets one reference).
+__device__ inline bool esc_vertices(const float* __restrict__ vtx, int64_t nv, const int3* __restrict__ tri,
+                                    int64_t t, double (&p)[3][3]) {
+    const int3 v = tri[t];
+    if (v.x < 0 || v.y < 0 || v.z < 0 || v.x >= nv || v.y >= nv || v.z >= nv) return false;
+    const int idx[3] = {v.x, v.y, v.z};
+    for (int a = 0; a < 3; a++)
+        for (int c = 0; c < 3; c++) {
+            const float f = vtx[3 * (int64_t)idx[a] + c];
+            if (!isfinite(f)) return false;
+            p[a][c] = (double)f;
+        }
+    return true;
+}
+
+// Number of slabs for the triangle and the axis they cut (its box's longest).
+__device__ inline int esc_slabs(const double (&p)[3][3], int& ax, double& lo, double& ext) {
+    double e[3], l[3];
+    for (int c = 0; c < 3; c++) {
+        l[c] = fmin(p[0][c], fmin(p[1][c], p[2][c]));
+        e[c] = fmax(p[0][c], fmax(p[1][c], p[2][c])) - l[c];
+    }
+    ax = e[0] >= e[1] ? (e[0] >= e[2] ? 0 : 2) : (e[1] >= e[2] ? 1 : 2);
+    lo = l[ax];
+    ext = e[ax];
+    double a[3], b[3];
+    for (int c = 0; c < 3; c++) {
+        a[c] = p[1][c] - p[0][c];
+        b[c] = p[2][c] - p[0][c];
+    }
+    const double nx = a[1] * b[2] - a[2] * b[1], ny = a[2] * b[0] - a[0] * b[2], nz = a[0] * b[1] - a[1] * b[0];
+    const double two_area = sqrt(nx * nx + ny * ny + nz * nz);
+    const double box_area = 2.0 * (e[0] * e[1] + e[1] * e[2] + e[0] * e[2]);
+    if (!(two_area > 0.0) || !(ext > 0.0) || box_area <= kEscTau * two_area) return 1;
+    const double k = ceil(box_area / (kEscTau * two_area));
+    return k >= (double)kEscMax ? kEscMax : (int)k;
+}
+
+// One side of an axis-aligned plane (Sutherland-Hodgman): the vertices of
+// polygon `in` with coordinate `ax` >= v (keep_lo false) or <= v (true), at
+// most `cap` of them.  The decisions compare exact coordinates (original
+// vertices, or v itself for points on an earlier cut parallel to this one),
+// so a convex input gains at most one vertex.
+__device__ inline int esc_clip(const double (*in)[3], int n, int ax, double v, bool keep_lo, double (*out)[3],
+                               int cap) {
+    int m = 0;
+    for (int i = 0; i < n; i++) {
+        const double* a = in[i];
+        const double* b = in[i + 1 < n ? i + 1 : 0];
+        const bool ia = keep_lo ? a[ax] <= v : a[ax] >= v;
+        const bool ib = keep_lo ? b[ax] <= v : b[ax] >= v;
+        if (ia && m < cap) {
+            for (int c = 0; c < 3; c++) out[m][c] = a[c];
+            m++;
+        }
+        if (ia != ib && m < cap) {
+            const double t = (v - a[ax]) / (b[ax] - a[ax]);
+            for (int c = 0; c < 3; c++) out[m][c] = a[c] + t * (b[c] - a[c]);
+            out[m][ax] = v;
+            m++;
+        }
+    }
+    return m;
+}
+
+__device__ inline float round_down(double x) {
+    float f = (float)x;
+    if ((double)f > x) f = nextafterf(f, -INFINITY);
+    return f;
+}
+__device__ inline float round_up(double x) {
+    float f = (float)x;
+    if ((double)f < x) f = nextafterf(f, INFINITY);
+    return f;
+}
+
+__global__ void k_esc_count(const float* __restrict__ vtx, int64_t nv, const int3* __restrict__ tri, int64_t nt,
+                            uint32_t* __restrict__ cnt) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nt) return;
+    double p[3][3];
+    int ax;
+    double lo, ext;
+    cnt[t] = esc_vertices(vtx, nv, tri, t, p) ? (uint32_t)esc_slabs(p, ax, lo, ext) : 1u;
+}
+
+// References of triangle t at [off[t], off[t+1]): an unsplit triangle keeps
+// its FP32 box; piece i of k is the triangle clipped to slab i of its box's
+// longest side (FP64), its box rounded outward to FP32 and widened by
+// `margin` (8 units in the last place of the scene's extent: the FP32
+// watertight test decides hits within a few such units of an edge, and a
+// cut adds box faces that the triangle's own box did not have).
+__global__ void k_esc_emit(const float* __restrict__ vtx, int64_t nv, const int3* __restrict__ tri, int64_t nt,
+                           const uint32_t* __restrict__ off, const uint32_t* __restrict__ bounds,
+                           float* __restrict__ ref_box, uint32_t* __restrict__ ref_tri) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nt) return;
+    const int64_t r0 = off[t];
+    const int k = (int)(off[t + 1] - off[t]);
+    double p[3][3];
+    if (!esc_vertices(vtx, nv, tri, t, p)) {
+        for (int c = 0; c < 6; c++) ref_box[6 * r0 + c] = 0.f;
+        ref_tri[r0] = (uint32_t)t;
+        return;
+    }
+    if (k == 1) {
+        for (int c = 0; c < 3; c++) {
+            ref_box[6 * r0 + c] = (float)fmin(p[0][c], fmin(p[1][c], p[2][c]));
+            ref_box[6 * r0 + 3 + c] = (float)fmax(p[0][c], fmax(p[1][c], p[2][c]));
+        }
+        ref_tri[r0] = (uint32_t)t;
+        return;
+    }
+    int ax;
+    double lo, ext;
+    esc_slabs(p, ax, lo, ext);
+    double scene = 0.0;
+    for (int c = 0; c < 3; c++) scene = fmax(scene, (double)funord(bounds[3 + c]) - (double)funord(bounds[c]));
+    const double margin = scene * 0x1p-20;
+    for (int i = 0; i < k; i++) {
+        double q1[4][3], q2[5][3];
+        int m = 3;
+        const double(*cur)[3] = p;
+        if (i > 0) {
+            m = esc_clip(cur, m, ax, lo + ext * (double)i / (double)k, false, q1, 4);
+            cur = q1;
+        }
+        if (i + 1 < k) {
+            m = esc_clip(cur, m, ax, lo + ext * (double)(i + 1) / (double)k, true, q2, 5);
+            cur = q2;
+        }
+        double bl[3] = {INFINITY, INFINITY, INFINITY}, bh[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int j = 0; j < m; j++)
+            for (int c = 0; c < 3; c++) {
+                bl[c] = fmin(bl[c], cur[j][c]);
+                bh[c] = fmax(bh[c], cur[j][c]);
+            }
+        const int64_t r = r0 + i;
+        for (int c = 0; c < 3; c++) {
+            ref_box[6 * r + c] = m > 0 ? round_down(bl[c] - margin) : INFINITY;
+            ref_box[6 * r + 3 + c] = m > 0 ? round_up(bh[c] + margin) : -INFINITY;
+        }
+        ref_tri[r] = (uint32_t)t;
+    }
 }
 
 __device__ inline int prefix_len(const uint64_t* __restrict__ k, int64_t n, int64_t i, int64_t j) {
@@ -576,12 +742,13 @@ __global__ void k_single_leaf_root(const uint32_t* __restrict__ bounds, int32_t 
     nodes[0] = nd;
 }
 
-__global__ void k_tri_records(const float* __restrict__ vtx, int64_t nv, const int3* __restrict__ tri, int64_t nt,
+__global__ void k_tri_records(const float* __restrict__ vtx, int64_t nv, const int3* __restrict__ tri, int64_t nr,
                               const int32_t* __restrict__ material, const int32_t* __restrict__ tri_plane,
-                              const uint32_t* __restrict__ order, float4* __restrict__ rec) {
+                              const uint32_t* __restrict__ order, const uint32_t* __restrict__ ref_tri,
+                              float4* __restrict__ rec) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= nt) return;
-    const uint32_t t = order[j];
+    if (j >= nr) return;
+    const uint32_t t = ref_tri[order[j]];
     const int3 v = tri[t];
     if (v.x < 0 || v.y < 0 || v.z < 0 || v.x >= nv || v.y >= nv || v.z >= nv) return;   // reported already
     const int idx[3] = {v.x, v.y, v.z};
@@ -649,8 +816,6 @@ extern "C" int rt_build_tree(const float* vtx, int64_t n_vtx, const int32_t* tri
     RT_CHECK(leaf >= 1 && leaf <= kMaxLeaf, RT_EINVAL, "rt_build_tree: leaf_size must be in [1, %d]", kMaxLeaf);
     hipStream_t st = (hipStream_t)stream;
     const int64_t nt = n_tri;
-    const int64_t n_in = nt - 1;
-    const bool single = n_in == 0 || nt <= leaf;
     TmpBufs tmp;
     rt_scene* s = new rt_scene();
     auto fail = [&](int code) {
@@ -661,26 +826,20 @@ extern "C" int rt_build_tree(const float* vtx, int64_t n_vtx, const int32_t* tri
     s->n_tri = nt;
     s->n_vtx = n_vtx;
     s->leaf_size = leaf;
-    // upper bound of 4-wide nodes: inner binary nodes (one per adjacent pair)
-    const int64_t node_cap = single ? 1 : n_in;
     s->plane_n = (double*)dcache_alloc(sizeof(double) * 3 * nt);
     s->plane_p = (double*)dcache_alloc(sizeof(double) * 3 * nt);
     s->plane_mat = (int32_t*)dcache_alloc(sizeof(int32_t) * nt);
     s->tri_plane = (int32_t*)dcache_alloc(sizeof(int32_t) * nt);
-    s->tri_rec = (float4*)dcache_alloc(sizeof(float4) * 3 * nt);
-    s->nodes = (Node4*)dcache_alloc(sizeof(Node4) * node_cap);
     float* tri_box = tmp.get<float>(6 * nt);
     float* cen = tmp.get<float>(3 * nt);
     uint32_t* bounds = tmp.get<uint32_t>(12);
     uint32_t* info = tmp.get<uint32_t>(4);
     uint32_t* prep_part = tmp.get<uint32_t>(14 * (int64_t)blocks(nt));
     int32_t* prep = tmp.get<int32_t>(nt);
-    uint64_t* codes0 = tmp.get<uint64_t>(nt);
-    uint64_t* codes1 = tmp.get<uint64_t>(nt);
-    uint32_t* ord0 = tmp.get<uint32_t>(nt);
-    uint32_t* ord1 = tmp.get<uint32_t>(nt);
-    if (!s->plane_n || !s->plane_p || !s->plane_mat || !s->tri_plane || !s->tri_rec || !s->nodes || !tri_box ||
-        !cen || !bounds || !info || !prep_part || !prep || !codes0 || !codes1 || !ord0 || !ord1) {
+    uint32_t* ref_cnt = tmp.get<uint32_t>(nt);
+    uint32_t* ref_off = tmp.get<uint32_t>(nt + 1);
+    if (!s->plane_n || !s->plane_p || !s->plane_mat || !s->tri_plane || !tri_box || !cen || !bounds || !info ||
+        !prep_part || !prep || !ref_cnt || !ref_off) {
         set_error("rt_build_tree: out of device memory");
         return fail(RT_ENOMEM);
     }
@@ -693,22 +852,58 @@ extern "C" int rt_build_tree(const float* vtx, int64_t n_vtx, const int32_t* tri
                        s->plane_n, s->plane_p, s->plane_mat);
     hipLaunchKernelGGL(k_coplanar, dim3(blocks(nt)), dim3(256), 0, st, vtx, n_vtx, (const int3*)tri, nt, material,
                        plane_id, s->plane_n, s->plane_p, s->plane_mat, bounds, s->tri_plane, info);
-    hipLaunchKernelGGL(k_morton, dim3(blocks(nt)), dim3(256), 0, st, cen, nt, bounds, codes0);
+    // references: slab counts per triangle, their offsets, then the total
+    hipLaunchKernelGGL(k_esc_count, dim3(blocks(nt)), dim3(256), 0, st, vtx, n_vtx, (const int3*)tri, nt, ref_cnt);
+    int rc = exclusive_scan_u32(s->ws, ref_cnt, ref_off, nt, nullptr, st);
+    if (rc) return fail(rc);
+    RT_HIP(hipGetLastError());
+    uint32_t h_info[4], h_bounds[12], h_nr = 0;
+    RT_HIP(hipMemcpyAsync(h_info, info, sizeof(h_info), hipMemcpyDeviceToHost, st));
+    RT_HIP(hipMemcpyAsync(&h_nr, ref_off + nt, sizeof(h_nr), hipMemcpyDeviceToHost, st));
+    RT_HIP(hipStreamSynchronize(st));
+    if (h_info[0]) {
+        set_error("rt_build_tree: %s", err_text(h_info[0]));
+        const bool degen = (h_info[0] & (kErrNonFinite | kErrZeroArea)) &&
+                           !(h_info[0] & (kErrIndex | kErrPlaneRange | kErrMaterial));
+        return fail(degen ? RT_EDEGENERATE : RT_EINVAL);
+    }
+    const int64_t nr = h_nr;
+    RT_CHECK(nr >= nt && nr < kMaxTris, RT_EINVAL, "rt_build_tree: %lld references (at most 2^27)", (long long)nr);
+    const int64_t n_in = nr - 1;
+    const bool single = n_in == 0 || nr <= leaf;
+    // upper bound of 4-wide nodes: inner binary nodes (one per adjacent pair)
+    const int64_t node_cap = single ? 1 : n_in;
+    s->n_ref = nr;
+    s->tri_rec = (float4*)dcache_alloc(sizeof(float4) * 3 * nr);
+    s->nodes = (Node4*)dcache_alloc(sizeof(Node4) * node_cap);
+    float* ref_box = tmp.get<float>(6 * nr);
+    uint32_t* ref_tri = tmp.get<uint32_t>(nr);
+    uint64_t* codes0 = tmp.get<uint64_t>(nr);
+    uint64_t* codes1 = tmp.get<uint64_t>(nr);
+    uint32_t* ord0 = tmp.get<uint32_t>(nr);
+    uint32_t* ord1 = tmp.get<uint32_t>(nr);
+    if (!s->tri_rec || !s->nodes || !ref_box || !ref_tri || !codes0 || !codes1 || !ord0 || !ord1) {
+        set_error("rt_build_tree: out of device memory");
+        return fail(RT_ENOMEM);
+    }
+    hipLaunchKernelGGL(k_esc_emit, dim3(blocks(nt)), dim3(256), 0, st, vtx, n_vtx, (const int3*)tri, nt, ref_off,
+                       bounds, ref_box, ref_tri);
+    hipLaunchKernelGGL(k_morton, dim3(blocks(nr)), dim3(256), 0, st, ref_box, nr, bounds, codes0);
     int which = 0;
-    int rc = radix_sort_pairs(s->ws, codes0, ord0, codes1, ord1, nt, nullptr, 0, 3 * kMortonBits, st, &which, true);
+    rc = radix_sort_pairs(s->ws, codes0, ord0, codes1, ord1, nr, nullptr, 0, 3 * kMortonBits, st, &which, true);
     if (rc) return fail(rc);
     uint64_t* codes = which ? codes1 : codes0;
     uint32_t* order = which ? ord1 : ord0;
     uint32_t* n4_dev = info + 3;
     if (single) {
-        hipLaunchKernelGGL(k_single_leaf_root, dim3(1), dim3(1), 0, st, bounds, (int32_t)nt, s->nodes);
+        hipLaunchKernelGGL(k_single_leaf_root, dim3(1), dim3(1), 0, st, bounds, (int32_t)nr, s->nodes);
     } else {
         int32_t* left = tmp.get<int32_t>(n_in);
         int32_t* right = tmp.get<int32_t>(n_in);
         int32_t* first = tmp.get<int32_t>(n_in);
         int32_t* last = tmp.get<int32_t>(n_in);
         int32_t* par_in = tmp.get<int32_t>(n_in);
-        int32_t* par_leaf = tmp.get<int32_t>(nt);
+        int32_t* par_leaf = tmp.get<int32_t>(nr);
         int32_t* depth = tmp.get<int32_t>(n_in);
         float* box_in = tmp.get<float>(6 * n_in);
         uint32_t* flag = tmp.get<uint32_t>(n_in);
@@ -719,13 +914,13 @@ extern "C" int rt_build_tree(const float* vtx, int64_t n_vtx, const int32_t* tri
             set_error("rt_build_tree: out of device memory");
             return fail(RT_ENOMEM);
         }
-        hipLaunchKernelGGL(k_radix_tree, dim3(blocks(n_in)), dim3(256), 0, st, codes, nt, left, right, first, last,
+        hipLaunchKernelGGL(k_radix_tree, dim3(blocks(n_in)), dim3(256), 0, st, codes, nr, left, right, first, last,
                            par_in, par_leaf);
-        // segment tree over the ordered triangle boxes, then one range query per inner node
+        // segment tree over the ordered reference boxes, then one range query per inner node
         SegLevels seg;
         seg.n_levels = 0;
         int64_t total = 0;
-        for (int64_t w = nt;; w = (w + 1) / 2) {
+        for (int64_t w = nr;; w = (w + 1) / 2) {
             total += w;
             seg.n_levels++;
             if (w == 1 || seg.n_levels == 32) break;
@@ -742,12 +937,12 @@ extern "C" int rt_build_tree(const float* vtx, int64_t n_vtx, const int32_t* tri
             for (int lv = 0; lv < seg.n_levels; lv++) {
                 segw.lvl[lv] = segbuf + off;
                 seg.lvl[lv] = segbuf + off;
-                off += (nt + ((int64_t)1 << lv) - 1) >> lv;
+                off += (nr + ((int64_t)1 << lv) - 1) >> lv;
             }
-            hipLaunchKernelGGL(k_seg_block, dim3((unsigned)((nt + kSegBlockLeaves - 1) / kSegBlockLeaves)), dim3(1024),
-                               0, st, nt, order, tri_box, segw);
+            hipLaunchKernelGGL(k_seg_block, dim3((unsigned)((nr + kSegBlockLeaves - 1) / kSegBlockLeaves)), dim3(1024),
+                               0, st, nr, order, ref_box, segw);
             if (seg.n_levels > kSegBlockLevels + 1)
-                hipLaunchKernelGGL(k_seg_top, dim3(1), dim3(1024), 0, st, nt, segw);
+                hipLaunchKernelGGL(k_seg_top, dim3(1), dim3(1024), 0, st, nr, segw);
         }
         hipLaunchKernelGGL(k_node_boxes, dim3(blocks(n_in)), dim3(256), 0, st, n_in, first, last, seg, box_in);
         hipLaunchKernelGGL(k_flag4, dim3(blocks(n_in)), dim3(256), 0, st, n_in, first, last, par_in, leaf, flag,
@@ -756,22 +951,15 @@ extern "C" int rt_build_tree(const float* vtx, int64_t n_vtx, const int32_t* tri
         if (rc) return fail(rc);
         hipLaunchKernelGGL(k_list4, dim3(blocks(n_in)), dim3(256), 0, st, n_in, flag, index, list4);
         hipLaunchKernelGGL(k_emit4, dim3(blocks(n_in)), dim3(256), 0, st, n_in, left, right, first, last, list4,
-                           index, depth, box_in, tri_box, order, leaf, s->nodes, info);
+                           index, depth, box_in, ref_box, order, leaf, s->nodes, info);
         hipLaunchKernelGGL(k_copy_u32, dim3(1), dim3(1), 0, st, index + n_in, n4_dev);
     }
-    hipLaunchKernelGGL(k_tri_records, dim3(blocks(nt)), dim3(256), 0, st, vtx, n_vtx, (const int3*)tri, nt, material,
-                       s->tri_plane, order, s->tri_rec);
+    hipLaunchKernelGGL(k_tri_records, dim3(blocks(nr)), dim3(256), 0, st, vtx, n_vtx, (const int3*)tri, nr, material,
+                       s->tri_plane, order, ref_tri, s->tri_rec);
     RT_HIP(hipGetLastError());
-    uint32_t h_info[4], h_bounds[12];
     RT_HIP(hipMemcpyAsync(h_info, info, sizeof(h_info), hipMemcpyDeviceToHost, st));
     RT_HIP(hipMemcpyAsync(h_bounds, bounds, sizeof(h_bounds), hipMemcpyDeviceToHost, st));
     RT_HIP(hipStreamSynchronize(st));
-    if (h_info[0]) {
-        set_error("rt_build_tree: %s", err_text(h_info[0]));
-        const bool degen = (h_info[0] & (kErrNonFinite | kErrZeroArea)) &&
-                           !(h_info[0] & (kErrIndex | kErrPlaneRange | kErrMaterial));
-        return fail(degen ? RT_EDEGENERATE : RT_EINVAL);
-    }
     s->n_mat = (int32_t)h_info[1] + 1;
     double d2 = 0;
     for (int c = 0; c < 3; c++) {

@@ -87,6 +87,8 @@ struct DevScene {
     int32_t n_tri;
     int32_t mat_off;   // first row of this scene's materials in a batch absorption table
     int32_t n_mat;
+    int32_t n_ref;     // triangle records (references) in tree order
+    int32_t pad;
 };
 
 struct DevJob {
@@ -146,6 +148,7 @@ struct rt_batch {
 struct rt_scene {
     int device = 0;
     int64_t n_tri = 0;
+    int64_t n_ref = 0;          // references (triangle records in tree order; >= n_tri)
     int64_t n_vtx = 0;
     int32_t n_mat = 0;
     int32_t leaf_size = 1;
@@ -155,7 +158,7 @@ struct rt_scene {
     float bounds[6] = {0, 0, 0, 0, 0, 0};
     // device arrays
     rtac::Node4* nodes = nullptr;   // [n_nodes]
-    float4* tri_rec = nullptr;      // [n_tri * 3] in tree (Morton) order:
+    float4* tri_rec = nullptr;      // [n_ref * 3] one record per reference, in tree (Morton) order:
                                     // (v0, plane id) (v1, triangle id) (v2, material) as int bits in w
     double* plane_n = nullptr;      // [n_tri * 3] unit normal per plane id (representative)
     double* plane_p = nullptr;      // [n_tri * 3] first vertex of the representative

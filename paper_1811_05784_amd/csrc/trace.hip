@@ -45,6 +45,17 @@ constexpr int kSpillChunk = 8;
 
 enum : int { kIdle = 0, kQuery = 1, kDone = 2 };
 
+// A box is skipped only when its FP32 entry distance exceeds the nearest hit
+// found so far by more than 16 units in the last place (at least 2^-20
+// relative).  Each slab distance (b - o) / u is within 3 FP32 roundings
+// (relative) of the exact one, which is never beyond the distance of a hit
+// inside the box; so whenever the watertight distance of that hit is within
+// 13 roundings of its exact value (all but near-grazing hits), a triangle
+// whose FP32 distance equals the best one is always tested, whatever the
+// search order, and exact ties go to the lowest triangle id.  t >= 0; +inf
+// stays +inf.  (An integer add, so a wave-uniform bound stays scalar.)
+__device__ inline float widen(float t) { return __uint_as_float(min(__float_as_uint(t) + 16u, 0x7F800000u)); }
+
 enum : unsigned long long { kErrStack = 1ull, kErrNode = 2ull, kErrSteps = 4ull, kErrQueue = 8ull };
 
 struct TraceArgs {
@@ -53,7 +64,7 @@ struct TraceArgs {
     const double* plane_n;
     const double* plane_p;
     int32_t n_nodes;
-    int32_t n_tri;
+    int32_t n_ref;                  // triangle records (leaf ranges index them)
     float src[3];
     const float* origins;
     const float* dirs;
@@ -65,6 +76,7 @@ struct TraceArgs {
     int32_t R;
     float max_len;
     int32_t record;
+    const int32_t* record_rows;     // NULL: ray i records into row i; else row record_rows[i] (< 0: none)
     int32_t* hit_seq;
     int32_t* det;
     int64_t det_cap;
@@ -98,7 +110,7 @@ struct TraceArgs {
     int32_t n_jobs;
 };
 
-// queued ray: (ray, k, last plane, -) (o.x, o.y, o.z, L) (u.x, u.y, u.z, -)
+// queued ray: (ray, k, last plane, -) (o.x, o.y, o.z, L low word) (u.x, u.y, u.z, L high word)
 constexpr int kQueueInts = 12;
 
 constexpr int kXcd = 8;             // accelerator complexes (own L2 each); workgroup b runs on b % 8
@@ -229,11 +241,163 @@ __device__ inline void cswap(float& ta, int32_t& ra, float& tb, int32_t& rb) {
     }
 }
 
+// Nearest hit of one query by a group of G lanes (G = 64: the whole
+// wavefront; 32: one half, lanes li = 0..31 from lane gbase), breadth first
+// over a frontier kept in the group's columns of the LDS stack area (refs in
+// slots 0..7, entry distances in slots 8..15: 8 G entries).  Each step every
+// lane of the group takes one frontier item, the most recent first: an inner
+// node is slab-tested and every child whose box is hit joins the frontier
+// (far children first, so the nearest are taken next); a leaf has its
+// triangles tested.  So a step makes one dependent memory access per lane.
+// The group keeps the nearest hit, (t, id) lexicographic: exact ties go to the
+// lowest triangle id and the result is the per-lane walk's.  bt, bid, bj come
+// in as the owner's best so far and leave as the group's result (the same in
+// every lane of the group).  Returns false when the frontier would overflow,
+// the step bound is reached or a reference is out of range (for either group
+// of a wavefront); the owner then walks the query from the root, bounded by
+// the best hit found so far.
+template <int G>
+__device__ inline bool coop_search(const Ray& q, int32_t qlp, float& bt, int32_t& bid, int32_t& bj, int32_t* base_col,
+                                   int li, int gbase, const Node4* nodes, const float4* tri, int32_t n_nodes,
+                                   int32_t n_tri, int32_t max_steps) {
+    constexpr int kCap = 8 * G;
+    int32_t* fref = base_col;
+    float* ft = reinterpret_cast<float*>(base_col + 8 * kBlock);
+    auto fat = [](int k) { return (k / G) * kBlock + (k % G); };
+    int nf = 1;
+    if (li == 0) {
+        fref[0] = 0;
+        ft[0] = 0.f;
+    }
+    bool ok = true;
+    int csteps = 0;
+    while (__ballot(nf > 0) != 0ull) {
+        if (++csteps > max_steps) {
+            ok = false;
+            break;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int take = nf < G ? nf : G;
+        const int base = nf - take;   // the most recent entries, deepest first
+        int32_t item = kEmpty;
+        float it = INFINITY;
+        if (li < take) {
+            item = fref[fat(base + li)];
+            it = ft[fat(base + li)];
+        }
+        nf = base;
+        float tn[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
+        int32_t rf[4] = {kEmpty, kEmpty, kEmpty, kEmpty};
+        float lt = bt;
+        int32_t lid = bid, lj = bj;
+        bool bad = item != kEmpty && item >= n_nodes;
+        const float tlim = widen(bt);
+        if (item != kEmpty && !bad && it <= tlim) {
+            if (item >= 0) {
+                const float4* np = reinterpret_cast<const float4*>(nodes + item);
+                const float4 lx = np[0], hx = np[1], ly = np[2], hy = np[3], lz = np[4], hz = np[5];
+                const int4 ch = reinterpret_cast<const int4*>(np)[6];
+#define RT_SLAB(S, LX, HX, LY, HY, LZ, HZ, CH)                                          \
+    {                                                                                    \
+        const float t0x = (LX - q.ox) * q.ix, t1x = (HX - q.ox) * q.ix;                  \
+        const float t0y = (LY - q.oy) * q.iy, t1y = (HY - q.oy) * q.iy;                  \
+        const float t0z = (LZ - q.oz) * q.iz, t1z = (HZ - q.oz) * q.iz;                  \
+        const float tmin = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)),               \
+                                 fmaxf(fminf(t0z, t1z), 0.f));                           \
+        float tmax = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z));    \
+        tmax *= 1.00000036f;                                                             \
+        const bool h = (CH != kEmpty) && tmin <= tmax && tmin <= tlim;                   \
+        tn[S] = h ? tmin : INFINITY;                                                     \
+        rf[S] = h ? CH : kEmpty;                                                         \
+    }
+                RT_SLAB(0, lx.x, hx.x, ly.x, hy.x, lz.x, hz.x, ch.x)
+                RT_SLAB(1, lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, ch.y)
+                RT_SLAB(2, lx.z, hx.z, ly.z, hy.z, lz.z, hz.z, ch.z)
+                RT_SLAB(3, lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, ch.w)
+#undef RT_SLAB
+            } else {
+                const int32_t first = leaf_first(item), cnt = leaf_count(item);
+                if (cnt == 0 || first + cnt > n_tri) {
+                    bad = true;
+                } else {
+                    for (int i = 0; i < cnt; i++) {
+                        const int32_t j = first + i;
+                        const float4 v0 = tri[3 * j], v1 = tri[3 * j + 1], v2 = tri[3 * j + 2];
+                        if (__float_as_int(v0.w) == qlp) continue;
+                        const float t = watertight(q, v0, v1, v2);
+                        const int32_t id = __float_as_int(v1.w);
+                        if (t > 0.f && (t < lt || (t == lt && id < lid))) {
+                            lt = t;
+                            lid = id;
+                            lj = j;
+                        }
+                    }
+                }
+            }
+        }
+        if (__ballot(bad)) {
+            ok = false;
+            break;
+        }
+        // nearest hit of the group: (t, id) lexicographic minimum
+        for (int off = G / 2; off > 0; off >>= 1) {
+            const float ot = __shfl_xor(lt, off);
+            const int32_t oid = __shfl_xor(lid, off), oj = __shfl_xor(lj, off);
+            if (ot < lt || (ot == lt && oid < lid)) {
+                lt = ot;
+                lid = oid;
+                lj = oj;
+            }
+        }
+        bt = lt;
+        bid = lid;
+        bj = lj;
+        // children that can still hold a nearer or equal hit join the frontier
+        const float tkeep = widen(bt);
+        int cnt = 0;
+#pragma unroll
+        for (int sl = 0; sl < 4; sl++) cnt += (rf[sl] != kEmpty && tn[sl] <= tkeep) ? 1 : 0;
+        int incl = cnt;
+        for (int off = 1; off < G; off <<= 1) {
+            const int x = __shfl_up(incl, off);
+            if (li >= off) incl += x;
+        }
+        const int total = __shfl(incl, gbase + G - 1);
+        if (__ballot(nf + total > kCap) != 0ull) {
+            ok = false;
+            break;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        int at = nf + incl - cnt;
+        // far children first, so that the nearest are taken next
+#pragma unroll
+        for (int sl = 3; sl >= 0; sl--) {
+            if (rf[sl] != kEmpty && tn[sl] <= tkeep) {
+                fref[fat(at)] = rf[sl];
+                ft[fat(at)] = tn[sl];
+                at++;
+            }
+        }
+        nf += total;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    return ok;
+}
+
 template <int kWavesPerEU, bool kBatch>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWavesPerEU, 8)))
 k_trace(TraceArgs a) {
     __shared__ int32_t lds_stack[kRing * kBlock];
     __shared__ double rcv_s[kMaxRcv][4];
+    // travelled length of each lane's ray, FP64 across all its segments (kept
+    // out of the registers of the node loop, which never reads it)
+    __shared__ double len_s[kBlock];
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     if (!kBatch && tid < a.n_rcv * 4) rcv_s[tid >> 2][tid & 3] = (double)a.rcv[tid];
@@ -243,7 +407,7 @@ k_trace(TraceArgs a) {
     const float4* tri = a.tri;
     const double* pl_n = a.plane_n;
     const double* pl_p = a.plane_p;
-    int32_t n_nodes = a.n_nodes, n_tri = a.n_tri, rcv_off = 0, n_rcv = a.n_rcv;
+    int32_t n_nodes = a.n_nodes, n_tri = a.n_ref, rcv_off = 0, n_rcv = a.n_rcv;
     // travelled length at which a ray stops (+inf: no limit)
     float lim = a.max_len > 0.f ? a.max_len : INFINITY;
     if (!kBatch && a.beam_n > 0) {
@@ -259,7 +423,7 @@ k_trace(TraceArgs a) {
     int status = kIdle;
     int32_t ray = 0;
     int k = 0;
-    float L = 0.f;
+    len_s[tid] = 0.0;
     int32_t last_plane = -1;
     Ray r;
     r.ox = r.oy = r.oz = r.ux = r.uy = r.uz = 0.f;
@@ -330,7 +494,7 @@ k_trace(TraceArgs a) {
                         r.ux = d[0];
                         r.uy = d[1];
                         r.uz = d[2];
-                        L = 0.f;
+                        len_s[tid] = 0.0;
                         last_plane = -1;
                         k = 0;
                     } else if (a.q_in) {
@@ -341,7 +505,7 @@ k_trace(TraceArgs a) {
                         r.ox = __int_as_float(e1.x);
                         r.oy = __int_as_float(e1.y);
                         r.oz = __int_as_float(e1.z);
-                        L = __int_as_float(e1.w);
+                        len_s[tid] = __hiloint2double(e2.w, e1.w);
                         r.ux = __int_as_float(e2.x);
                         r.uy = __int_as_float(e2.y);
                         r.uz = __int_as_float(e2.z);
@@ -359,7 +523,7 @@ k_trace(TraceArgs a) {
                         r.ux = a.dirs[3 * ray];
                         r.uy = a.dirs[3 * ray + 1];
                         r.uz = a.dirs[3 * ray + 2];
-                        L = a.start_len ? a.start_len[ray] : 0.f;
+                        len_s[tid] = a.start_len ? (double)a.start_len[ray] : 0.0;
                         last_plane = a.start_plane ? a.start_plane[ray] : -1;
                         k = 0;
                     }
@@ -371,7 +535,7 @@ k_trace(TraceArgs a) {
                         pl_n = sc.plane_n;
                         pl_p = sc.plane_p;
                         n_nodes = sc.n_nodes;
-                        n_tri = sc.n_tri;
+                        n_tri = sc.n_ref;
                         rcv_off = jb.rcv_off;
                         n_rcv = jb.n_rcv;
                         lim = jb.max_len > 0.f ? jb.max_len : INFINITY;
@@ -409,9 +573,11 @@ k_trace(TraceArgs a) {
                         const unsigned long long pos = base + (unsigned long long)__popcll(act & lt_mask);
                         int4* q = a.q_out + 3 * pos;
                         q[0] = make_int4((int)ray, k, last_plane, 0);
+                        const double lq = len_s[tid];
                         q[1] = make_int4(__float_as_int(r.ox), __float_as_int(r.oy), __float_as_int(r.oz),
-                                         __float_as_int(L));
-                        q[2] = make_int4(__float_as_int(r.ux), __float_as_int(r.uy), __float_as_int(r.uz), 0);
+                                         __double2loint(lq));
+                        q[2] = make_int4(__float_as_int(r.ux), __float_as_int(r.uy), __float_as_int(r.uz),
+                                         __double2hiint(lq));
                         status = kIdle;
                     }
                 }
@@ -423,177 +589,19 @@ k_trace(TraceArgs a) {
             continue;
         }
 
-        // ---- one query left in the wavefront: search it with every lane -------
-        // Breadth first over a frontier of inner nodes kept in the wavefront's
-        // LDS stack area (the owner's own stack is dropped, the other lanes'
-        // are empty): each step every lane expands one frontier node, tests
-        // the leaves it reaches and the wavefront keeps the nearest hit (exact
-        // ties to the lowest triangle id), so the result is the owner's own
-        // walk's, in about tree-depth steps instead of one node per step.
+        // ---- one or two queries left in the wavefront: search them with every lane
+        // (coop_search: breadth first over a frontier in the wavefront's LDS
+        // stack area; the owners' own stacks are dropped, the other lanes' are
+        // empty), so a query takes about tree-depth steps instead of one node
+        // per step; the result is the owner's own walk's.
         if (!kBatch && a.coop && pool_empty) {
             const uint64_t act = __ballot(status == kQuery);
-            if (__popcll(act) == 1 && __ballot(status == kDone) == 0ull) {
-                const int owner = __ffsll((long long)act) - 1;
-                // wave-uniform copies of the owner's query (scalar registers)
-                auto rdf = [owner](float x) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), owner)); };
-                Ray q;
-                q.ox = rdf(r.ox);
-                q.oy = rdf(r.oy);
-                q.oz = rdf(r.oz);
-                q.ux = rdf(r.ux);
-                q.uy = rdf(r.uy);
-                q.uz = rdf(r.uz);
-                setup_ray(q);
-                const int32_t qlp = __builtin_amdgcn_readlane(last_plane, owner);
-                float bt = rdf(best_t);
-                int32_t bid = __builtin_amdgcn_readlane(best_id, owner), bj = __builtin_amdgcn_readlane(best_j, owner);
-                // frontier: refs in slots 0..7, entry distances in slots 8..15 of the wave's columns
-                int32_t* fref = lds_stack + (tid - lane);
-                float* ft = reinterpret_cast<float*>(lds_stack + 8 * kBlock + (tid - lane));
-                auto fat = [](int k) { return (k >> 6) * kBlock + (k & (kWave - 1)); };
-                constexpr int kCoopCap = 8 * kWave;
-                int nf = 1;
-                if (lane == 0) {
-                    fref[0] = 0;
-                    ft[0] = 0.f;
-                }
-                bool ok = true;
-                int csteps = 0;
-                while (nf > 0) {
-                    if (++csteps > a.max_steps) {
-                        ok = false;
-                        break;
-                    }
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                    const int take = nf < kWave ? nf : kWave;
-                    const int base = nf - take;   // the most recent entries, deepest first
-                    int32_t item = -1;
-                    float it = INFINITY;
-                    if (lane < take) {
-                        item = fref[fat(base + lane)];
-                        it = ft[fat(base + lane)];
-                    }
-                    nf = base;
-                    float tn[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
-                    int32_t rf[4] = {kEmpty, kEmpty, kEmpty, kEmpty};
-                    float lt = bt;
-                    int32_t lid = bid, lj = bj;
-                    bool bad = item >= n_nodes;
-                    if (item >= 0 && item < n_nodes && it <= bt) {
-                        const float4* np = reinterpret_cast<const float4*>(nodes + item);
-                        const float4 lx = np[0], hx = np[1], ly = np[2], hy = np[3], lz = np[4], hz = np[5];
-                        const int4 ch = reinterpret_cast<const int4*>(np)[6];
-                        const float tlim = bt;
-#define RT_SLAB(S, LX, HX, LY, HY, LZ, HZ, CH)                                          \
-    {                                                                                    \
-        const float t0x = (LX - q.ox) * q.ix, t1x = (HX - q.ox) * q.ix;                  \
-        const float t0y = (LY - q.oy) * q.iy, t1y = (HY - q.oy) * q.iy;                  \
-        const float t0z = (LZ - q.oz) * q.iz, t1z = (HZ - q.oz) * q.iz;                  \
-        const float tmin = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)),               \
-                                 fmaxf(fminf(t0z, t1z), 0.f));                           \
-        float tmax = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z));    \
-        tmax *= 1.00000036f;                                                             \
-        const bool h = (CH != kEmpty) && tmin <= tmax && tmin <= tlim;                   \
-        tn[S] = h ? tmin : INFINITY;                                                     \
-        rf[S] = h ? CH : kEmpty;                                                         \
-    }
-                        RT_SLAB(0, lx.x, hx.x, ly.x, hy.x, lz.x, hz.x, ch.x)
-                        RT_SLAB(1, lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, ch.y)
-                        RT_SLAB(2, lx.z, hx.z, ly.z, hy.z, lz.z, hz.z, ch.z)
-                        RT_SLAB(3, lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, ch.w)
-#undef RT_SLAB
-#pragma unroll
-                        for (int sl = 0; sl < 4; sl++) {
-                            if (rf[sl] < 0 && rf[sl] != kEmpty) {
-                                const int32_t first = leaf_first(rf[sl]), cnt = leaf_count(rf[sl]);
-                                rf[sl] = kEmpty;
-                                if (first + cnt > n_tri) {
-                                    bad = true;
-                                } else {
-                                    for (int i = 0; i < cnt; i++) {
-                                        const int32_t j = first + i;
-                                        const float4 v0 = tri[3 * j], v1 = tri[3 * j + 1], v2 = tri[3 * j + 2];
-                                        if (__float_as_int(v0.w) == qlp) continue;
-                                        const float t = watertight(q, v0, v1, v2);
-                                        const int32_t id = __float_as_int(v1.w);
-                                        if (t > 0.f && (t < lt || (t == lt && id < lid))) {
-                                            lt = t;
-                                            lid = id;
-                                            lj = j;
-                                        }
-                                    }
-                                }
-                            }
-                        }
-                    }
-                    if (__ballot(bad)) {
-                        ok = false;
-                        break;
-                    }
-                    // nearest hit of the wavefront: (t, id) lexicographic minimum
-                    for (int off = kWave / 2; off > 0; off >>= 1) {
-                        const float ot = __shfl_xor(lt, off);
-                        const int32_t oid = __shfl_xor(lid, off), oj = __shfl_xor(lj, off);
-                        if (ot < lt || (ot == lt && oid < lid)) {
-                            lt = ot;
-                            lid = oid;
-                            lj = oj;
-                        }
-                    }
-                    bt = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(lt)));
-                    bid = __builtin_amdgcn_readfirstlane(lid);
-                    bj = __builtin_amdgcn_readfirstlane(lj);
-                    // children that can still hold a nearer or equal hit join the frontier
-                    int cnt = 0;
-#pragma unroll
-                    for (int sl = 0; sl < 4; sl++) cnt += (rf[sl] >= 0 && tn[sl] <= bt) ? 1 : 0;
-                    int incl = cnt;
-                    for (int off = 1; off < kWave; off <<= 1) {
-                        const int x = __shfl_up(incl, off);
-                        if (lane >= off) incl += x;
-                    }
-                    const int total = __builtin_amdgcn_readlane(incl, kWave - 1);
-                    if (nf + total > kCoopCap) {
-                        ok = false;
-                        break;
-                    }
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                    int at = nf + incl - cnt;
-                    // far children first, so that the nearest are taken next
-#pragma unroll
-                    for (int sl = 3; sl >= 0; sl--) {
-                        if (rf[sl] >= 0 && tn[sl] <= bt) {
-                            fref[fat(at)] = rf[sl];
-                            ft[fat(at)] = tn[sl];
-                            at++;
-                        }
-                    }
-                    nf += total;
-                }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                if (lane == owner) {
-                    best_t = bt;
-                    best_id = bid;
-                    best_j = bj;
-                    st = Stack{0, 0, 0};
-                    if (ok) {
-                        status = kDone;
-                    } else {
-                        cur = 0;   // fall back: the owner's own walk from the root, bounded by the hit so far
-                        steps = 0;
-                    }
-                }
-            } else if (__popcll(act) == 2 && __ballot(status == kDone) == 0ull) {
-                // two queries left: each half of the wavefront searches one of them the same way
-                const int g = lane >> 5, li = lane & 31;
+            const int n_act = __popcll(act);
+            if ((n_act == 1 || n_act == 2) && __ballot(status == kDone) == 0ull) {
+                // one query: all 64 lanes; two: 32 lanes each (an owner may sit in either half)
                 const int own0 = __ffsll((long long)act) - 1;
-                const int own1 = __ffsll((long long)(act & (act - 1))) - 1;
+                const int own1 = n_act == 2 ? __ffsll((long long)(act & (act - 1))) - 1 : own0;
+                const int g = n_act == 2 ? lane >> 5 : 0;
                 const int mo = g ? own1 : own0;
                 Ray q;
                 q.ox = __shfl(r.ox, mo);
@@ -606,140 +614,20 @@ k_trace(TraceArgs a) {
                 const int32_t qlp = __shfl(last_plane, mo);
                 float bt = __shfl(best_t, mo);
                 int32_t bid = __shfl(best_id, mo), bj = __shfl(best_j, mo);
-                // per half: refs in slots 0..7, entry distances in slots 8..15 of its 32 columns
-                int32_t* fref = lds_stack + (tid - lane) + 32 * g;
-                float* ft = reinterpret_cast<float*>(lds_stack + 8 * kBlock + (tid - lane) + 32 * g);
-                auto fat = [](int k) { return (k >> 5) * kBlock + (k & 31); };
-                constexpr int kCap2 = 8 * 32;
-                int nf = 1;
-                if (li == 0) {
-                    fref[0] = 0;
-                    ft[0] = 0.f;
+                bool ok;
+                if (n_act == 1) {
+                    ok = coop_search<64>(q, qlp, bt, bid, bj, lds_stack + (tid - lane), lane, 0, nodes, tri, n_nodes,
+                                         n_tri, a.max_steps);
+                } else {
+                    ok = coop_search<32>(q, qlp, bt, bid, bj, lds_stack + (tid - lane) + 32 * g, lane & 31, 32 * g,
+                                         nodes, tri, n_nodes, n_tri, a.max_steps);
                 }
-                bool ok = true;
-                int csteps = 0;
-                while (__ballot(nf > 0) != 0ull) {
-                    if (++csteps > a.max_steps) {
-                        ok = false;
-                        break;
-                    }
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                    const int take = nf < 32 ? nf : 32;
-                    const int base = nf - take;
-                    int32_t item = -1;
-                    float it = INFINITY;
-                    if (li < take) {
-                        item = fref[fat(base + li)];
-                        it = ft[fat(base + li)];
-                    }
-                    nf = base;
-                    float tn[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
-                    int32_t rf[4] = {kEmpty, kEmpty, kEmpty, kEmpty};
-                    float lt = bt;
-                    int32_t lid = bid, lj = bj;
-                    bool bad = item >= n_nodes;
-                    if (item >= 0 && item < n_nodes && it <= bt) {
-                        const float4* np = reinterpret_cast<const float4*>(nodes + item);
-                        const float4 lx = np[0], hx = np[1], ly = np[2], hy = np[3], lz = np[4], hz = np[5];
-                        const int4 ch = reinterpret_cast<const int4*>(np)[6];
-                        const float tlim = bt;
-#define RT_SLAB(S, LX, HX, LY, HY, LZ, HZ, CH)                                          \
-    {                                                                                    \
-        const float t0x = (LX - q.ox) * q.ix, t1x = (HX - q.ox) * q.ix;                  \
-        const float t0y = (LY - q.oy) * q.iy, t1y = (HY - q.oy) * q.iy;                  \
-        const float t0z = (LZ - q.oz) * q.iz, t1z = (HZ - q.oz) * q.iz;                  \
-        const float tmin = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)),               \
-                                 fmaxf(fminf(t0z, t1z), 0.f));                           \
-        float tmax = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z));    \
-        tmax *= 1.00000036f;                                                             \
-        const bool h = (CH != kEmpty) && tmin <= tmax && tmin <= tlim;                   \
-        tn[S] = h ? tmin : INFINITY;                                                     \
-        rf[S] = h ? CH : kEmpty;                                                         \
-    }
-                        RT_SLAB(0, lx.x, hx.x, ly.x, hy.x, lz.x, hz.x, ch.x)
-                        RT_SLAB(1, lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, ch.y)
-                        RT_SLAB(2, lx.z, hx.z, ly.z, hy.z, lz.z, hz.z, ch.z)
-                        RT_SLAB(3, lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, ch.w)
-#undef RT_SLAB
-#pragma unroll
-                        for (int sl = 0; sl < 4; sl++) {
-                            if (rf[sl] < 0 && rf[sl] != kEmpty) {
-                                const int32_t first = leaf_first(rf[sl]), cnt = leaf_count(rf[sl]);
-                                rf[sl] = kEmpty;
-                                if (first + cnt > n_tri) {
-                                    bad = true;
-                                } else {
-                                    for (int i = 0; i < cnt; i++) {
-                                        const int32_t j = first + i;
-                                        const float4 v0 = tri[3 * j], v1 = tri[3 * j + 1], v2 = tri[3 * j + 2];
-                                        if (__float_as_int(v0.w) == qlp) continue;
-                                        const float t = watertight(q, v0, v1, v2);
-                                        const int32_t id = __float_as_int(v1.w);
-                                        if (t > 0.f && (t < lt || (t == lt && id < lid))) {
-                                            lt = t;
-                                            lid = id;
-                                            lj = j;
-                                        }
-                                    }
-                                }
-                            }
-                        }
-                    }
-                    if (__ballot(bad)) {
-                        ok = false;
-                        break;
-                    }
-                    // nearest hit of each half: (t, id) lexicographic minimum over its 32 lanes
-                    for (int off = 16; off > 0; off >>= 1) {
-                        const float ot = __shfl_xor(lt, off);
-                        const int32_t oid = __shfl_xor(lid, off), oj = __shfl_xor(lj, off);
-                        if (ot < lt || (ot == lt && oid < lid)) {
-                            lt = ot;
-                            lid = oid;
-                            lj = oj;
-                        }
-                    }
-                    bt = lt;
-                    bid = lid;
-                    bj = lj;
-                    int cnt = 0;
-#pragma unroll
-                    for (int sl = 0; sl < 4; sl++) cnt += (rf[sl] >= 0 && tn[sl] <= bt) ? 1 : 0;
-                    int incl = cnt;
-                    for (int off = 1; off < 32; off <<= 1) {
-                        const int x = __shfl_up(incl, off);
-                        if (li >= off) incl += x;
-                    }
-                    const int total = __shfl(incl, (lane & 32) + 31);
-                    if (__ballot(nf + total > kCap2) != 0ull) {
-                        ok = false;
-                        break;
-                    }
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                    int at = nf + incl - cnt;
-#pragma unroll
-                    for (int sl = 3; sl >= 0; sl--) {
-                        if (rf[sl] >= 0 && tn[sl] <= bt) {
-                            fref[fat(at)] = rf[sl];
-                            ft[fat(at)] = tn[sl];
-                            at++;
-                        }
-                    }
-                    nf += total;
-                }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                // each owner takes its half's result (an owner may sit in either half)
+                // each owner takes its group's result
                 const float bt0 = __shfl(bt, 0), bt1 = __shfl(bt, 32);
                 const int32_t bid0 = __shfl(bid, 0), bid1 = __shfl(bid, 32);
                 const int32_t bj0 = __shfl(bj, 0), bj1 = __shfl(bj, 32);
                 if (lane == own0 || lane == own1) {
-                    const bool first = lane == own0;
+                    const bool first = lane == own0 || n_act == 1;
                     best_t = first ? bt0 : bt1;
                     best_id = first ? bid0 : bid1;
                     best_j = first ? bj0 : bj1;
@@ -747,7 +635,7 @@ k_trace(TraceArgs a) {
                     if (ok) {
                         status = kDone;
                     } else {
-                        cur = 0;
+                        cur = 0;   // fall back: the owner's own walk from the root, bounded by the hit so far
                         steps = 0;
                     }
                 }
@@ -776,29 +664,36 @@ k_trace(TraceArgs a) {
                 status = kDone;
                 continue;
             }
-            // every step visits one inner node; leaf children whose box is hit
-            // are tested on the spot, inner children are descended or pushed
-            if (cur < 0 || cur >= n_nodes) {
+            // A step visits the lane's inner node, if it holds one: its four
+            // children are slab-tested, the nearest inner child is descended
+            // into, the nearest leaf child is tested in this same step and every
+            // other hit child (inner or leaf) is pushed far to near.  A lane
+            // holding a leaf taken from the stack tests it.  So each step runs
+            // the triangle test at most once per lane: the wavefront executes
+            // it once, not once per child slot.
+            if (cur >= n_nodes) {
                 atomicOr(&a.counters[3], kErrNode);
                 best_j = -1;
                 status = kDone;
                 continue;
             }
-            if (want_stats) st_nodes++;
-            const float4* np = reinterpret_cast<const float4*>(nodes + cur);
-            const float4 lx = np[0], hx = np[1], ly = np[2], hy = np[3], lz = np[4], hz = np[5];
-            const int4 ch = reinterpret_cast<const int4*>(np)[6];
-            // once the pool is empty: touch the node on top of the stack along with
-            // this one, so that the pop after a step whose children all miss finds
-            // its node in the cache (a step that pops pushes nothing)
+            int32_t leaf = kEmpty;
             int32_t touch = 0;
-            if (pool_empty && st.cnt > 0) {
-                const int32_t top = lds_stack[((st.base + st.cnt - 1) & (kRing - 1)) * kBlock + tid];
-                if (top >= 0 && top < n_nodes) touch = reinterpret_cast<const int32_t*>(nodes + top)[0];
-            }
-            const float tlim = best_t;
-            float tn[4];
-            int32_t rf[4];
+            bool ok = true;
+            if (cur >= 0) {
+                if (want_stats) st_nodes++;
+                const float4* np = reinterpret_cast<const float4*>(nodes + cur);
+                const float4 lx = np[0], hx = np[1], ly = np[2], hy = np[3], lz = np[4], hz = np[5];
+                const int4 ch = reinterpret_cast<const int4*>(np)[6];
+                // once the pool is empty: touch the node on top of the stack along
+                // with this one, so that a later pop finds it in the cache
+                if (pool_empty && st.cnt > 0) {
+                    const int32_t top = lds_stack[((st.base + st.cnt - 1) & (kRing - 1)) * kBlock + tid];
+                    if (top >= 0 && top < n_nodes) touch = reinterpret_cast<const int32_t*>(nodes + top)[0];
+                }
+                const float tlim = widen(best_t);
+                float tn[4];
+                int32_t rf[4];
 #define RT_SLAB(S, LX, HX, LY, HY, LZ, HZ, CH)                                          \
     {                                                                                    \
         const float t0x = (LX - r.ox) * r.ix, t1x = (HX - r.ox) * r.ix;                  \
@@ -812,74 +707,73 @@ k_trace(TraceArgs a) {
         tn[S] = h ? tmin : INFINITY;                                                     \
         rf[S] = CH;                                                                      \
     }
-            RT_SLAB(0, lx.x, hx.x, ly.x, hy.x, lz.x, hz.x, ch.x)
-            RT_SLAB(1, lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, ch.y)
-            RT_SLAB(2, lx.z, hx.z, ly.z, hy.z, lz.z, hz.z, ch.z)
-            RT_SLAB(3, lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, ch.w)
+                RT_SLAB(0, lx.x, hx.x, ly.x, hy.x, lz.x, hz.x, ch.x)
+                RT_SLAB(1, lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, ch.y)
+                RT_SLAB(2, lx.z, hx.z, ly.z, hy.z, lz.z, hz.z, ch.z)
+                RT_SLAB(3, lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, ch.w)
 #undef RT_SLAB
-            cswap(tn[0], rf[0], tn[1], rf[1]);
-            cswap(tn[2], rf[2], tn[3], rf[3]);
-            cswap(tn[0], rf[0], tn[2], rf[2]);
-            cswap(tn[1], rf[1], tn[3], rf[3]);
-            cswap(tn[1], rf[1], tn[2], rf[2]);
-            // leaves, near to far, each only while its box can still hold a nearer hit
-            uint32_t inner = 0;
-            bool bad = false;
+                cswap(tn[0], rf[0], tn[1], rf[1]);
+                cswap(tn[2], rf[2], tn[3], rf[3]);
+                cswap(tn[0], rf[0], tn[2], rf[2]);
+                cswap(tn[1], rf[1], tn[3], rf[3]);
+                cswap(tn[1], rf[1], tn[2], rf[2]);
+                // slots of the nearest inner and the nearest leaf child that are hit
+                int ii = -1, li = -1;
 #pragma unroll
-            for (int sl = 0; sl < 4; sl++) {
-                if (tn[sl] < INFINITY) {
-                    if (rf[sl] >= 0) {
-                        inner |= 1u << sl;
-                    } else if (tn[sl] <= best_t) {
-                        const int32_t first = leaf_first(rf[sl]), cnt = leaf_count(rf[sl]);
-                        if (want_stats) {
-                            st_leaves++;
-                            st_tris += (uint32_t)cnt;
-                        }
-                        if (first + cnt > n_tri) {
-                            bad = true;
-                        } else {
-                            for (int i = 0; i < cnt; i++) {
-                                const int32_t j = first + i;
-                                const float4 v0 = tri[3 * j], v1 = tri[3 * j + 1], v2 = tri[3 * j + 2];
-                                if (__float_as_int(v0.w) == last_plane) continue;
-                                const float t = watertight(r, v0, v1, v2);
-                                const int32_t id = __float_as_int(v1.w);
-                                if (t > 0.f && (t < best_t || (t == best_t && id < best_id))) {
-                                    best_t = t;
-                                    best_j = j;
-                                    best_id = id;
-                                }
-                            }
-                        }
+                for (int sl = 3; sl >= 0; sl--) {
+                    if (tn[sl] < INFINITY) {
+                        if (rf[sl] >= 0) ii = sl;
+                        else li = sl;
                     }
                 }
-            }
-            if (bad) {
-                atomicOr(&a.counters[3], kErrNode);
-                best_j = -1;
-                status = kDone;
-                continue;
-            }
-            // descend into the nearest inner child, push the others far to near
-            const int nearest = inner ? __ffs(inner) - 1 : -1;
-            bool ok = true;
-            if (want_stats && st.cnt + (int)__popc(inner) - 1 > kRing) st_spill++;
+                if (want_stats) {
+                    int np_ = 0;
 #pragma unroll
-            for (int sl = 3; sl >= 1; sl--)
-                if (((inner >> sl) & 1u) && sl != nearest)
-                    ok &= stack_push(st, lds_stack, spill, a.spill_per_lane, tid, rf[sl]);
+                    for (int sl = 0; sl < 4; sl++) np_ += (tn[sl] < INFINITY && sl != ii && sl != li) ? 1 : 0;
+                    if (st.cnt + np_ > kRing) st_spill++;
+                }
+#pragma unroll
+                for (int sl = 3; sl >= 0; sl--)
+                    if (tn[sl] < INFINITY && sl != ii && sl != li)
+                        ok &= stack_push(st, lds_stack, spill, a.spill_per_lane, tid, rf[sl]);
+                leaf = li == 0 ? rf[0] : li == 1 ? rf[1] : li == 2 ? rf[2] : li == 3 ? rf[3] : kEmpty;
+                cur = ii == 0 ? rf[0] : ii == 1 ? rf[1] : ii == 2 ? rf[2] : ii == 3 ? rf[3] : kEmpty;
+            } else {
+                leaf = cur;   // a leaf taken from the stack
+                cur = kEmpty;
+            }
             if (!ok) {
                 atomicOr(&a.counters[3], kErrStack);
                 best_j = -1;
                 status = kDone;
                 continue;
             }
-            if (nearest >= 0) {
-                cur = nearest == 0 ? rf[0] : nearest == 1 ? rf[1] : nearest == 2 ? rf[2] : rf[3];
-            } else {
-                have = stack_pop(st, lds_stack, spill, tid, cur);
+            if (leaf != kEmpty) {
+                const int32_t first = leaf_first(leaf), cnt = leaf_count(leaf);
+                if (want_stats) {
+                    st_leaves++;
+                    st_tris += (uint32_t)cnt;
+                }
+                if (first + cnt > n_tri) {
+                    atomicOr(&a.counters[3], kErrNode);
+                    best_j = -1;
+                    status = kDone;
+                    continue;
+                }
+                for (int i = 0; i < cnt; i++) {
+                    const int32_t j = first + i;
+                    const float4 v0 = tri[3 * j], v1 = tri[3 * j + 1], v2 = tri[3 * j + 2];
+                    if (__float_as_int(v0.w) == last_plane) continue;
+                    const float t = watertight(r, v0, v1, v2);
+                    const int32_t id = __float_as_int(v1.w);
+                    if (t > 0.f && (t < best_t || (t == best_t && id < best_id))) {
+                        best_t = t;
+                        best_j = j;
+                        best_id = id;
+                    }
+                }
             }
+            if (cur == kEmpty) have = stack_pop(st, lds_stack, spill, tid, cur);
             if (!have) status = kDone;
             asm volatile("" ::"v"(touch));   // keeps the touch load
         }
@@ -965,15 +859,17 @@ k_trace(TraceArgs a) {
             n_query++;
             int32_t* hs = a.hit_seq + (int64_t)ray * R1;
             hs[k] = hit_id;
-            if (a.record) {
-                float* sp = a.states + ((int64_t)ray * (R1 + 1) + k) * 8;
+            const double Lc = len_s[tid];
+            const int64_t srow = a.record ? (a.record_rows ? (int64_t)a.record_rows[ray] : (int64_t)ray) : -1;
+            if (srow >= 0) {
+                float* sp = a.states + (srow * (R1 + 1) + k) * 8;
                 sp[0] = r.ox;
                 sp[1] = r.oy;
                 sp[2] = r.oz;
                 sp[3] = r.ux;
                 sp[4] = r.uy;
                 sp[5] = r.uz;
-                sp[6] = L;
+                sp[6] = (float)Lc;
                 sp[7] = __int_as_float(last_plane);
             }
             bool stop = true;
@@ -983,25 +879,25 @@ k_trace(TraceArgs a) {
                 const double nx = pl_n[3 * (int64_t)hit_plane], ny = pl_n[3 * (int64_t)hit_plane + 1],
                              nz = pl_n[3 * (int64_t)hit_plane + 2];
                 const double udn = ux * nx + uy * ny + uz * nz;
-                const double Ln = (double)L + dl * sqrt(uu);
+                const double Ln = Lc + dl * sqrt(uu);
                 r.ox = (float)(ox + dl * ux);
                 r.oy = (float)(oy + dl * uy);
                 r.oz = (float)(oz + dl * uz);
                 r.ux = (float)(ux - 2.0 * udn * nx);
                 r.uy = (float)(uy - 2.0 * udn * ny);
                 r.uz = (float)(uz - 2.0 * udn * nz);
-                L = (float)Ln;
+                len_s[tid] = Ln;
                 last_plane = hit_plane;
                 stop = (k == a.R) || Ln >= (double)lim;
-                if (a.record) {
-                    float* sp = a.states + ((int64_t)ray * (R1 + 1) + k + 1) * 8;
+                if (srow >= 0) {
+                    float* sp = a.states + (srow * (R1 + 1) + k + 1) * 8;
                     sp[0] = r.ox;
                     sp[1] = r.oy;
                     sp[2] = r.oz;
                     sp[3] = r.ux;
                     sp[4] = r.uy;
                     sp[5] = r.uz;
-                    sp[6] = L;
+                    sp[6] = (float)Ln;
                     sp[7] = __int_as_float(last_plane);
                 }
             }
@@ -1036,9 +932,11 @@ k_trace(TraceArgs a) {
                     if (pos < (unsigned long long)a.q_cap) {
                         int4* q = a.q_out + 3 * pos;
                         q[0] = make_int4((int)ray, k, last_plane, 0);
+                        const double lq = len_s[tid];
                         q[1] = make_int4(__float_as_int(r.ox), __float_as_int(r.oy), __float_as_int(r.oz),
-                                         __float_as_int(L));
-                        q[2] = make_int4(__float_as_int(r.ux), __float_as_int(r.uy), __float_as_int(r.uz), 0);
+                                         __double2loint(lq));
+                        q[2] = make_int4(__float_as_int(r.ux), __float_as_int(r.uy), __float_as_int(r.uz),
+                                         __double2hiint(lq));
                     } else {
                         atomicOr(&a.counters[3], kErrQueue);
                     }
@@ -1184,12 +1082,13 @@ namespace {
 // fill, launches.  `ws` is the scene whose workspace holds the scratch.
 int run_trace(rt_scene* ws, TraceArgs& a, const rt_trace_params* p, int depth, int64_t max_steps, int64_t n_rays,
               int32_t* hit_seq, const float* dirs, const float* origins, const float* bounds, hipStream_t st) {
-    // Single scene: 5 waves per SIMD by default; a 96-register budget spills a little, but the busy
-    // phase is bound by the latency of dependent node fetches and gains more from the fifth wavefront
-    // than it loses.  Batched: 4, since that instance keeps a per-lane scene view and at 96 registers
-    // spills in its node loop (5 and 6 waves are 42 % and 67 % slower on the 8-room batch).
+    // 4 waves per SIMD by default: the 128-register budget of the kernel spills nothing.  A fifth
+    // wavefront (96 registers, spills around the shading) raises the busy-phase rate of closed rooms a
+    // little (the 100k-triangle box: 3 %) but slows the drain of an open scene's long bounce chains
+    // (the theater: 9 %); the batched instance keeps a per-lane scene view and spills in its node loop
+    // at 96 registers (5 and 6 waves are 42 % and 67 % slower on the 8-room batch).
     const int wps = p->waves_per_simd;
-    const int occ = (wps == 4 || wps == 5 || wps == 6 || wps == 8) ? wps : (a.jobs ? 4 : 5);
+    const int occ = (wps == 4 || wps == 5 || wps == 6 || wps == 8) ? wps : 4;
     const int bpc = p->blocks_per_cu > 0 ? p->blocks_per_cu : occ;
     int64_t nblk = (int64_t)device_sm_count() * bpc;
     const int64_t need = (n_rays + kBlock - 1) / kBlock;
@@ -1312,7 +1211,7 @@ extern "C" int rt_trace_rays(const rt_scene* scene, const float* src_host, const
     a.plane_n = s->plane_n;
     a.plane_p = s->plane_p;
     a.n_nodes = s->n_nodes;
-    a.n_tri = (int32_t)s->n_tri;
+    a.n_ref = (int32_t)s->n_ref;
     a.src[0] = src_host ? src_host[0] : 0.f;
     a.src[1] = src_host ? src_host[1] : 0.f;
     a.src[2] = src_host ? src_host[2] : 0.f;
@@ -1330,6 +1229,7 @@ extern "C" int rt_trace_rays(const rt_scene* scene, const float* src_host, const
     // the cooperative search off, so that every step of every query is counted
     a.coop = p->coop_queries >= 0 && !p->stats ? 1 : 0;
     a.record = p->record_states ? 1 : 0;
+    a.record_rows = p->record_rows;
     a.hit_seq = hit_seq;
     a.det = det;
     a.det_cap = det_cap;
@@ -1339,7 +1239,7 @@ extern "C" int rt_trace_rays(const rt_scene* scene, const float* src_host, const
     a.jobs = nullptr;
     a.scenes = nullptr;
     a.n_jobs = 0;
-    return run_trace(s, a, p, s->depth, 8 * ((int64_t)s->n_nodes + s->n_tri) + 4096, n_rays, hit_seq, dirs,
+    return run_trace(s, a, p, s->depth, 8 * ((int64_t)s->n_nodes + s->n_ref) + 4096, n_rays, hit_seq, dirs,
                      origins, s->bounds, st);
 }
 
@@ -1358,7 +1258,7 @@ extern "C" int rt_batch_create(const rt_scene* const* scenes, int32_t n_scenes, 
         const rt_scene* s = scenes[i];
         RT_CHECK(s, RT_EINVAL, "rt_batch_create: scene %d is NULL", i);
         hs[i] = DevScene{s->nodes, s->tri_rec, s->plane_n, s->plane_p, s->plane_mat, s->tri_plane, s->n_nodes,
-                         (int32_t)s->n_tri, mat_off, s->n_mat};
+                         (int32_t)s->n_tri, mat_off, s->n_mat, (int32_t)s->n_ref, 0};
         mat_off += s->n_mat;
     }
     std::vector<DevJob> hj(n_jobs);
@@ -1389,7 +1289,7 @@ extern "C" int rt_batch_create(const rt_scene* const* scenes, int32_t n_scenes, 
     int64_t steps = 0;
     for (int i = 0; i < n_scenes; i++) {
         depth = depth > scenes[i]->depth ? depth : scenes[i]->depth;
-        const int64_t ms = 8 * ((int64_t)scenes[i]->n_nodes + scenes[i]->n_tri) + 4096;
+        const int64_t ms = 8 * ((int64_t)scenes[i]->n_nodes + scenes[i]->n_ref) + 4096;
         steps = steps > ms ? steps : ms;
     }
     b->max_depth = depth;
@@ -1436,10 +1336,10 @@ extern "C" int rt_batch_info(const rt_batch* b, int64_t* info_host) {
 }
 
 extern "C" int rt_trace_batch(rt_batch* b, const float* rcv, const rt_trace_params* p, int32_t* hit_seq, int32_t* det,
-                              int64_t det_cap, int64_t* counters, void* stream) {
+                              int64_t det_cap, int64_t* counters, float* states, void* stream) {
     RT_CHECK(b && rcv && hit_seq && counters, RT_EINVAL, "rt_trace_batch: null argument");
     if (check_params(p)) return RT_EINVAL;
-    RT_CHECK(!p->record_states, RT_EINVAL, "rt_trace_batch: record_states is not supported for batches");
+    RT_CHECK(!p->record_states || states, RT_EINVAL, "rt_trace_batch: record_states needs states");
     RT_CHECK(det_cap >= 0 && (det_cap == 0 || det), RT_EINVAL, "rt_trace_batch: det is NULL");
     hipStream_t st = (hipStream_t)stream;
     rt_scene* s = b->ws_owner;
@@ -1453,6 +1353,9 @@ extern "C" int rt_trace_batch(rt_batch* b, const float* rcv, const rt_trace_para
     a.R = p->max_reflections;
     a.beam_n = p->min_beam_rays;
     a.coop = p->coop_queries >= 0 && !p->stats ? 1 : 0;
+    a.record = p->record_states ? 1 : 0;
+    a.record_rows = p->record_rows;
+    a.states = states;
     a.hit_seq = hit_seq;
     a.det = det;
     a.det_cap = det_cap;
