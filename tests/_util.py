@@ -56,3 +56,42 @@ def synthetic_is_table(scene, n_is, max_reflections, n_rcv, seed, L, c, fs, n_ra
     for i, k in enumerate(ks):
         arr[i, : len(k)] = k
     return tab, arr
+
+
+def crossing_and_miss(o, u, v0, v1, v2):
+    """FP64 plane crossing of rays o + t u with triangles (v0, v1, v2), row by
+    row: t of the crossing (inf when u is parallel to the plane) and the
+    distance from the crossing point to the closed triangle (0 inside).
+    Plain geometry for checking a flagged query's GPU answer; no arithmetic
+    of the method."""
+    o, u, v0, v1, v2 = [np.asarray(a, np.float64).reshape(-1, 3) for a in (o, u, v0, v1, v2)]
+    e1, e2 = v1 - v0, v2 - v0
+    n = np.cross(e1, e2)
+    den = np.einsum("ij,ij->i", u, n)
+    num = np.einsum("ij,ij->i", v0 - o, n)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t = np.where(den != 0.0, num / den, np.inf)
+    p = o + np.where(np.isfinite(t), t, 0.0)[:, None] * u
+    miss = np.zeros(len(o))
+    for i in range(len(o)):
+        if not np.isfinite(t[i]):
+            miss[i] = np.inf
+            continue
+        miss[i] = _point_triangle_distance(p[i], v0[i], v1[i], v2[i])
+    return t, miss
+
+
+def _point_triangle_distance(p, a, b, c):
+    """Distance from p (in the triangle's plane) to the closed triangle abc:
+    0 when the barycentric coordinates are all >= 0, else the distance to the
+    nearest of the three edge segments."""
+    m = np.array([b - a, c - a]).T
+    lam, mu = np.linalg.lstsq(m, p - a, rcond=None)[0]
+    if lam >= 0 and mu >= 0 and lam + mu <= 1:
+        return 0.0
+    best = np.inf
+    for s0, s1 in ((a, b), (b, c), (c, a)):
+        d = s1 - s0
+        w = np.clip(np.dot(p - s0, d) / np.dot(d, d), 0.0, 1.0)
+        best = min(best, float(np.linalg.norm(p - (s0 + w * d))))
+    return best

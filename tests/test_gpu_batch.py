@@ -17,7 +17,7 @@ import pytest
 import torch
 
 import synth
-from tests._util import gpu_is_dict
+from tests._util import gpu_is_dict, material_of_plane
 
 pytestmark = pytest.mark.gpu
 
@@ -110,6 +110,64 @@ def test_batch_collect_assemble_adjoint_equal_single(rt, setup):
     scale = np.abs(grad_ref).max()
     assert scale > 0
     assert np.allclose(gab, grad_ref, rtol=1e-5, atol=1e-6 * scale)
+
+
+def test_batch_collect_assemble_adjoint_match_oracle(rt, oracle_lib, setup):
+    """Batched image sources, responses and absorption gradient against the
+    FP64 oracle, job by job, from the batched launch's own hit sequences and
+    detections (sections "Image-sources" and the eq. for E_s): keys and counts
+    identical, positions and distances within 1e-9, band energies, histogram
+    bins and FIR band energies within 1e-4, the gradient (summed over the
+    jobs of each room, per material row) within 1e-5."""
+    rooms, scenes, jobs, b = setup
+    tr = rt.trace_batch(b, R)
+    isb = rt.collect_batch(b, tr)
+    gb = gpu_is_dict(isb)
+    L, c, fs = 24_000, 343.0, 48_000.0
+    taps = synth.octave_fir_taps(255)
+    alpha = np.concatenate([r.alpha for r in rooms]).astype(np.float32)
+    beta = rooms[0].beta
+    irb = rt.assemble_batch(b, isb, alpha, beta, c, fs, L, taps)
+    g = np.random.default_rng(3).standard_normal((b.n_rcv, 8)).astype(np.float32)
+    gab = rt.adjoint_batch(b, isb, alpha, beta, c, fs, L, g).cpu().numpy()
+    hs = tr.hit_seq.cpu().numpy()
+    det = tr.detections().cpu().numpy()
+    band = irb.band_energy.cpu().numpy().astype(np.float64)
+    hist = irb.hist.cpu().numpy().astype(np.float64)
+    bir = irb.band_ir.cpu().numpy().astype(np.float64)
+    grad_ref = np.zeros(gab.shape)
+    n_keys = 0
+    for j, job in enumerate(jobs):
+        room = rooms[job["scene"]]
+        lo, hi = b.ray_off[j], b.ray_off[j + 1]
+        r0 = int(b.rcv_off[j])
+        dj = det[(det[:, 0] >= lo) & (det[:, 0] < hi)].copy()
+        dj[:, 0] -= lo
+        dj[:, 2] -= r0
+        okeys = oracle_lib.image_source_keys(room.plane_id, hs[lo:hi], dj)
+        sub = {(k[0] - r0,) + k[1:]: v for k, v in gb.items() if k[0] == r0}
+        assert set(sub) == set(okeys), j
+        assert all(sub[k][0] == n for k, n in okeys.items()), j
+        tab = oracle_lib.image_sources(oracle_lib.OracleScene.of(room), job["src"], job["rcv"], okeys)
+        gp = np.array([sub[k][1] for k in tab["keys"]])
+        gd = np.array([sub[k][2] for k in tab["keys"]])
+        assert np.abs(gp - tab["pos"]).max() <= 1e-9 * max(1.0, float(np.abs(tab["pos"]).max())), j
+        assert np.abs(gd - tab["dist"]).max() <= 1e-9 * max(1.0, float(tab["dist"].max())), j
+        mop = material_of_plane(room)
+        ref = oracle_lib.assemble_ir(tab, job["n_rays"], 1, room.alpha, beta, mop, c, fs, L, taps)
+        assert np.all(np.abs(band[r0] - ref["band_energy"][0]) <= 1e-4 * ref["band_energy"][0]), j
+        big = ref["hist"][0] >= 1e-9 * ref["hist"][0].max(axis=1, keepdims=True)
+        assert np.all(np.abs(hist[r0] - ref["hist"][0])[big] <= 1e-4 * ref["hist"][0][big]), j
+        e_ref = (ref["band_ir"][0] ** 2).sum(-1)
+        assert np.all(np.abs((bir[r0] ** 2).sum(-1) - e_ref) <= 1e-4 * e_ref), j
+        m0 = int(b.mat_off[job["scene"]])
+        grad_ref[m0:m0 + room.n_mat] += oracle_lib.band_energy_grad(tab, job["n_rays"], 1, room.n_mat, room.alpha,
+                                                                    beta, mop, c, fs, L, g[r0:r0 + 1])
+        n_keys += len(okeys)
+    scale = np.abs(grad_ref).max()
+    assert scale > 0
+    assert np.allclose(gab, grad_ref, rtol=1e-5, atol=1e-6 * scale)
+    _say("batch vs oracle: %d jobs, %d image sources, gradient scale %.3e" % (len(jobs), n_keys, scale))
 
 
 def test_graph_replay_matches_eager(rt, setup):

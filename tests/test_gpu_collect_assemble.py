@@ -197,73 +197,70 @@ def test_band_energy_autograd_and_finite_differences(rt, c1):
     assert np.allclose(grad, fd, rtol=1e-2, atol=1e-2 * scale)
 
 
-def _full_size_tables(rt, oracle_lib, s, sc, R, mpl, mirror_rows, seed):
-    """Trace every ray of the configuration, collect and assemble, then check
-    properties that hold at any size: counts add up to the detections, keys
-    are distinct, the positions of `mirror_rows` seeded rows (all rows if
-    None) are the source mirrored (FP64) through their keys' planes taken from
-    the mesh, distances match positions, and the band energies are the sums
-    over the table of n/N e^(-beta d) prod(1 - alpha) over the sources that
-    arrive within the response (1e-4 relative).  Returns (n_is, n_det, max rel)."""
+def _full_size_tables(rt, oracle_lib, s, sc, R, mpl):
+    """Trace every ray of the configuration (the benchmarked launch), collect
+    and assemble its image sources and response, and compare with the oracle
+    computed from the GPU's own hit sequences and detections (section
+    "Image-sources"): the oracle keys every detection, so keys and counts must
+    be identical; it mirrors the source through each key's planes, so
+    positions and distances must agree within 1e-9 (both FP64, different
+    order); from that table it assembles the response (FP64 histogram, sqrt,
+    direct 'same' FIR with the 4095 taps), so band energies, histogram bins
+    (those >= 1e-9 of the band's largest) and FIR band energies must agree
+    within 1e-4.  Returns (n_is, n_det, max rel of the band energies, of the
+    FIR band energies)."""
     N = s.n_rays
     dirs = rt.fibonacci_directions(N, device="cuda:0")
     tr = rt.trace_rays(sc, dirs, s.rcv, R, src=s.src, max_path_length=mpl, det_cap=6 * N)
     isrc = rt.collect_image_sources(sc, s.src, s.rcv, tr)
-    key, cnt, pos, dist = [t.cpu().numpy() for t in isrc.valid()]
-    assert int(cnt.sum()) == int(tr.counters[0]) and len(key) > 10_000
-    kk = key[:, 1].astype(np.int64)
-    width = 2 + int(kk.max())
-    trimmed = np.where(np.arange(width)[None, :] < (2 + kk)[:, None], key[:, :width], -2)
-    assert len(np.unique(trimmed, axis=0)) == len(key)
-    pn, pp = oracle_lib.OracleScene.of(s).planes()
-    rcv = s.rcv.astype(np.float64)
-    src = np.asarray(s.src, np.float64)
-    scale = float(np.abs(pos).max())
-    rows = np.arange(len(key)) if mirror_rows is None else \
-        np.random.default_rng(seed).choice(len(key), mirror_rows, replace=False)
-    for i in rows:
-        r, p, d = key[i], pos[i], dist[i]
-        m, k = int(r[0]), int(r[1])
-        x = src.copy()
-        for j in range(k):
-            q = int(r[2 + j])
-            x = x - 2.0 * np.dot(x - pp[q], pn[q]) * pn[q]
-        assert np.abs(x - p).max() <= 1e-9 * scale
-        assert abs(np.linalg.norm(p - rcv[m, :3]) - d) <= 1e-12 * max(d, 1.0)
+    g = gpu_is_dict(isrc)
+    n_det = int(tr.counters[0])
+    assert sum(v[0] for v in g.values()) == n_det and len(g) > 10_000
+    hs = tr.hit_seq.cpu().numpy()
+    det = tr.detections().cpu().numpy()
+    _say("  %d detections, %d GPU image sources; keying on the CPU" % (n_det, len(g)))
+    okeys = oracle_lib.image_source_keys(s.plane_id, hs, det)
+    assert set(g) == set(okeys)
+    assert all(g[k][0] == n for k, n in okeys.items())
+    tab = oracle_lib.image_sources(oracle_lib.OracleScene.of(s), s.src, s.rcv, okeys)
+    gp = np.array([g[k][1] for k in tab["keys"]])
+    gd = np.array([g[k][2] for k in tab["keys"]])
+    scale = float(np.abs(tab["pos"]).max())
+    assert np.abs(gp - tab["pos"]).max() <= 1e-9 * scale
+    assert np.all(np.abs(gd - tab["dist"]) <= 1e-9 * np.maximum(tab["dist"], 1.0))
     taps = synth.octave_fir_taps(4095)
-    ir = rt.assemble_ir(sc, isrc, N, len(s.rcv), s.alpha, s.beta, s.c, s.fs, s.ir_len, taps)
-    mop = material_of_plane(s)
-    one_minus = np.vstack([1.0 - np.asarray(s.alpha, np.float64), np.ones((1, 8))])   # last row: no plane
-    beta = np.asarray(s.beta, np.float64)
-    want = np.zeros((len(s.rcv), 8))
-    inside = np.floor(dist * s.fs / s.c) < s.ir_len
-    for c0 in range(0, len(key), 50_000):
-        sl = slice(c0, c0 + 50_000)
-        pl = key[sl, 2:2 + R].astype(np.int64)
-        live = np.arange(pl.shape[1])[None, :] < kk[sl, None]
-        mat = np.where(live, mop[np.where(live, pl, 0)], len(one_minus) - 1)
-        e = (cnt[sl] / N)[:, None] * np.exp(-beta[None, :] * dist[sl, None]) * one_minus[mat].prod(axis=1)
-        e[~inside[sl]] = 0.0
-        np.add.at(want, key[sl, 0], e)
-    got = ir.band_energy.cpu().numpy().astype(np.float64)
-    rel = float(np.max(np.abs(got - want) / np.maximum(want, 1e-30)))
-    assert np.all(np.abs(got - want) <= 1e-4 * np.abs(want) + 1e-30)
-    return len(key), int(cnt.sum()), rel
+    n_rcv = len(s.rcv)
+    ir = rt.assemble_ir(sc, isrc, N, n_rcv, s.alpha, s.beta, s.c, s.fs, s.ir_len, taps)
+    ref = oracle_lib.assemble_ir(tab, N, n_rcv, s.alpha, s.beta, material_of_plane(s), s.c, s.fs, s.ir_len, taps)
+    be = ir.band_energy.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(be - ref["band_energy"]) <= 1e-4 * ref["band_energy"])
+    H = ir.hist.cpu().numpy().astype(np.float64)
+    big = ref["hist"] >= 1e-9 * ref["hist"].max(axis=2, keepdims=True)
+    assert big.any() and np.all(np.abs(H - ref["hist"])[big] <= 1e-4 * ref["hist"][big])
+    e_gpu = (ir.band_ir.cpu().numpy().astype(np.float64) ** 2).sum(-1)
+    e_ref = (ref["band_ir"] ** 2).sum(-1)
+    assert np.all(np.abs(e_gpu - e_ref) <= 1e-4 * e_ref)
+    rel_b = float(np.max(np.abs(be - ref["band_energy"]) / ref["band_energy"]))
+    rel_f = float(np.max(np.abs(e_gpu - e_ref) / e_ref))
+    return len(g), n_det, rel_b, rel_f
 
 
 def test_theater_full_size_image_sources_and_bands(rt, oracle_lib):
     """The benchmarked trace (436,120 triangles, 10^6 rays, R = 60, 8
-    receivers, 2 s response): every image-source row checked."""
+    receivers, 2 s response at 48 kHz: L = 96,000, K = 4095): the whole
+    image-source set and response against the oracle."""
     s = synth.theater_c3()
     sc = rt.Scene.from_synth(s, device="cuda:0")
-    n_is, n_det, rel = _full_size_tables(rt, oracle_lib, s, sc, s.max_reflections, s.max_path_length, None, 0)
-    _say("theater full size: %d image sources, %d detections, band energies max rel %.1e" % (n_is, n_det, rel))
+    n_is, n_det, rb, rf = _full_size_tables(rt, oracle_lib, s, sc, s.max_reflections, s.max_path_length)
+    _say("theater full size: %d image sources, %d detections; band energies max rel %.1e, FIR band energies "
+         "(L = 96,000, K = 4095) max rel %.1e" % (n_is, n_det, rb, rf))
 
 
 def test_jittered_box_full_size_image_sources_and_bands(rt, oracle_lib, c2):
     """The 100k-triangle jittered box at full size (10^6 rays, R = 50, 3
-    receivers, 1 s response, plane id = triangle id): 3,000 seeded rows
-    mirrored, every row in the band energies."""
+    receivers, 1 s response, plane id = triangle id): the whole image-source
+    set and response against the oracle."""
     s, sc = c2
-    n_is, n_det, rel = _full_size_tables(rt, oracle_lib, s, sc, s.max_reflections, s.max_path_length, 3_000, 22)
-    _say("jittered box full size: %d image sources, %d detections, band energies max rel %.1e" % (n_is, n_det, rel))
+    n_is, n_det, rb, rf = _full_size_tables(rt, oracle_lib, s, sc, s.max_reflections, s.max_path_length)
+    _say("jittered box full size: %d image sources, %d detections; band energies max rel %.1e, FIR band energies "
+         "max rel %.1e" % (n_is, n_det, rb, rf))

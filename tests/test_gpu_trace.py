@@ -59,10 +59,11 @@ def test_fibonacci_matches_oracle(rt, oracle_lib, n):
 
 def test_build_tree_reports(rt, scenes):
     for name, (s, sc) in scenes.items():
-        _say("scene", name, sc.n_tri, sc.n_nodes, sc.depth, sc.n_mat)
+        _say("scene", name, sc.n_tri, sc.n_ref, sc.n_nodes, sc.depth, sc.n_mat)
         assert sc.n_tri == s.n_tri and sc.n_mat == s.n_mat
         assert abs(sc.diag - s.diag()) < 1e-5 * s.diag()
-        assert 1 <= sc.n_nodes <= s.n_tri and 1 <= sc.depth <= 64
+        assert s.n_tri <= sc.n_ref <= 64 * s.n_tri
+        assert 1 <= sc.n_nodes <= sc.n_ref and 1 <= sc.depth <= 64
 
 
 def test_build_tree_rejects_bad_meshes(rt):
