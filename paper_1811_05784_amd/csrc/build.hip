@@ -11,8 +11,9 @@
 //
 // Before the tree is built, thin triangles are cut into references (early
 // split clipping, Ernst and Greiner 2007): a triangle whose bounding box has
-// more than kEscTau times the surface of the triangle itself is cut into k
-// slabs along the longest side of its box, and each reference carries the
+// a surface above kEscTau times twice the triangle's area (a flat right
+// triangle in an axis plane has 2) is cut into k slabs along the longest side
+// of its box, and each reference carries the
 // box of its piece only.  Fans of sliver triangles (a ring mesh around its
 // centre) otherwise give hundreds of overlapping boxes around one point, and
 // a query through that point tests every one of them.  A triangle may thus
@@ -295,7 +296,7 @@ __global__ void k_morton(const float* __restrict__ ref_box, int64_t nr, const ui
 // ---------------------------------------------------------------------------
 // early split clipping
 // ---------------------------------------------------------------------------
-constexpr double kEscTau = 8.0;   // box surface / (2 x triangle area) above which a triangle is cut
+constexpr double kEscTau = 16.0;  // box surface / (2 x triangle area) above which a triangle is cut
 constexpr int kEscMax = 64;       // most references per triangle
 
 // The triangle's vertices in FP64, or false when its indices or coordinates
@@ -385,31 +386,39 @@ __global__ void k_esc_count(const float* __restrict__ vtx, int64_t nv, const int
     cnt[t] = esc_vertices(vtx, nv, tri, t, p) ? (uint32_t)esc_slabs(p, ax, lo, ext) : 1u;
 }
 
-// References of triangle t at [off[t], off[t+1]): an unsplit triangle keeps
-// its FP32 box; piece i of k is the triangle clipped to slab i of its box's
-// longest side (FP64), its box rounded outward to FP32 and widened by
-// `margin` (8 units in the last place of the scene's extent: the FP32
-// watertight test decides hits within a few such units of an edge, and a
-// cut adds box faces that the triangle's own box did not have).
-__global__ void k_esc_emit(const float* __restrict__ vtx, int64_t nv, const int3* __restrict__ tri, int64_t nt,
-                           const uint32_t* __restrict__ off, const uint32_t* __restrict__ bounds,
-                           float* __restrict__ ref_box, uint32_t* __restrict__ ref_tri) {
+// Triangle of every reference: t at off[t] .. off[t+1] - 1.
+__global__ void k_esc_owner(int64_t nt, const uint32_t* __restrict__ off, uint32_t* __restrict__ ref_tri) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nt) return;
-    const int64_t r0 = off[t];
+    for (uint32_t r = off[t]; r < off[t + 1]; r++) ref_tri[r] = (uint32_t)t;
+}
+
+// Reference r: piece i of triangle t = ref_tri[r] (one thread per reference,
+// so triangles cut into many pieces do not hold up a wavefront).  An unsplit triangle keeps its FP32 box;
+// piece i of k is the triangle clipped to slab i of its box's longest side
+// (FP64), its box rounded outward to FP32 and widened by `margin` (8 units in
+// the last place of the scene's extent: the FP32 watertight test decides hits
+// within a few such units of an edge, and a cut adds box faces that the
+// triangle's own box did not have).
+__global__ void k_esc_emit(const float* __restrict__ vtx, int64_t nv, const int3* __restrict__ tri, int64_t nt,
+                           const uint32_t* __restrict__ off, int64_t nr, const uint32_t* __restrict__ bounds,
+                           const uint32_t* __restrict__ ref_tri, float* __restrict__ ref_box) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nr) return;
+    const int64_t t = ref_tri[r];
+    if (t >= nt) return;
+    const int i = (int)(r - (int64_t)off[t]);
     const int k = (int)(off[t + 1] - off[t]);
     double p[3][3];
     if (!esc_vertices(vtx, nv, tri, t, p)) {
-        for (int c = 0; c < 6; c++) ref_box[6 * r0 + c] = 0.f;
-        ref_tri[r0] = (uint32_t)t;
+        for (int c = 0; c < 6; c++) ref_box[6 * r + c] = 0.f;
         return;
     }
     if (k == 1) {
         for (int c = 0; c < 3; c++) {
-            ref_box[6 * r0 + c] = (float)fmin(p[0][c], fmin(p[1][c], p[2][c]));
-            ref_box[6 * r0 + 3 + c] = (float)fmax(p[0][c], fmax(p[1][c], p[2][c]));
+            ref_box[6 * r + c] = (float)fmin(p[0][c], fmin(p[1][c], p[2][c]));
+            ref_box[6 * r + 3 + c] = (float)fmax(p[0][c], fmax(p[1][c], p[2][c]));
         }
-        ref_tri[r0] = (uint32_t)t;
         return;
     }
     int ax;
@@ -418,30 +427,26 @@ __global__ void k_esc_emit(const float* __restrict__ vtx, int64_t nv, const int3
     double scene = 0.0;
     for (int c = 0; c < 3; c++) scene = fmax(scene, (double)funord(bounds[3 + c]) - (double)funord(bounds[c]));
     const double margin = scene * 0x1p-20;
-    for (int i = 0; i < k; i++) {
-        double q1[4][3], q2[5][3];
-        int m = 3;
-        const double(*cur)[3] = p;
-        if (i > 0) {
-            m = esc_clip(cur, m, ax, lo + ext * (double)i / (double)k, false, q1, 4);
-            cur = q1;
-        }
-        if (i + 1 < k) {
-            m = esc_clip(cur, m, ax, lo + ext * (double)(i + 1) / (double)k, true, q2, 5);
-            cur = q2;
-        }
-        double bl[3] = {INFINITY, INFINITY, INFINITY}, bh[3] = {-INFINITY, -INFINITY, -INFINITY};
-        for (int j = 0; j < m; j++)
-            for (int c = 0; c < 3; c++) {
-                bl[c] = fmin(bl[c], cur[j][c]);
-                bh[c] = fmax(bh[c], cur[j][c]);
-            }
-        const int64_t r = r0 + i;
+    double q1[4][3], q2[5][3];
+    int m = 3;
+    const double(*cur)[3] = p;
+    if (i > 0) {
+        m = esc_clip(cur, m, ax, lo + ext * (double)i / (double)k, false, q1, 4);
+        cur = q1;
+    }
+    if (i + 1 < k) {
+        m = esc_clip(cur, m, ax, lo + ext * (double)(i + 1) / (double)k, true, q2, 5);
+        cur = q2;
+    }
+    double bl[3] = {INFINITY, INFINITY, INFINITY}, bh[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int j = 0; j < m; j++)
         for (int c = 0; c < 3; c++) {
-            ref_box[6 * r + c] = m > 0 ? round_down(bl[c] - margin) : INFINITY;
-            ref_box[6 * r + 3 + c] = m > 0 ? round_up(bh[c] + margin) : -INFINITY;
+            bl[c] = fmin(bl[c], cur[j][c]);
+            bh[c] = fmax(bh[c], cur[j][c]);
         }
-        ref_tri[r] = (uint32_t)t;
+    for (int c = 0; c < 3; c++) {
+        ref_box[6 * r + c] = m > 0 ? round_down(bl[c] - margin) : INFINITY;
+        ref_box[6 * r + 3 + c] = m > 0 ? round_up(bh[c] + margin) : -INFINITY;
     }
 }
 
@@ -769,7 +774,7 @@ __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
 __global__ void k_init_bounds(uint32_t* b, uint32_t* info) {
     const int t = threadIdx.x;
     if (t < 12) b[t] = (t % 6) < 3 ? 0xFFFFFFFFu : 0u;
-    if (t < 4) info[t] = 0;
+    if (t < 8) info[t] = 0;
 }
 
 inline int blocks(int64_t n, int t = 256) { return (int)((n + t - 1) / t); }
@@ -833,7 +838,7 @@ extern "C" int rt_build_tree(const float* vtx, int64_t n_vtx, const int32_t* tri
     float* tri_box = tmp.get<float>(6 * nt);
     float* cen = tmp.get<float>(3 * nt);
     uint32_t* bounds = tmp.get<uint32_t>(12);
-    uint32_t* info = tmp.get<uint32_t>(4);
+    uint32_t* info = tmp.get<uint32_t>(8);   // [0] errors [1] max material [2] depth [3] 4-wide nodes [4] references
     uint32_t* prep_part = tmp.get<uint32_t>(14 * (int64_t)blocks(nt));
     int32_t* prep = tmp.get<int32_t>(nt);
     uint32_t* ref_cnt = tmp.get<uint32_t>(nt);
@@ -856,10 +861,10 @@ extern "C" int rt_build_tree(const float* vtx, int64_t n_vtx, const int32_t* tri
     hipLaunchKernelGGL(k_esc_count, dim3(blocks(nt)), dim3(256), 0, st, vtx, n_vtx, (const int3*)tri, nt, ref_cnt);
     int rc = exclusive_scan_u32(s->ws, ref_cnt, ref_off, nt, nullptr, st);
     if (rc) return fail(rc);
+    hipLaunchKernelGGL(k_copy_u32, dim3(1), dim3(1), 0, st, ref_off + nt, info + 4);
     RT_HIP(hipGetLastError());
-    uint32_t h_info[4], h_bounds[12], h_nr = 0;
+    uint32_t h_info[5], h_bounds[12];
     RT_HIP(hipMemcpyAsync(h_info, info, sizeof(h_info), hipMemcpyDeviceToHost, st));
-    RT_HIP(hipMemcpyAsync(&h_nr, ref_off + nt, sizeof(h_nr), hipMemcpyDeviceToHost, st));
     RT_HIP(hipStreamSynchronize(st));
     if (h_info[0]) {
         set_error("rt_build_tree: %s", err_text(h_info[0]));
@@ -867,7 +872,7 @@ extern "C" int rt_build_tree(const float* vtx, int64_t n_vtx, const int32_t* tri
                            !(h_info[0] & (kErrIndex | kErrPlaneRange | kErrMaterial));
         return fail(degen ? RT_EDEGENERATE : RT_EINVAL);
     }
-    const int64_t nr = h_nr;
+    const int64_t nr = h_info[4];
     RT_CHECK(nr >= nt && nr < kMaxTris, RT_EINVAL, "rt_build_tree: %lld references (at most 2^27)", (long long)nr);
     const int64_t n_in = nr - 1;
     const bool single = n_in == 0 || nr <= leaf;
@@ -886,8 +891,9 @@ extern "C" int rt_build_tree(const float* vtx, int64_t n_vtx, const int32_t* tri
         set_error("rt_build_tree: out of device memory");
         return fail(RT_ENOMEM);
     }
-    hipLaunchKernelGGL(k_esc_emit, dim3(blocks(nt)), dim3(256), 0, st, vtx, n_vtx, (const int3*)tri, nt, ref_off,
-                       bounds, ref_box, ref_tri);
+    hipLaunchKernelGGL(k_esc_owner, dim3(blocks(nt)), dim3(256), 0, st, nt, ref_off, ref_tri);
+    hipLaunchKernelGGL(k_esc_emit, dim3(blocks(nr)), dim3(256), 0, st, vtx, n_vtx, (const int3*)tri, nt, ref_off, nr,
+                       bounds, ref_tri, ref_box);
     hipLaunchKernelGGL(k_morton, dim3(blocks(nr)), dim3(256), 0, st, ref_box, nr, bounds, codes0);
     int which = 0;
     rc = radix_sort_pairs(s->ws, codes0, ord0, codes1, ord1, nr, nullptr, 0, 3 * kMortonBits, st, &which, true);
