@@ -368,8 +368,9 @@ def run_rooms(args):
     tune = {}
     tr = rt.trace_batch(b, R, det_cap=2 * b.n_rays)
     if not args.no_tune:
-        space = {"waves_per_simd": [4], "blocks_per_cu": [0, 8], "fetch_threshold": [16, 32],
-                 "shade_threshold": [16]}
+        # coordinate descent over the launch tile, the ray-queue thresholds and the LDS stack depth
+        space = {"waves_per_simd": [4, 5], "blocks_per_cu": [0, 8], "fetch_threshold": [16, 32],
+                 "shade_threshold": [16, 32], "stack_depth": [8, 16, 32]}
         key = autotune.key_for(max(sc.n_tri for sc in scenes), b.n_rays)
         tune = autotune.tune(lambda st: rt.trace_batch(b, R, out=tr, check_capacity=False, **st), key,
                              space=space, repeats=1)

@@ -182,6 +182,9 @@ typedef struct {
                                   device int32[n_rays] (global ray ids in a batch): ray i writes
                                   row record_rows[i] (< 0: not recorded), so a few rays of a large
                                   launch can be recorded without changing the launch            */
+    int32_t stack_depth;       /* 0 = default (16); 8, 16 or 32: LDS traversal-stack entries per lane
+                                  (the stack spills to global memory beyond them; the cooperative
+                                  search's frontier holds stack_depth / 2 entries per lane)     */
 } rt_trace_params;
 
 /*
@@ -448,7 +451,7 @@ int rt_room_params(const float* hist, int32_t n_rcv, int64_t L, float fs, double
 int rt_room_params_noalloc(const float* hist, int32_t n_rcv, int64_t L, float fs, double* params, void* stream);
 
 /* Test hook for the exact-grouping path of rt_collect_image_sources: keep
- * only the low `bits` bits (1..64, default 32) of the 64-bit key hash so that
+ * only the low `bits` bits (1..64, default 48) of the 64-bit key hash so that
  * distinct keys collide.  Process-wide; not thread-safe with concurrent
  * collect calls.  Grouping stays exact at any setting (full-key comparison);
  * only speed changes. */

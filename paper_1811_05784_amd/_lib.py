@@ -27,7 +27,7 @@ class TraceParams(ctypes.Structure):
                 ("keep_order", I32), ("stats", P), ("rounds", I32), ("spill_threshold", I32),
                 ("waves_per_simd", I32), ("kernel_event_start", P),
                 ("kernel_event_stop", P), ("suspend_after", I32), ("min_beam_rays", I32),
-                ("xcd_pools", I32), ("coop_queries", I32), ("record_rows", P)]
+                ("xcd_pools", I32), ("coop_queries", I32), ("record_rows", P), ("stack_depth", I32)]
 
 
 class Job(ctypes.Structure):

@@ -141,7 +141,7 @@ def trace_rays(scene: Scene, dirs: torch.Tensor, rcv, max_reflections: int, src=
                stats: Optional[torch.Tensor] = None, rounds: int = 0, spill_threshold: int = 0,
                waves_per_simd: int = 0, kernel_events=None, suspend_after: int = 0,
                min_beam_rays: int = 0, xcd_pools: int = 0, coop_queries: int = 0,
-               record_rows=None) -> TraceResult:
+               record_rows=None, stack_depth: int = 0) -> TraceResult:
     """rt_trace_rays.  With check_capacity the call synchronises, and re-runs
     with a larger detection buffer if the first one overflowed.
     record_rows: with record_states, an int32 [n] map ray -> row of `states`
@@ -177,7 +177,8 @@ def trace_rays(scene: Scene, dirs: torch.Tensor, rcv, max_reflections: int, src=
     prm = TraceParams(int(max_reflections), float(max_path_length), int(bool(record_states)), int(fetch_threshold),
                       int(shade_threshold), int(blocks_per_cu), int(bool(keep_order)), _ptr(stats),
                       int(rounds), int(spill_threshold), int(waves_per_simd), *_event_ptrs(kernel_events),
-                      int(suspend_after), int(min_beam_rays), int(xcd_pools), int(coop_queries), _ptr(rrows))
+                      int(suspend_after), int(min_beam_rays), int(xcd_pools), int(coop_queries), _ptr(rrows),
+                      int(stack_depth))
     with torch.cuda.device(dev):
         check(lib.rt_trace_rays(scene.handle, src_h, _ptr(org), _ptr(dirs), _ptr(spl), _ptr(sln), n, _ptr(rcv_t),
                                 rcv_t.shape[0], ctypes.byref(prm), _ptr(out.hit_seq), _ptr(out.det),
@@ -194,7 +195,7 @@ def trace_rays(scene: Scene, dirs: torch.Tensor, rcv, max_reflections: int, src=
                               keep_order=keep_order, stats=stats, rounds=rounds,
                               spill_threshold=spill_threshold, waves_per_simd=waves_per_simd,
                               suspend_after=suspend_after, min_beam_rays=min_beam_rays, xcd_pools=xcd_pools,
-                              coop_queries=coop_queries, record_rows=rrows)
+                              coop_queries=coop_queries, record_rows=rrows, stack_depth=stack_depth)
     return out
 
 
@@ -423,7 +424,7 @@ def trace_batch(b: Batch, max_reflections: int, det_cap: Optional[int] = None, o
                       int(tune.get("rounds", 0)), int(tune.get("spill_threshold", 0)),
                       int(tune.get("waves_per_simd", 0)), *_event_ptrs(tune.get("kernel_events")),
                       int(tune.get("suspend_after", 0)), int(min_beam_rays), int(tune.get("xcd_pools", 0)), 0,
-                      _ptr(rrows))
+                      _ptr(rrows), int(tune.get("stack_depth", 0)))
     with torch.cuda.device(dev):
         check(lib.rt_trace_batch(b.handle, _ptr(b.rcv), ctypes.byref(prm), _ptr(out.hit_seq), _ptr(out.det),
                                  out.det.shape[0], _ptr(out.counters), _ptr(out.states), _stream(dev)),

@@ -1,11 +1,16 @@
 """Autotuner for the persistent trace launch.
 
-Times candidate launch settings (register budget = waves per SIMD,
-persistent workgroups per compute unit, fetch and shade thresholds of the
-wavefront loop) on the caller's own workload and keeps the fastest.  Results
-are cached in a JSON file keyed by (GPU architecture, log2 of the largest
-scene's triangle count, log2 of the ray count), so a later call with a
-similar workload reuses the choice without timing.
+Times candidate launch settings on the caller's own workload and keeps the
+fastest: the launch tile (register budget = waves per SIMD, persistent
+workgroups per compute unit), the ray queue (fetch threshold: idle lanes
+before a wavefront takes new rays from the pool; shade threshold: finished
+queries before it shades them) and the LDS traversal-stack depth per lane.
+The search is coordinate descent from the library defaults (each parameter
+in turn, the others held, two sweeps; repeated settings are timed once) or,
+on request, the whole product.  Results are cached in a JSON file keyed by
+(GPU architecture, log2 of the largest scene's triangle count, log2 of the
+ray count), so a later call with a similar workload reuses the choice
+without timing.
 
 The cache lives at $RTAC_TUNE_CACHE, else ~/.cache/rtac/autotune.json.
 """
@@ -25,7 +30,11 @@ DEFAULT_CANDIDATES = {
     "blocks_per_cu": [0, 8],
     "fetch_threshold": [8, 16, 32],
     "shade_threshold": [8, 16, 32],
+    "stack_depth": [8, 16, 32],
 }
+# library defaults (0 = the library's own choice), where coordinate descent starts
+DEFAULT_START = {"waves_per_simd": 4, "blocks_per_cu": 0, "fetch_threshold": 16, "shade_threshold": 16,
+                 "stack_depth": 16}
 
 
 def cache_path() -> str:
@@ -69,16 +78,9 @@ def candidates(space: Optional[Dict[str, List[int]]] = None) -> List[dict]:
     return [dict(zip(names, vals)) for vals in itertools.product(*[space[n] for n in names])]
 
 
-def tune(run: Callable[[dict], None], key: str, space: Optional[Dict[str, List[int]]] = None, repeats: int = 2,
-         use_cache: bool = True, verbose: bool = False) -> dict:
-    """Return the fastest setting for `run(setting)` (which must launch the
-    work on the current stream).  Each candidate is run once to warm up,
-    then timed `repeats` times with events; the median decides."""
-    cache = _load() if use_cache else {}
-    if use_cache and key in cache:
-        return dict(cache[key]["setting"])
-    best, best_ms, table = None, float("inf"), []
-    for setting in candidates(space):
+def _event_timer(run: Callable[[dict], None], repeats: int) -> Callable[[dict], float]:
+    """Median of `repeats` event-timed runs after one warm-up run."""
+    def timer(setting: dict) -> float:
         run(setting)
         torch.cuda.synchronize()
         times = []
@@ -90,14 +92,65 @@ def tune(run: Callable[[dict], None], key: str, space: Optional[Dict[str, List[i
             e1.record()
             torch.cuda.synchronize()
             times.append(e0.elapsed_time(e1))
-        ms = sorted(times)[len(times) // 2]
-        table.append((ms, setting))
-        if verbose:
-            print("autotune %s %.3f ms" % (setting, ms), flush=True)
-        if ms < best_ms:
-            best, best_ms = setting, ms
+        return sorted(times)[len(times) // 2]
+    return timer
+
+
+def search(timer: Callable[[dict], float], space: Dict[str, List[int]], method: str = "coordinate",
+           start: Optional[dict] = None, sweeps: int = 2, verbose: bool = False):
+    """Best setting of `space` under `timer(setting) -> ms` (lower is better)
+    and the table of timed settings.  "coordinate": from `start` (the first
+    value of each parameter if absent), each parameter in turn over its
+    values with the others held, `sweeps` times; "exhaustive": every
+    combination.  Every distinct setting is timed once."""
+    seen: Dict[tuple, float] = {}
+
+    def time_of(setting: dict) -> float:
+        k = tuple(sorted(setting.items()))
+        if k not in seen:
+            seen[k] = timer(setting)
+            if verbose:
+                print("autotune %s %.3f ms" % (setting, seen[k]), flush=True)
+        return seen[k]
+
+    if method == "exhaustive":
+        best = min(candidates(space), key=time_of)
+    elif method == "coordinate":
+        best = {n: (start[n] if start and n in start and start[n] in space[n] else space[n][0]) for n in sorted(space)}
+        best_ms = time_of(best)
+        for _ in range(sweeps):
+            changed = False
+            for n in sorted(space):
+                for v in space[n]:
+                    trial = dict(best)
+                    trial[n] = v
+                    ms = time_of(trial)
+                    if ms < best_ms:
+                        best, best_ms, changed = trial, ms, True
+            if not changed:
+                break
+    else:
+        raise ValueError("method must be 'coordinate' or 'exhaustive'")
+    table = sorted(((ms, dict(k)) for k, ms in seen.items()), key=lambda e: e[0])
+    return dict(best), table
+
+
+def tune(run: Callable[[dict], None], key: str, space: Optional[Dict[str, List[int]]] = None, repeats: int = 2,
+         use_cache: bool = True, verbose: bool = False, method: str = "coordinate",
+         timer: Optional[Callable[[dict], float]] = None) -> dict:
+    """Return the fastest setting for `run(setting)` (which must launch the
+    work on the current stream).  Each candidate is run once to warm up,
+    then timed `repeats` times with events; the median decides (`timer`
+    replaces that measurement)."""
+    cache = _load() if use_cache else {}
+    if use_cache and key in cache:
+        return dict(cache[key]["setting"])
+    space = space or DEFAULT_CANDIDATES
+    best, table = search(timer or _event_timer(run, repeats), space, method=method, start=DEFAULT_START,
+                         verbose=verbose)
     if use_cache:
         cache = _load()
-        cache[key] = {"setting": best, "ms": best_ms, "when": time.time(), "candidates": len(table)}
+        cache[key] = {"setting": best, "ms": table[0][0], "when": time.time(), "candidates": len(table),
+                      "method": method}
         _store(cache)
-    return dict(best)
+    return best

@@ -4,10 +4,13 @@
 // image source; all rays with the same reflection sequence land on the same
 // one and the receiver counts n of them (section "Image-sources").  The key
 // of a detection (ray, k, m) is (m, k, plane ids hit on segments 0..k-1).
-// Keys are hashed to 64 bits, sorted (stable radix sort), and split into
-// groups wherever the hash changes or a full comparison of the sequences
-// differs.  Equal hashes of different keys (vanishingly rare) are resolved
-// by a per-run insertion sort on the full key, so grouping is exact.  Each
+// Keys are hashed (64-bit mix), the low 48 bits sorted (stable radix sort,
+// six 8-bit passes), and split into groups wherever the hash changes or a
+// full comparison of the sequences differs.  Equal 48-bit hashes of
+// different keys (about n^2 / 2^49: 1e-3 for 10^6 distinct keys) are
+// resolved by a per-run insertion sort on the full key, so grouping is exact
+// at any hash width; a wide hash keeps those runs, and the single thread that
+// re-sorts each of them, away from heavily detected keys.  Each
 // group's position is the source mirrored through its planes in order (FP64).
 #include "common.h"
 
@@ -15,7 +18,7 @@ namespace rtac {
 
 namespace {
 
-int g_hash_bits = 32;   // key hash width (keys are compared in full); the test hook lowers it
+int g_hash_bits = 48;   // sorted hash width (keys are compared in full); the test hook lowers it
 
 __device__ inline uint64_t mix64(uint64_t x) {
     x ^= x >> 30;

@@ -40,7 +40,9 @@ namespace rtac {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kRing = 16;                 // LDS stack entries per lane
+// LDS stack entries per lane (template parameter kRing of the trace kernel):
+// 8, 16 (default) or 32; the ring spills to a per-lane global area in chunks.
+constexpr int kRingDefault = 16;
 constexpr int kSpillChunk = 8;
 
 enum : int { kIdle = 0, kQuery = 1, kDone = 2 };
@@ -195,6 +197,7 @@ struct Stack {
     int base, cnt, gsp;
 };
 
+template <int kRing>
 __device__ inline bool stack_push(Stack& s, int32_t* lds, int32_t* spill, int spill_n, int tid, int32_t item) {
     if (s.cnt == kRing) {
         if (s.gsp + kSpillChunk > spill_n) return false;
@@ -209,6 +212,7 @@ __device__ inline bool stack_push(Stack& s, int32_t* lds, int32_t* spill, int sp
 }
 
 // Returns false when the stack is empty.
+template <int kRing>
 __device__ inline bool stack_pop(Stack& s, int32_t* lds, const int32_t* spill, int tid, int32_t& item) {
     if (s.cnt == 0) {
         if (s.gsp == 0) return false;
@@ -244,7 +248,8 @@ __device__ inline void cswap(float& ta, int32_t& ra, float& tb, int32_t& rb) {
 // Nearest hit of one query by a group of G lanes (G = 64: the whole
 // wavefront; 32: one half, lanes li = 0..31 from lane gbase), breadth first
 // over a frontier kept in the group's columns of the LDS stack area (refs in
-// slots 0..7, entry distances in slots 8..15: 8 G entries).  Each step every
+// the first half of the kRing slots, entry distances in the second: kRing/2 G
+// entries).  Each step every
 // lane of the group takes one frontier item, the most recent first: an inner
 // node is slab-tested and every child whose box is hit joins the frontier
 // (far children first, so the nearest are taken next); a leaf has its
@@ -256,13 +261,13 @@ __device__ inline void cswap(float& ta, int32_t& ra, float& tb, int32_t& rb) {
 // the step bound is reached or a reference is out of range (for either group
 // of a wavefront); the owner then walks the query from the root, bounded by
 // the best hit found so far.
-template <int G>
+template <int G, int kRing>
 __device__ inline bool coop_search(const Ray& q, int32_t qlp, float& bt, int32_t& bid, int32_t& bj, int32_t* base_col,
                                    int li, int gbase, const Node4* nodes, const float4* tri, int32_t n_nodes,
                                    int32_t n_tri, int32_t max_steps) {
-    constexpr int kCap = 8 * G;
+    constexpr int kCap = (kRing / 2) * G;
     int32_t* fref = base_col;
-    float* ft = reinterpret_cast<float*>(base_col + 8 * kBlock);
+    float* ft = reinterpret_cast<float*>(base_col + (kRing / 2) * kBlock);
     auto fat = [](int k) { return (k / G) * kBlock + (k % G); };
     int nf = 1;
     if (li == 0) {
@@ -390,7 +395,7 @@ __device__ inline bool coop_search(const Ray& q, int32_t qlp, float& bt, int32_t
     return ok;
 }
 
-template <int kWavesPerEU, bool kBatch>
+template <int kWavesPerEU, bool kBatch, int kRing>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWavesPerEU, 8)))
 k_trace(TraceArgs a) {
     __shared__ int32_t lds_stack[kRing * kBlock];
@@ -616,10 +621,10 @@ k_trace(TraceArgs a) {
                 int32_t bid = __shfl(best_id, mo), bj = __shfl(best_j, mo);
                 bool ok;
                 if (n_act == 1) {
-                    ok = coop_search<64>(q, qlp, bt, bid, bj, lds_stack + (tid - lane), lane, 0, nodes, tri, n_nodes,
+                    ok = coop_search<64, kRing>(q, qlp, bt, bid, bj, lds_stack + (tid - lane), lane, 0, nodes, tri, n_nodes,
                                          n_tri, a.max_steps);
                 } else {
-                    ok = coop_search<32>(q, qlp, bt, bid, bj, lds_stack + (tid - lane) + 32 * g, lane & 31, 32 * g,
+                    ok = coop_search<32, kRing>(q, qlp, bt, bid, bj, lds_stack + (tid - lane) + 32 * g, lane & 31, 32 * g,
                                          nodes, tri, n_nodes, n_tri, a.max_steps);
                 }
                 // each owner takes its group's result
@@ -735,7 +740,7 @@ k_trace(TraceArgs a) {
 #pragma unroll
                 for (int sl = 3; sl >= 0; sl--)
                     if (tn[sl] < INFINITY && sl != ii && sl != li)
-                        ok &= stack_push(st, lds_stack, spill, a.spill_per_lane, tid, rf[sl]);
+                        ok &= stack_push<kRing>(st, lds_stack, spill, a.spill_per_lane, tid, rf[sl]);
                 leaf = li == 0 ? rf[0] : li == 1 ? rf[1] : li == 2 ? rf[2] : li == 3 ? rf[3] : kEmpty;
                 cur = ii == 0 ? rf[0] : ii == 1 ? rf[1] : ii == 2 ? rf[2] : ii == 3 ? rf[3] : kEmpty;
             } else {
@@ -773,7 +778,7 @@ k_trace(TraceArgs a) {
                     }
                 }
             }
-            if (cur == kEmpty) have = stack_pop(st, lds_stack, spill, tid, cur);
+            if (cur == kEmpty) have = stack_pop<kRing>(st, lds_stack, spill, tid, cur);
             if (!have) status = kDone;
             asm volatile("" ::"v"(touch));   // keeps the touch load
         }
@@ -1042,22 +1047,28 @@ __global__ void k_fibonacci(int64_t n, float* __restrict__ out) {
     fibonacci_dir(i, n, out + 3 * i);
 }
 
-void launch_trace(int occ, bool batch, unsigned nblk, hipStream_t st, const TraceArgs& a) {
-    if (batch) {
-        switch (occ) {
-            case 8: hipLaunchKernelGGL((k_trace<8, true>), dim3(nblk), dim3(kBlock), 0, st, a); break;
-            case 6: hipLaunchKernelGGL((k_trace<6, true>), dim3(nblk), dim3(kBlock), 0, st, a); break;
-            case 5: hipLaunchKernelGGL((k_trace<5, true>), dim3(nblk), dim3(kBlock), 0, st, a); break;
-            default: hipLaunchKernelGGL((k_trace<4, true>), dim3(nblk), dim3(kBlock), 0, st, a); break;
-        }
-    } else {
-        switch (occ) {
-            case 8: hipLaunchKernelGGL((k_trace<8, false>), dim3(nblk), dim3(kBlock), 0, st, a); break;
-            case 6: hipLaunchKernelGGL((k_trace<6, false>), dim3(nblk), dim3(kBlock), 0, st, a); break;
-            case 5: hipLaunchKernelGGL((k_trace<5, false>), dim3(nblk), dim3(kBlock), 0, st, a); break;
-            default: hipLaunchKernelGGL((k_trace<4, false>), dim3(nblk), dim3(kBlock), 0, st, a); break;
-        }
+template <bool kBatch, int kRing>
+void launch_trace_ring(int occ, unsigned nblk, hipStream_t st, const TraceArgs& a) {
+    switch (occ) {
+        case 8: hipLaunchKernelGGL((k_trace<8, kBatch, kRing>), dim3(nblk), dim3(kBlock), 0, st, a); break;
+        case 6: hipLaunchKernelGGL((k_trace<6, kBatch, kRing>), dim3(nblk), dim3(kBlock), 0, st, a); break;
+        case 5: hipLaunchKernelGGL((k_trace<5, kBatch, kRing>), dim3(nblk), dim3(kBlock), 0, st, a); break;
+        default: hipLaunchKernelGGL((k_trace<4, kBatch, kRing>), dim3(nblk), dim3(kBlock), 0, st, a); break;
     }
+}
+
+template <bool kBatch>
+void launch_trace_batch(int occ, int ring, unsigned nblk, hipStream_t st, const TraceArgs& a) {
+    switch (ring) {
+        case 8: launch_trace_ring<kBatch, 8>(occ, nblk, st, a); break;
+        case 32: launch_trace_ring<kBatch, 32>(occ, nblk, st, a); break;
+        default: launch_trace_ring<kBatch, kRingDefault>(occ, nblk, st, a); break;
+    }
+}
+
+void launch_trace(int occ, int ring, bool batch, unsigned nblk, hipStream_t st, const TraceArgs& a) {
+    if (batch) launch_trace_batch<true>(occ, ring, nblk, st, a);
+    else launch_trace_batch<false>(occ, ring, nblk, st, a);
 }
 
 }  // namespace
@@ -1090,6 +1101,7 @@ int run_trace(rt_scene* ws, TraceArgs& a, const rt_trace_params* p, int depth, i
     const int wps = p->waves_per_simd;
     const int occ = (wps == 4 || wps == 5 || wps == 6 || wps == 8) ? wps : 4;
     const int bpc = p->blocks_per_cu > 0 ? p->blocks_per_cu : occ;
+    const int ring = p->stack_depth > 0 ? p->stack_depth : kRingDefault;
     int64_t nblk = (int64_t)device_sm_count() * bpc;
     const int64_t need = (n_rays + kBlock - 1) / kBlock;
     if (nblk > need) nblk = need;
@@ -1160,7 +1172,7 @@ int run_trace(rt_scene* ws, TraceArgs& a, const rt_trace_params* p, int depth, i
         a.suspend_k = suspend && rd == 0 ? p->suspend_after : 0;
         a.spill_thr = suspend ? 0 : spill_thr;
         if (rd > 0) a.order = nullptr;
-        launch_trace(occ, a.jobs != nullptr, (unsigned)nblk, st, a);
+        launch_trace(occ, ring, a.jobs != nullptr, (unsigned)nblk, st, a);
     }
     RT_HIP(hipGetLastError());
     if (p->kernel_event_stop) RT_HIP(hipEventRecord((hipEvent_t)p->kernel_event_stop, st));
@@ -1175,6 +1187,8 @@ int check_params(const rt_trace_params* p) {
     RT_CHECK(p->min_beam_rays >= 0, RT_EINVAL, "min_beam_rays must be >= 0");
     RT_CHECK(p->xcd_pools >= -1 && p->xcd_pools <= 0, RT_EINVAL, "xcd_pools must be 0 or -1");
     RT_CHECK(p->coop_queries >= -1 && p->coop_queries <= 0, RT_EINVAL, "coop_queries must be 0 or -1");
+    RT_CHECK(p->stack_depth == 0 || p->stack_depth == 8 || p->stack_depth == 16 || p->stack_depth == 32, RT_EINVAL,
+             "stack_depth must be 0 (default 16), 8, 16 or 32");
     return RT_OK;
 }
 

@@ -53,7 +53,7 @@ def test_argument_validation_without_device(lib):
                                       None, None, None) == -1
     assert lib.rt_debug_set_hash_bits(0) == -1
     assert lib.rt_debug_set_hash_bits(64) == 0
-    assert lib.rt_debug_set_hash_bits(32) == 0   # back to the default
+    assert lib.rt_debug_set_hash_bits(48) == 0   # back to the default
     assert lib.rt_scene_destroy(None) == 0
 
 

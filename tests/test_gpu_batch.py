@@ -218,7 +218,8 @@ def test_autotuner_picks_and_caches(rt, setup, tmp_path, monkeypatch):
     from paper_1811_05784_amd import autotune
     rooms, scenes, jobs, b = setup
     monkeypatch.setenv("RTAC_TUNE_CACHE", str(tmp_path / "tune.json"))
-    space = {"waves_per_simd": [4], "blocks_per_cu": [0, 8], "fetch_threshold": [8, 16], "shade_threshold": [16]}
+    space = {"waves_per_simd": [4], "blocks_per_cu": [0, 8], "fetch_threshold": [8, 16], "shade_threshold": [16],
+             "stack_depth": [8, 16, 32]}
     out = rt.trace_batch(b, R, det_cap=4 * b.n_rays)
     calls = []
 
@@ -232,10 +233,12 @@ def test_autotuner_picks_and_caches(rt, setup, tmp_path, monkeypatch):
     n = len(calls)
     again = autotune.tune(run, key, space=space)
     assert again == best and len(calls) == n            # served from the cache
-    # the chosen setting gives the same result
+    # the chosen setting, and every stack depth, give the same result
     ref = rt.trace_batch(b, R).hit_seq
     got = rt.trace_batch(b, R, **best).hit_seq
     assert torch.equal(ref, got)
+    for depth in (8, 32):
+        assert torch.equal(ref, rt.trace_batch(b, R, stack_depth=depth).hit_seq), depth
 
 
 def test_batch_suspension_unchanged(rt, setup):

@@ -85,7 +85,7 @@ def test_collect_collisions_resolved_exactly(rt, oracle_lib, c2):
                                                        max_reflections=10))
             assert set(got) == set(ref) and all(got[k][0] == ref[k][0] for k in ref)
     finally:
-        lib.rt_debug_set_hash_bits(32)
+        lib.rt_debug_set_hash_bits(48)
     _check_is(oracle_lib, s, rt.collect_image_sources(sc, s.src, s.rcv, None, hit_seq=hs, det=det,
                                                       max_reflections=10), hs, det)
 

@@ -245,11 +245,16 @@ def _sorted_det(tr):
                                          ("c1", 20, 10_000, dict(coop_queries=-1)),
                                          ("c2", 20, 50_000, dict(coop_queries=-1)),
                                          ("c3", 60, 1_000_000, dict(coop_queries=-1)),
-                                         ("c3", 60, 1_000_000, dict(coop_queries=-1, xcd_pools=-1))])
+                                         ("c3", 60, 1_000_000, dict(coop_queries=-1, xcd_pools=-1)),
+                                         ("c3", 60, 1_000_000, dict(stack_depth=8)),
+                                         ("c3", 60, 1_000_000, dict(stack_depth=32, waves_per_simd=5)),
+                                         ("c2", 20, 50_000, dict(stack_depth=8, waves_per_simd=5)),
+                                         ("c2", 20, 50_000, dict(stack_depth=32))])
 def test_scheduling_leaves_results_unchanged(rt, scenes, name, R, n, kw):
-    """Suspension into a second launch, continuation rounds, per-XCD pools and
-    single queries searched by whole wavefronts reorder work only: hit
-    sequences, detections and counters are identical."""
+    """Suspension into a second launch, continuation rounds, per-XCD pools,
+    single queries searched by whole wavefronts, other register budgets and
+    LDS stack depths (8: the cooperative frontier holds 4 entries per lane)
+    reorder work only: hit sequences, detections and counters are identical."""
     s, sc = scenes[name]
     dirs = rt.fibonacci_directions(n, device="cuda:0")
     mpl = s.max_path_length if name == "c3" else 0.0
