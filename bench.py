@@ -482,6 +482,12 @@ def run_surrogate(args):
     pred = net.forward(xe)
     e_mlp = sg.band_rms_db(pred, te).cpu().numpy()
     e_base = sg.band_rms_db(be, te).cpu().numpy()
+    # fair predictor without the network: the training rooms' mean decay curve
+    tm0 = tgt[:n_train].cpu().numpy().reshape(-1, 8, sg.TARGET_BINS).astype(np.float64)
+    mm0 = mask[:n_train].cpu().numpy().reshape(-1, 8, sg.TARGET_BINS).astype(np.float64)
+    mc0 = np.where(mm0.sum(0) > 0, (tm0 * mm0).sum(0) / np.maximum(mm0.sum(0), 1.0), tm0.mean(0))
+    e_mean_ho = sg.band_rms_db(torch.as_tensor(np.broadcast_to(mc0, (len(te), 8, sg.TARGET_BINS))
+                                               .reshape(len(te), -1).astype(np.float32), device=dev), te).cpu().numpy()
     # timing on the held-out rooms: full 60-bounce trace vs 8 bounces + MLP
     held = synth.surrogate_rooms(n_rooms=n_rooms, first=n_train)
     timers = {}
@@ -504,6 +510,39 @@ def run_surrogate(args):
     t_mlp = e0.elapsed_time(e1)
     t_full = sum(timers[R_full]) + t_edc
     t_sur = sum(timers[sg.EARLY_ORDER]) + t_mlp
+    # the configuration's evaluation scene: the 436k-triangle theater, 10^6 rays, its 8 receivers;
+    # 8-bounce trace + network against the full 60-bounce trace (the training rooms are closed
+    # lattice rooms, the theater an open-air scene: a shift of domain, reported as measured)
+    th = synth.theater_c3()
+    h_full_th, h_early_th = sg.room_histograms([th], th.n_rays, (R_full, sg.EARLY_ORDER),
+                                               (sg.TARGET_BINS, sg.FEAT_BINS), T=T, device=dev, rooms_per_batch=1,
+                                               spans=(T, sg.FEAT_SECONDS))      # warm-up
+    timers_th = {}
+    h_full_th, h_early_th = sg.room_histograms([th], th.n_rays, (R_full, sg.EARLY_ORDER),
+                                               (sg.TARGET_BINS, sg.FEAT_BINS), T=T, device=dev, rooms_per_batch=1,
+                                               timers=timers_th, spans=(T, sg.FEAT_SECONDS))
+    n_th = h_full_th.shape[0]
+    full_th = sg.edc_db(h_full_th).reshape(n_th, -1)
+    e0.record()
+    pred_th = net.forward(sg.hist_features(h_early_th).reshape(n_th, -1).contiguous())
+    e1.record()
+    torch.cuda.synchronize()
+    t_mlp_th = e0.elapsed_time(e1)
+    e_th = sg.band_rms_db(pred_th, full_th).cpu().numpy()
+    tm = tgt[:n_train].cpu().numpy().reshape(-1, 8, sg.TARGET_BINS).astype(np.float64)
+    mm = mask[:n_train].cpu().numpy().reshape(-1, 8, sg.TARGET_BINS).astype(np.float64)
+    mean_curve = np.where(mm.sum(0) > 0, (tm * mm).sum(0) / np.maximum(mm.sum(0), 1.0), tm.mean(0))
+    pred_mean_th = torch.as_tensor(np.broadcast_to(mean_curve, (n_th, 8, sg.TARGET_BINS)).reshape(n_th, -1)
+                                   .astype(np.float32), device=dev)
+    e_th_mean = sg.band_rms_db(pred_mean_th, full_th).cpu().numpy()
+    theater = {"receivers": n_th, "rays": th.n_rays, "triangles": th.n_tri,
+               "full_trace_ms": sum(timers_th[R_full]), "surrogate_ms": sum(timers_th[sg.EARLY_ORDER]) + t_mlp_th,
+               "speedup": sum(timers_th[R_full]) / (sum(timers_th[sg.EARLY_ORDER]) + t_mlp_th),
+               "rms_db_mlp": {"mean": float(e_th.mean()), "per_receiver": [float(v) for v in e_th.mean(1)],
+                              "frac_bands_le_0.5dB": float((e_th <= 0.5).mean())},
+               "rms_db_training_mean_curve": float(e_th_mean.mean()),
+               "note": "goal 0.5 dB per band: not met; trained on closed lattice rooms, evaluated on the "
+                       "open-air theater (no ceiling)"}
     # one training step (forward + backward + Adam) at batch 256: matrix-core rate
     xb, tb, mb = x[:256].contiguous(), tgt[:256].contiguous(), mask[:256].contiguous()
     for _ in range(3):
@@ -551,6 +590,8 @@ def run_surrogate(args):
                        "per_band_mean": [float(v) for v in e_mlp.mean(0)],
                        "frac_bands_le_0.5dB": float((e_mlp <= 0.5).mean())},
         "rms_db_8_bounce_only": {"mean": float(e_base.mean()), "median": float(np.median(e_base))},
+        "rms_db_training_mean_curve": float(e_mean_ho.mean()),
+        "theater_436k_1e6_rays": theater,
         "train_loss_first_last": [losses[0], losses[-1]], "data_s": data_s, "train_s": train_s,
         "roofline": {"bound": "mfma", "achieved": tflops, "peak": 2500.0, "unit": "TFLOP/s",
                      "frac": tflops / 2500.0, "traffic": None, "kernel": "MLP train step (batch 256)",

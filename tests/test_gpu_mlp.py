@@ -282,3 +282,84 @@ def test_pipeline_small_rooms(sg):
     assert losses[-1] < losses[0]
     err = sg.band_rms_db(net.forward(x), tgt)
     assert torch.isfinite(err).all()
+
+
+def _bf16_up(v):
+    """Smallest-magnitude value k 2^e (|k| < 256, so exact in BF16) with
+    |value| >= |v|, same sign."""
+    v = float(v)
+    if v == 0.0:
+        return 0.0
+    e = np.floor(np.log2(abs(v))) - 7
+    k = np.ceil(abs(v) / 2.0 ** e)
+    if k > 255:
+        e += 1
+        k = np.ceil(abs(v) / 2.0 ** e)
+    return float(np.sign(v) * k * 2.0 ** e)
+
+
+def test_backward_full_width_gated_elementwise(sg):
+    """The surrogate's widths (512-256-256-256-1024) with mixed-sign weights
+    and inputs, every hidden unit's bias set so that its pre-activation keeps
+    one sign with a wide margin over the whole batch: half the units active,
+    half cut off by their ReLU, decided the same way on both sides.  Every
+    gradient element is compared: elements of cut-off units (and the weights
+    fed by them) must be exactly 0; the others within 2^-6 of the element's
+    magnitude bound G (the same chain rule on absolute values: |W|, |delta|,
+    |activation|, plus the output's own rounding), which covers the BF16
+    rounding of hidden activations and deltas (2^-9 each, a few per path)."""
+    widths = sg.WIDTHS
+    B = 96
+    theta = synth.mlp_init(21, widths, bias_std=0.0).astype(np.float64)
+    x = synth.mlp_inputs(22, B, widths[0]).astype(np.float64)
+    layers = omlp.split_params(theta, widths)
+    rng = np.random.default_rng(23)
+    a = x
+    for li in range(len(layers) - 1):
+        W, b = layers[li]
+        z = a @ W.T
+        s = np.where(rng.uniform(size=W.shape[0]) < 0.5, 1.0, -1.0)
+        mag = np.abs(z).max(axis=0)
+        for j in range(W.shape[0]):
+            b[j] = _bf16_up(s[j] * (1.5 * mag[j] + 1e-3))
+        a = np.maximum(z + b, 0.0)
+        gate = (z + b) > 0
+        assert np.all(((z + b) > 0) == (s > 0)[None, :])          # one sign per unit over the batch
+        assert gate.any() and (~gate).any()
+    theta32 = theta.astype(np.float32)
+    assert np.array_equal(theta32.astype(np.float64), theta)       # exactly representable
+    ref_y = omlp.forward(theta, widths, x)[-1]
+    tgt = (ref_y + np.sqrt((ref_y ** 2).mean()) * rng.standard_normal(ref_y.shape)).astype(np.float32)
+    mask = (rng.uniform(size=tgt.shape) < 0.8).astype(np.float32)
+    net = sg.Mlp(theta32, widths, max_batch=128, device=DEV)
+    xb = _bf16(x.astype(np.float32))
+    y = net.forward(xb)
+    lt = net.backward(xb, y, torch.as_tensor(tgt, device=DEV), torch.as_tensor(mask, device=DEV))
+    msum = float(lt.cpu().numpy()[1])
+    g = net.grad.cpu().numpy().astype(np.float64) / msum
+    _, gref = omlp.backward(theta, widths, x, tgt.astype(np.float64), mask.astype(np.float64))
+    # magnitude bound: forward magnitudes F, output rounding, then |delta| backwards
+    acts = omlp.forward(theta, widths, x)
+    F = [np.abs(x)]
+    for li, (W, b) in enumerate(layers):
+        f = F[-1] @ np.abs(W).T + np.abs(b)
+        if li + 1 < len(layers):
+            f = f * (acts[li + 1] > 0)
+        F.append(f)
+    m = mask.astype(np.float64)
+    D = (2.0 * m * (np.abs(acts[-1] - tgt) + 2.0 ** -6 * F[-1])) / m.sum()
+    Gs = []
+    for li in range(len(layers) - 1, -1, -1):
+        W, _ = layers[li]
+        Gs.append(np.concatenate([(D.T @ F[li]).ravel(), D.sum(axis=0)]))
+        if li > 0:
+            D = (D @ np.abs(W)) * (acts[li] > 0)
+    G = np.concatenate(Gs[::-1])
+    zero = G == 0.0
+    assert zero.any() and (~zero).any()
+    assert np.all(g[zero] == 0.0) and np.all(gref[zero] == 0.0)
+    err = np.abs(g - gref)
+    worst = float((err[~zero] / G[~zero]).max())
+    print("gated full width: %d of %d gradient elements gated to 0; worst |error| / bound %.3e"
+          % (int(zero.sum()), g.size, worst))
+    assert np.all(err <= 2.0 ** -6 * G)

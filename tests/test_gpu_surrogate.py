@@ -1,0 +1,85 @@
+"""What the trained late-tail surrogate gains over the method without it.
+
+The network is trained (by the library's own BF16 matrix-core kernels) on
+1,080 seeded lattice rooms (10^5 rays each; with 2 10^4 rays the histograms
+of orders 0..8 are too noisy for it to beat the mean curve) and judged on
+120 held-out rooms against the full 60-bounce
+trace's per-band decay curve (mean per-band RMS dB over the bins where the
+full curve is >= -60 dB).  It must beat two predictors that use no network:
+
+* the mean decay curve of the training rooms (per band and bin);
+* the 8-bounce trace's own decay extrapolated: per band, the least-squares
+  line through its curve between -0.5 and -5 dB (the early decay, before the
+  truncation of the reflection orders shows), continued in dB as a single
+  exponential decay (where fewer than two bins fall in that range, the
+  training mean).
+
+The truncated 8-bounce curve itself is reported, not used as the bar (it
+drops to the floor once the early energy ends).  The extension's 0.5 dB goal
+is not asserted here: it is not met (the numbers are printed)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def extrapolated_decay(base_db, fallback, T=2.0, lo=-5.0, hi=-0.5):
+    """[n, 8, bins] early decay curves -> the line through each band's points
+    with lo <= EDC <= hi, continued over all bins (<= 0 dB); rows/bands with
+    fewer than 2 such points take the fallback curve."""
+    n, nb, bins = base_db.shape
+    t = (np.arange(bins) + 0.5) * T / bins
+    out = np.empty_like(base_db)
+    for i in range(n):
+        for b in range(nb):
+            c = base_db[i, b]
+            sel = (c <= hi) & (c >= lo)
+            if sel.sum() >= 2:
+                k, c0 = np.polyfit(t[sel], c[sel], 1)
+                out[i, b] = np.minimum(c0 + k * t, 0.0)
+            else:
+                out[i, b] = fallback[b]
+    return out
+
+
+def test_surrogate_beats_predictors_without_network():
+    from paper_1811_05784_amd import surrogate as sg
+    n_rooms, n_train = 1200, 1080
+    rooms = synth.surrogate_rooms(seed=5, n_rooms=n_rooms, m_hi=20_000.0)
+    x, tgt, mask, base = sg.dataset(rooms, n_rays=100_000, full_order=60, T=2.0, device=DEV, rooms_per_batch=40)
+    _say("surrogate data: %d rooms" % n_rooms)
+    net = sg.Mlp(synth.mlp_init(5, sg.WIDTHS), sg.WIDTHS, max_batch=256, device=DEV)
+    sg.train(net, x[:n_train].contiguous(), tgt[:n_train].contiguous(), mask[:n_train].contiguous(), epochs=200,
+             batch=128, lr=1e-3)
+    xe, te = x[n_train:].contiguous(), tgt[n_train:]
+    e_mlp = sg.band_rms_db(net.forward(xe), te).cpu().numpy()
+    t_np = tgt.cpu().numpy().reshape(-1, 8, 128).astype(np.float64)
+    m_np = mask.cpu().numpy().reshape(-1, 8, 128).astype(np.float64)
+    msum = m_np[:n_train].sum(0)
+    mean_curve = np.where(msum > 0, (t_np[:n_train] * m_np[:n_train]).sum(0) / np.maximum(msum, 1), t_np[:n_train].mean(0))
+    held = len(te)
+    pred_mean = torch.as_tensor(np.broadcast_to(mean_curve, (held, 8, 128)).reshape(held, -1).astype(np.float32),
+                                device=DEV)
+    e_mean = sg.band_rms_db(pred_mean, te).cpu().numpy()
+    base_np = base.cpu().numpy().reshape(-1, 8, 128).astype(np.float64)[n_train:]
+    pred_ext = torch.as_tensor(extrapolated_decay(base_np, mean_curve).reshape(held, -1).astype(np.float32),
+                               device=DEV)
+    e_ext = sg.band_rms_db(pred_ext, te).cpu().numpy()
+    e_trunc = sg.band_rms_db(base[n_train:], te).cpu().numpy()
+    _say("held-out rooms %d: mean per-band RMS dB  network %.2f | training-mean curve %.2f | extrapolated "
+         "8-bounce decay %.2f | truncated 8-bounce curve %.2f (goal 0.5 dB; bands <= 0.5 dB: %.0f %%)"
+         % (held, e_mlp.mean(), e_mean.mean(), e_ext.mean(), e_trunc.mean(), 100 * (e_mlp <= 0.5).mean()))
+    assert np.isfinite(e_mlp).all()
+    assert e_mlp.mean() < e_mean.mean()
+    assert e_mlp.mean() < e_ext.mean()
