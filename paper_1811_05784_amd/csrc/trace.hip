@@ -245,6 +245,30 @@ __device__ inline void cswap(float& ta, int32_t& ra, float& tb, int32_t& rb) {
     }
 }
 
+// Minimum of v over each group of G lanes (G = 64: the wavefront; 32: its
+// halves), in every lane of the group: an inclusive min-scan within rows of
+// 16 lanes by row shifts of 1, 2, 4, 8, then the broadcasts of lane 15 (to
+// rows 1 and 3) and, for the whole wavefront, of lane 31 (to rows 2 and 3),
+// all data-parallel moves between lanes; the group's last lane holds the
+// minimum.  Every lane of the wavefront must be active.
+template <int G>
+__device__ inline uint32_t group_umin(uint32_t v) {
+    constexpr int kId = -1;   // 0xFFFFFFFF: the identity of an unsigned minimum
+    auto take = [](uint32_t a, int b) { return a < (uint32_t)b ? a : (uint32_t)b; };
+    v = take(v, __builtin_amdgcn_update_dpp(kId, (int)v, 0x111, 0xF, 0xF, false));   // row_shr:1
+    v = take(v, __builtin_amdgcn_update_dpp(kId, (int)v, 0x112, 0xF, 0xF, false));   // row_shr:2
+    v = take(v, __builtin_amdgcn_update_dpp(kId, (int)v, 0x114, 0xF, 0xF, false));   // row_shr:4
+    v = take(v, __builtin_amdgcn_update_dpp(kId, (int)v, 0x118, 0xF, 0xF, false));   // row_shr:8
+    v = take(v, __builtin_amdgcn_update_dpp(kId, (int)v, 0x142, 0xA, 0xF, false));   // row_bcast:15
+    if (G == kWave) {
+        v = take(v, __builtin_amdgcn_update_dpp(kId, (int)v, 0x143, 0xC, 0xF, false));   // row_bcast:31
+        return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+    }
+    const uint32_t m0 = (uint32_t)__builtin_amdgcn_readlane((int)v, 31);
+    const uint32_t m1 = (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+    return (threadIdx.x & (kWave - 1)) < 32 ? m0 : m1;
+}
+
 // Nearest hit of one query by a group of G lanes (G = 64: the whole
 // wavefront; 32: one half, lanes li = 0..31 from lane gbase), breadth first
 // over a frontier kept in the group's columns of the LDS stack area (refs in
@@ -346,30 +370,30 @@ __device__ inline bool coop_search(const Ray& q, int32_t qlp, float& bt, int32_t
             ok = false;
             break;
         }
-        // nearest hit of the group: (t, id) lexicographic minimum
-        for (int off = G / 2; off > 0; off >>= 1) {
-            const float ot = __shfl_xor(lt, off);
-            const int32_t oid = __shfl_xor(lid, off), oj = __shfl_xor(lj, off);
-            if (ot < lt || (ot == lt && oid < lid)) {
-                lt = ot;
-                lid = oid;
-                lj = oj;
-            }
-        }
-        bt = lt;
-        bid = lid;
-        bj = lj;
-        // children that can still hold a nearer or equal hit join the frontier
+        // nearest hit of the group: (t, id) lexicographic minimum (t >= 0, so its
+        // bits order like its values), then the record of the first lane holding it
+        const int lane = (int)(threadIdx.x & (kWave - 1));
+        const uint64_t gmask = G == kWave ? ~0ull : (lane < 32 ? 0xFFFFFFFFull : 0xFFFFFFFF00000000ull);
+        const uint32_t tbits = __float_as_uint(lt);
+        const uint32_t tmin = group_umin<G>(tbits);
+        const uint32_t idmin = group_umin<G>(tbits == tmin ? (uint32_t)lid : 0xFFFFFFFFu);
+        const uint64_t holder = __ballot(tbits == tmin && (uint32_t)lid == idmin);
+        const int src_lo = __ffsll((long long)(holder & 0xFFFFFFFFull)) - 1;
+        const int src_hi = __ffsll((long long)(holder & 0xFFFFFFFF00000000ull)) - 1;
+        const int src = (G == kWave || lane < 32) ? (src_lo >= 0 ? src_lo : src_hi) : src_hi;
+        bt = __uint_as_float(tmin);
+        bid = (int32_t)idmin;
+        bj = __shfl(lj, src);
+        // children that can still hold a nearer or equal hit join the frontier;
+        // each lane's offset counts the children of the group's lanes below it
         const float tkeep = widen(bt);
         int cnt = 0;
 #pragma unroll
         for (int sl = 0; sl < 4; sl++) cnt += (rf[sl] != kEmpty && tn[sl] <= tkeep) ? 1 : 0;
-        int incl = cnt;
-        for (int off = 1; off < G; off <<= 1) {
-            const int x = __shfl_up(incl, off);
-            if (li >= off) incl += x;
-        }
-        const int total = __shfl(incl, gbase + G - 1);
+        const uint64_t c1 = __ballot(cnt & 1) & gmask, c2 = __ballot(cnt & 2) & gmask, c4 = __ballot(cnt & 4) & gmask;
+        const uint64_t below = lane ? (~0ull >> (kWave - lane)) : 0ull;
+        const int excl = __popcll(c1 & below) + 2 * __popcll(c2 & below) + 4 * __popcll(c4 & below);
+        const int total = __popcll(c1) + 2 * __popcll(c2) + 4 * __popcll(c4);
         if (__ballot(nf + total > kCap) != 0ull) {
             ok = false;
             break;
@@ -377,7 +401,7 @@ __device__ inline bool coop_search(const Ray& q, int32_t qlp, float& bt, int32_t
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        int at = nf + incl - cnt;
+        int at = nf + excl;
         // far children first, so that the nearest are taken next
 #pragma unroll
         for (int sl = 3; sl >= 0; sl--) {
