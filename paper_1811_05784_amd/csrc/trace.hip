@@ -246,11 +246,11 @@ __device__ inline void cswap(float& ta, int32_t& ra, float& tb, int32_t& rb) {
 }
 
 // Minimum of v over each group of G lanes (G = 64: the wavefront; 32: its
-// halves), in every lane of the group: an inclusive min-scan within rows of
-// 16 lanes by row shifts of 1, 2, 4, 8, then the broadcasts of lane 15 (to
-// rows 1 and 3) and, for the whole wavefront, of lane 31 (to rows 2 and 3),
-// all data-parallel moves between lanes; the group's last lane holds the
-// minimum.  Every lane of the wavefront must be active.
+// halves; 16: its rows), in every lane of the group: an inclusive min-scan
+// within rows of 16 lanes by row shifts of 1, 2, 4, 8, then the broadcasts of
+// lane 15 (to rows 1 and 3) and, for the whole wavefront, of lane 31 (to rows
+// 2 and 3), all data-parallel moves between lanes; the group's last lane
+// holds the minimum.  Every lane of the wavefront must be active.
 template <int G>
 __device__ inline uint32_t group_umin(uint32_t v) {
     constexpr int kId = -1;   // 0xFFFFFFFF: the identity of an unsigned minimum
@@ -259,6 +259,14 @@ __device__ inline uint32_t group_umin(uint32_t v) {
     v = take(v, __builtin_amdgcn_update_dpp(kId, (int)v, 0x112, 0xF, 0xF, false));   // row_shr:2
     v = take(v, __builtin_amdgcn_update_dpp(kId, (int)v, 0x114, 0xF, 0xF, false));   // row_shr:4
     v = take(v, __builtin_amdgcn_update_dpp(kId, (int)v, 0x118, 0xF, 0xF, false));   // row_shr:8
+    if (G == 16) {
+        const int row = (int)((threadIdx.x & (kWave - 1)) >> 4);
+        const uint32_t m0 = (uint32_t)__builtin_amdgcn_readlane((int)v, 15);
+        const uint32_t m1 = (uint32_t)__builtin_amdgcn_readlane((int)v, 31);
+        const uint32_t m2 = (uint32_t)__builtin_amdgcn_readlane((int)v, 47);
+        const uint32_t m3 = (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+        return row == 0 ? m0 : row == 1 ? m1 : row == 2 ? m2 : m3;
+    }
     v = take(v, __builtin_amdgcn_update_dpp(kId, (int)v, 0x142, 0xA, 0xF, false));   // row_bcast:15
     if (G == kWave) {
         v = take(v, __builtin_amdgcn_update_dpp(kId, (int)v, 0x143, 0xC, 0xF, false));   // row_bcast:31
@@ -270,7 +278,8 @@ __device__ inline uint32_t group_umin(uint32_t v) {
 }
 
 // Nearest hit of one query by a group of G lanes (G = 64: the whole
-// wavefront; 32: one half, lanes li = 0..31 from lane gbase), breadth first
+// wavefront; 32: one half; 16: one row; lanes li = 0..G-1 from lane gbase;
+// an inactive group has no query and idles), breadth first
 // over a frontier kept in the group's columns of the LDS stack area (refs in
 // the first half of the kRing slots, entry distances in the second: kRing/2 G
 // entries).  Each step every
@@ -281,20 +290,20 @@ __device__ inline uint32_t group_umin(uint32_t v) {
 // The group keeps the nearest hit, (t, id) lexicographic: exact ties go to the
 // lowest triangle id and the result is the per-lane walk's.  bt, bid, bj come
 // in as the owner's best so far and leave as the group's result (the same in
-// every lane of the group).  Returns false when the frontier would overflow,
-// the step bound is reached or a reference is out of range (for either group
-// of a wavefront); the owner then walks the query from the root, bounded by
-// the best hit found so far.
+// every lane of the group).  Returns false, for that group only, when its
+// frontier would overflow or it meets a reference out of range, and for all
+// groups when the step bound is reached; the owner then walks the query from
+// the root, bounded by the best hit found so far.
 template <int G, int kRing>
 __device__ inline bool coop_search(const Ray& q, int32_t qlp, float& bt, int32_t& bid, int32_t& bj, int32_t* base_col,
-                                   int li, int gbase, const Node4* nodes, const float4* tri, int32_t n_nodes,
-                                   int32_t n_tri, int32_t max_steps) {
+                                   int li, int gbase, bool active, const Node4* nodes, const float4* tri,
+                                   int32_t n_nodes, int32_t n_tri, int32_t max_steps) {
     constexpr int kCap = (kRing / 2) * G;
     int32_t* fref = base_col;
     float* ft = reinterpret_cast<float*>(base_col + (kRing / 2) * kBlock);
     auto fat = [](int k) { return (k / G) * kBlock + (k % G); };
-    int nf = 1;
-    if (li == 0) {
+    int nf = active ? 1 : 0;   // a group without a query stays idle
+    if (active && li == 0) {
         fref[0] = 0;
         ft[0] = 0.f;
     }
@@ -366,21 +375,15 @@ __device__ inline bool coop_search(const Ray& q, int32_t qlp, float& bt, int32_t
                 }
             }
         }
-        if (__ballot(bad)) {
-            ok = false;
-            break;
-        }
         // nearest hit of the group: (t, id) lexicographic minimum (t >= 0, so its
         // bits order like its values), then the record of the first lane holding it
         const int lane = (int)(threadIdx.x & (kWave - 1));
-        const uint64_t gmask = G == kWave ? ~0ull : (lane < 32 ? 0xFFFFFFFFull : 0xFFFFFFFF00000000ull);
+        const uint64_t gmask = G == kWave ? ~0ull : (((1ull << G) - 1ull) << gbase);
         const uint32_t tbits = __float_as_uint(lt);
         const uint32_t tmin = group_umin<G>(tbits);
         const uint32_t idmin = group_umin<G>(tbits == tmin ? (uint32_t)lid : 0xFFFFFFFFu);
-        const uint64_t holder = __ballot(tbits == tmin && (uint32_t)lid == idmin);
-        const int src_lo = __ffsll((long long)(holder & 0xFFFFFFFFull)) - 1;
-        const int src_hi = __ffsll((long long)(holder & 0xFFFFFFFF00000000ull)) - 1;
-        const int src = (G == kWave || lane < 32) ? (src_lo >= 0 ? src_lo : src_hi) : src_hi;
+        const uint64_t holder = __ballot(tbits == tmin && (uint32_t)lid == idmin) & gmask;
+        const int src = __ffsll((long long)holder) - 1;   // the group's first lane holding the minimum
         bt = __uint_as_float(tmin);
         bid = (int32_t)idmin;
         bj = __shfl(lj, src);
@@ -394,9 +397,12 @@ __device__ inline bool coop_search(const Ray& q, int32_t qlp, float& bt, int32_t
         const uint64_t below = lane ? (~0ull >> (kWave - lane)) : 0ull;
         const int excl = __popcll(c1 & below) + 2 * __popcll(c2 & below) + 4 * __popcll(c4 & below);
         const int total = __popcll(c1) + 2 * __popcll(c2) + 4 * __popcll(c4);
-        if (__ballot(nf + total > kCap) != 0ull) {
+        // a group whose frontier would overflow, or that met a reference out of
+        // range, stops (its owner falls back); the others go on
+        if ((__ballot(bad) & gmask) != 0ull || nf + total > kCap) {
             ok = false;
-            break;
+            nf = 0;
+            continue;
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -618,20 +624,23 @@ k_trace(TraceArgs a) {
             continue;
         }
 
-        // ---- one or two queries left in the wavefront: search them with every lane
+        // ---- one to four queries left in the wavefront: search them with every lane
         // (coop_search: breadth first over a frontier in the wavefront's LDS
         // stack area; the owners' own stacks are dropped, the other lanes' are
-        // empty), so a query takes about tree-depth steps instead of one node
-        // per step; the result is the owner's own walk's.
+        // empty): one query takes all 64 lanes, two take 32 each, three or four
+        // take 16 each, so a query takes about tree-depth steps instead of one
+        // node per step; the result is the owner's own walk's.
         if (!kBatch && a.coop && pool_empty) {
             const uint64_t act = __ballot(status == kQuery);
             const int n_act = __popcll(act);
-            if ((n_act == 1 || n_act == 2) && __ballot(status == kDone) == 0ull) {
-                // one query: all 64 lanes; two: 32 lanes each (an owner may sit in either half)
-                const int own0 = __ffsll((long long)act) - 1;
-                const int own1 = n_act == 2 ? __ffsll((long long)(act & (act - 1))) - 1 : own0;
-                const int g = n_act == 2 ? lane >> 5 : 0;
-                const int mo = g ? own1 : own0;
+            if (n_act >= 1 && n_act <= 4 && __ballot(status == kDone) == 0ull) {
+                const int G = n_act == 1 ? 64 : (n_act == 2 ? 32 : 16);
+                const int g = lane / G;                       // this lane's group
+                // owner of group g: the g-th query lane (groups beyond n_act stay idle)
+                uint64_t rest = act;
+                for (int i = 0; i < g && rest; i++) rest &= rest - 1;
+                const bool has_query = rest != 0ull;
+                const int mo = has_query ? __ffsll((long long)rest) - 1 : lane;
                 Ray q;
                 q.ox = __shfl(r.ox, mo);
                 q.oy = __shfl(r.oy, mo);
@@ -644,24 +653,29 @@ k_trace(TraceArgs a) {
                 float bt = __shfl(best_t, mo);
                 int32_t bid = __shfl(best_id, mo), bj = __shfl(best_j, mo);
                 bool ok;
-                if (n_act == 1) {
-                    ok = coop_search<64, kRing>(q, qlp, bt, bid, bj, lds_stack + (tid - lane), lane, 0, nodes, tri, n_nodes,
-                                         n_tri, a.max_steps);
+                int32_t* col = lds_stack + (tid - lane) + G * g;
+                if (G == 64) {
+                    ok = coop_search<64, kRing>(q, qlp, bt, bid, bj, col, lane, 0, has_query, nodes, tri, n_nodes,
+                                                n_tri, a.max_steps);
+                } else if (G == 32) {
+                    ok = coop_search<32, kRing>(q, qlp, bt, bid, bj, col, lane & 31, 32 * g, has_query, nodes, tri,
+                                                n_nodes, n_tri, a.max_steps);
                 } else {
-                    ok = coop_search<32, kRing>(q, qlp, bt, bid, bj, lds_stack + (tid - lane) + 32 * g, lane & 31, 32 * g,
-                                         nodes, tri, n_nodes, n_tri, a.max_steps);
+                    ok = coop_search<16, kRing>(q, qlp, bt, bid, bj, col, lane & 15, 16 * g, has_query, nodes, tri,
+                                                n_nodes, n_tri, a.max_steps);
                 }
-                // each owner takes its group's result
-                const float bt0 = __shfl(bt, 0), bt1 = __shfl(bt, 32);
-                const int32_t bid0 = __shfl(bid, 0), bid1 = __shfl(bid, 32);
-                const int32_t bj0 = __shfl(bj, 0), bj1 = __shfl(bj, 32);
-                if (lane == own0 || lane == own1) {
-                    const bool first = lane == own0 || n_act == 1;
-                    best_t = first ? bt0 : bt1;
-                    best_id = first ? bid0 : bid1;
-                    best_j = first ? bj0 : bj1;
+                // each owner takes its group's result (from the group's first lane)
+                const int my_g = (int)__popcll(act & lt_mask);   // an owner's group
+                const int from = (status == kQuery ? my_g : 0) * G;
+                const float rbt = __shfl(bt, from);
+                const int32_t rbid = __shfl(bid, from), rbj = __shfl(bj, from);
+                const bool rok = __shfl((int)ok, from) != 0;   // the group's outcome, not the owner lane's own
+                if (status == kQuery) {
+                    best_t = rbt;
+                    best_id = rbid;
+                    best_j = rbj;
                     st = Stack{0, 0, 0};
-                    if (ok) {
+                    if (rok) {
                         status = kDone;
                     } else {
                         cur = 0;   // fall back: the owner's own walk from the root, bounded by the hit so far
