@@ -332,11 +332,34 @@ __device__ inline bool coop_search(const Ray& q, int32_t qlp, float& bt, int32_t
         int32_t lid = bid, lj = bj;
         bool bad = item != kEmpty && item >= n_nodes;
         const float tlim = widen(bt);
-        if (item != kEmpty && !bad && it <= tlim) {
-            if (item >= 0) {
-                const float4* np = reinterpret_cast<const float4*>(nodes + item);
-                const float4 lx = np[0], hx = np[1], ly = np[2], hy = np[3], lz = np[4], hz = np[5];
-                const int4 ch = reinterpret_cast<const int4*>(np)[6];
+        const bool live = item != kEmpty && !bad && it <= tlim;
+        int32_t first = 0, ntri = 0;
+        if (live && item < 0) {
+            first = leaf_first(item);
+            ntri = leaf_count(item);
+            if (ntri == 0 || first + ntri > n_tri) bad = true;
+        }
+        const bool is_node = live && item >= 0;
+        const bool is_leaf = live && item < 0 && !bad;
+        // one memory phase per step: an inner node's boxes and children and a
+        // leaf's first triangle are loaded together, so a step whose lanes hold
+        // both kinds waits on memory once
+        const float4* src = is_node ? reinterpret_cast<const float4*>(nodes + item) : tri + 3 * (int64_t)first;
+        float4 d0, d1, d2, d3, d4, d5, d6;
+        if (is_node || is_leaf) {
+            d0 = src[0];
+            d1 = src[1];
+            d2 = src[2];
+        }
+        if (is_node) {
+            d3 = src[3];
+            d4 = src[4];
+            d5 = src[5];
+            d6 = src[6];
+        }
+        if (is_node) {
+            const int32_t c0 = __float_as_int(d6.x), c1 = __float_as_int(d6.y), c2 = __float_as_int(d6.z),
+                          c3 = __float_as_int(d6.w);
 #define RT_SLAB(S, LX, HX, LY, HY, LZ, HZ, CH)                                          \
     {                                                                                    \
         const float t0x = (LX - q.ox) * q.ix, t1x = (HX - q.ox) * q.ix;                  \
@@ -350,43 +373,47 @@ __device__ inline bool coop_search(const Ray& q, int32_t qlp, float& bt, int32_t
         tn[S] = h ? tmin : INFINITY;                                                     \
         rf[S] = h ? CH : kEmpty;                                                         \
     }
-                RT_SLAB(0, lx.x, hx.x, ly.x, hy.x, lz.x, hz.x, ch.x)
-                RT_SLAB(1, lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, ch.y)
-                RT_SLAB(2, lx.z, hx.z, ly.z, hy.z, lz.z, hz.z, ch.z)
-                RT_SLAB(3, lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, ch.w)
+            RT_SLAB(0, d0.x, d1.x, d2.x, d3.x, d4.x, d5.x, c0)
+            RT_SLAB(1, d0.y, d1.y, d2.y, d3.y, d4.y, d5.y, c1)
+            RT_SLAB(2, d0.z, d1.z, d2.z, d3.z, d4.z, d5.z, c2)
+            RT_SLAB(3, d0.w, d1.w, d2.w, d3.w, d4.w, d5.w, c3)
 #undef RT_SLAB
-            } else {
-                const int32_t first = leaf_first(item), cnt = leaf_count(item);
-                if (cnt == 0 || first + cnt > n_tri) {
-                    bad = true;
-                } else {
-                    for (int i = 0; i < cnt; i++) {
-                        const int32_t j = first + i;
-                        const float4 v0 = tri[3 * j], v1 = tri[3 * j + 1], v2 = tri[3 * j + 2];
-                        if (__float_as_int(v0.w) == qlp) continue;
-                        const float t = watertight(q, v0, v1, v2);
-                        const int32_t id = __float_as_int(v1.w);
-                        if (t > 0.f && (t < lt || (t == lt && id < lid))) {
-                            lt = t;
-                            lid = id;
-                            lj = j;
-                        }
-                    }
+        } else if (is_leaf) {
+            for (int i = 0; i < ntri; i++) {
+                const int32_t j = first + i;
+                float4 v0 = d0, v1 = d1, v2 = d2;
+                if (i > 0) {
+                    v0 = tri[3 * j];
+                    v1 = tri[3 * j + 1];
+                    v2 = tri[3 * j + 2];
+                }
+                // the plane left by the ray is excluded in the acceptance test, not by
+                // a branch before it, so the record's loads are issued together
+                const float t = watertight(q, v0, v1, v2);
+                const int32_t id = __float_as_int(v1.w);
+                if (__float_as_int(v0.w) != qlp && t > 0.f && (t < lt || (t == lt && id < lid))) {
+                    lt = t;
+                    lid = id;
+                    lj = j;
                 }
             }
         }
         // nearest hit of the group: (t, id) lexicographic minimum (t >= 0, so its
-        // bits order like its values), then the record of the first lane holding it
+        // bits order like its values), then the record of the first lane holding
+        // it; only in steps where some lane found a nearer hit (lanes only ever
+        // improve on the group's best, so otherwise it stands)
         const int lane = (int)(threadIdx.x & (kWave - 1));
         const uint64_t gmask = G == kWave ? ~0ull : (((1ull << G) - 1ull) << gbase);
-        const uint32_t tbits = __float_as_uint(lt);
-        const uint32_t tmin = group_umin<G>(tbits);
-        const uint32_t idmin = group_umin<G>(tbits == tmin ? (uint32_t)lid : 0xFFFFFFFFu);
-        const uint64_t holder = __ballot(tbits == tmin && (uint32_t)lid == idmin) & gmask;
-        const int src = __ffsll((long long)holder) - 1;   // the group's first lane holding the minimum
-        bt = __uint_as_float(tmin);
-        bid = (int32_t)idmin;
-        bj = __shfl(lj, src);
+        if (__ballot(lt != bt || lid != bid) != 0ull) {
+            const uint32_t tbits = __float_as_uint(lt);
+            const uint32_t tmin = group_umin<G>(tbits);
+            const uint32_t idmin = group_umin<G>(tbits == tmin ? (uint32_t)lid : 0xFFFFFFFFu);
+            const uint64_t holder = __ballot(tbits == tmin && (uint32_t)lid == idmin) & gmask;
+            const int src_lane = __ffsll((long long)holder) - 1;   // the group's first lane holding the minimum
+            bt = __uint_as_float(tmin);
+            bid = (int32_t)idmin;
+            bj = __shfl(lj, src_lane);
+        }
         // children that can still hold a nearer or equal hit join the frontier;
         // each lane's offset counts the children of the group's lanes below it
         const float tkeep = widen(bt);
@@ -806,10 +833,12 @@ k_trace(TraceArgs a) {
                 for (int i = 0; i < cnt; i++) {
                     const int32_t j = first + i;
                     const float4 v0 = tri[3 * j], v1 = tri[3 * j + 1], v2 = tri[3 * j + 2];
-                    if (__float_as_int(v0.w) == last_plane) continue;
+                    // the plane left by the ray is excluded in the acceptance test, not
+                    // by a branch before it, so the record's loads are issued together
                     const float t = watertight(r, v0, v1, v2);
                     const int32_t id = __float_as_int(v1.w);
-                    if (t > 0.f && (t < best_t || (t == best_t && id < best_id))) {
+                    if (__float_as_int(v0.w) != last_plane && t > 0.f &&
+                        (t < best_t || (t == best_t && id < best_id))) {
                         best_t = t;
                         best_j = j;
                         best_id = id;
@@ -868,8 +897,9 @@ k_trace(TraceArgs a) {
                 }
             }
         }
-        // wave-wide append of detections: one atomic per wavefront
-        {
+        // wave-wide append of detections: one atomic per wavefront (detections
+        // are rare, so the scan runs only when some lane has one)
+        if (__ballot(dm != 0u) != 0ull) {
             const int c = __popc(dm);
             int incl = c;
 #pragma unroll
