@@ -317,21 +317,53 @@ __device__ inline bool coop_search(const Ray& q, int32_t qlp, float& bt, int32_t
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const int take = nf < G ? nf : G;
+        // two tree levels per step: a frontier item takes four lanes.  For an
+        // inner node, lane s slab-tests the node's child s and expands a hit
+        // child in the same step (a child node's four boxes, or a leaf child's
+        // triangles); a leaf item is tested by its first lane
+        constexpr int kItems = G / 4;
+        const int take = nf < kItems ? nf : kItems;
         const int base = nf - take;   // the most recent entries, deepest first
-        int32_t item = kEmpty;
-        float it = INFINITY;
-        if (li < take) {
-            item = fref[fat(base + li)];
-            it = ft[fat(base + li)];
+        const int slot = li & 3;
+        int32_t parent = kEmpty;
+        float pt = INFINITY;
+        if ((li >> 2) < take) {
+            parent = fref[fat(base + (li >> 2))];
+            pt = ft[fat(base + (li >> 2))];
         }
         nf = base;
+        const float tlim = widen(bt);
+        bool bad = parent != kEmpty && parent >= n_nodes;
+        int32_t item = kEmpty;   // what this lane expands
+        float it = INFINITY;
+        if (parent != kEmpty && !bad && pt <= tlim) {
+            if (parent >= 0) {
+                // child `slot` of the node: its box (one float of each of the
+                // node's six bound vectors) and its reference
+                const float* nb = reinterpret_cast<const float*>(nodes + parent);
+                const float LX = nb[slot], HX = nb[4 + slot], LY = nb[8 + slot], HY = nb[12 + slot];
+                const float LZ = nb[16 + slot], HZ = nb[20 + slot];
+                const int32_t CH = reinterpret_cast<const int32_t*>(nb)[24 + slot];
+                const float t0x = (LX - q.ox) * q.ix, t1x = (HX - q.ox) * q.ix;
+                const float t0y = (LY - q.oy) * q.iy, t1y = (HY - q.oy) * q.iy;
+                const float t0z = (LZ - q.oz) * q.iz, t1z = (HZ - q.oz) * q.iz;
+                const float tmin = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.f));
+                float tmax = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z));
+                tmax *= 1.00000036f;
+                if (CH != kEmpty && tmin <= tmax && tmin <= tlim) {
+                    item = CH;
+                    it = tmin;
+                }
+            } else if (slot == 0) {
+                item = parent;
+                it = pt;
+            }
+        }
+        if (item != kEmpty && item >= n_nodes) bad = true;
         float tn[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
         int32_t rf[4] = {kEmpty, kEmpty, kEmpty, kEmpty};
         float lt = bt;
         int32_t lid = bid, lj = bj;
-        bool bad = item != kEmpty && item >= n_nodes;
-        const float tlim = widen(bt);
         const bool live = item != kEmpty && !bad && it <= tlim;
         int32_t first = 0, ntri = 0;
         if (live && item < 0) {
