@@ -246,15 +246,23 @@ __device__ inline void cswap(float& ta, int32_t& ra, float& tb, int32_t& rb) {
 }
 
 // Minimum of v over each group of G lanes (G = 64: the wavefront; 32: its
-// halves; 16: its rows), in every lane of the group: an inclusive min-scan
+// halves; 16: its rows; 8: half rows), in every lane of the group.  For 16 and
+// more lanes: an inclusive min-scan
 // within rows of 16 lanes by row shifts of 1, 2, 4, 8, then the broadcasts of
 // lane 15 (to rows 1 and 3) and, for the whole wavefront, of lane 31 (to rows
 // 2 and 3), all data-parallel moves between lanes; the group's last lane
 // holds the minimum.  Every lane of the wavefront must be active.
-template <int G>
-__device__ inline uint32_t group_umin(uint32_t v) {
+__device__ inline uint32_t group_umin(uint32_t v, int G) {
     constexpr int kId = -1;   // 0xFFFFFFFF: the identity of an unsigned minimum
     auto take = [](uint32_t a, int b) { return a < (uint32_t)b ? a : (uint32_t)b; };
+    if (G == 8) {
+        // butterfly within each 8-lane half row: swap neighbours, swap pairs
+        // (quad permutations), then mirror the half row; every lane ends with the minimum
+        v = take(v, __builtin_amdgcn_update_dpp(kId, (int)v, 0xB1, 0xF, 0xF, false));    // quad_perm [1,0,3,2]
+        v = take(v, __builtin_amdgcn_update_dpp(kId, (int)v, 0x4E, 0xF, 0xF, false));    // quad_perm [2,3,0,1]
+        v = take(v, __builtin_amdgcn_update_dpp(kId, (int)v, 0x141, 0xF, 0xF, false));   // row_half_mirror
+        return v;
+    }
     v = take(v, __builtin_amdgcn_update_dpp(kId, (int)v, 0x111, 0xF, 0xF, false));   // row_shr:1
     v = take(v, __builtin_amdgcn_update_dpp(kId, (int)v, 0x112, 0xF, 0xF, false));   // row_shr:2
     v = take(v, __builtin_amdgcn_update_dpp(kId, (int)v, 0x114, 0xF, 0xF, false));   // row_shr:4
@@ -294,14 +302,15 @@ __device__ inline uint32_t group_umin(uint32_t v) {
 // frontier would overflow or it meets a reference out of range, and for all
 // groups when the step bound is reached; the owner then walks the query from
 // the root, bounded by the best hit found so far.
-template <int G, int kRing>
+template <int kRing>
 __device__ inline bool coop_search(const Ray& q, int32_t qlp, float& bt, int32_t& bid, int32_t& bj, int32_t* base_col,
-                                   int li, int gbase, bool active, const Node4* nodes, const float4* tri,
+                                   int li, int gbase, int G, bool active, const Node4* nodes, const float4* tri,
                                    int32_t n_nodes, int32_t n_tri, int32_t max_steps) {
-    constexpr int kCap = (kRing / 2) * G;
+    const int lg = 31 - __builtin_clz((unsigned)G);   // G is 8, 16, 32 or 64, the same in every lane
+    const int kCap = (kRing / 2) << lg;
     int32_t* fref = base_col;
     float* ft = reinterpret_cast<float*>(base_col + (kRing / 2) * kBlock);
-    auto fat = [](int k) { return (k / G) * kBlock + (k % G); };
+    auto fat = [lg, G](int k) { return (k >> lg) * kBlock + (k & (G - 1)); };
     int nf = active ? 1 : 0;   // a group without a query stays idle
     if (active && li == 0) {
         fref[0] = 0;
@@ -321,7 +330,7 @@ __device__ inline bool coop_search(const Ray& q, int32_t qlp, float& bt, int32_t
         // inner node, lane s slab-tests the node's child s and expands a hit
         // child in the same step (a child node's four boxes, or a leaf child's
         // triangles); a leaf item is tested by its first lane
-        constexpr int kItems = G / 4;
+        const int kItems = G >> 2;
         const int take = nf < kItems ? nf : kItems;
         const int base = nf - take;   // the most recent entries, deepest first
         const int slot = li & 3;
@@ -435,11 +444,11 @@ __device__ inline bool coop_search(const Ray& q, int32_t qlp, float& bt, int32_t
         // it; only in steps where some lane found a nearer hit (lanes only ever
         // improve on the group's best, so otherwise it stands)
         const int lane = (int)(threadIdx.x & (kWave - 1));
-        const uint64_t gmask = G == kWave ? ~0ull : (((1ull << G) - 1ull) << gbase);
+        const uint64_t gmask = G == kWave ? ~0ull : (((1ull << (G & 63)) - 1ull) << gbase);
         if (__ballot(lt != bt || lid != bid) != 0ull) {
             const uint32_t tbits = __float_as_uint(lt);
-            const uint32_t tmin = group_umin<G>(tbits);
-            const uint32_t idmin = group_umin<G>(tbits == tmin ? (uint32_t)lid : 0xFFFFFFFFu);
+            const uint32_t tmin = group_umin(tbits, G);
+            const uint32_t idmin = group_umin(tbits == tmin ? (uint32_t)lid : 0xFFFFFFFFu, G);
             const uint64_t holder = __ballot(tbits == tmin && (uint32_t)lid == idmin) & gmask;
             const int src_lane = __ffsll((long long)holder) - 1;   // the group's first lane holding the minimum
             bt = __uint_as_float(tmin);
@@ -683,17 +692,18 @@ k_trace(TraceArgs a) {
             continue;
         }
 
-        // ---- one to four queries left in the wavefront: search them with every lane
+        // ---- one to eight queries left in the wavefront: search them with every lane
         // (coop_search: breadth first over a frontier in the wavefront's LDS
         // stack area; the owners' own stacks are dropped, the other lanes' are
         // empty): one query takes all 64 lanes, two take 32 each, three or four
-        // take 16 each, so a query takes about tree-depth steps instead of one
-        // node per step; the result is the owner's own walk's.
+        // take 16 each, five to eight take 8 each, so a query takes about half
+        // the tree depth in steps instead of one node per step; the result is
+        // the owner's own walk's.
         if (!kBatch && a.coop && pool_empty) {
             const uint64_t act = __ballot(status == kQuery);
             const int n_act = __popcll(act);
-            if (n_act >= 1 && n_act <= 4 && __ballot(status == kDone) == 0ull) {
-                const int G = n_act == 1 ? 64 : (n_act == 2 ? 32 : 16);
+            if (n_act >= 1 && n_act <= 8 && __ballot(status == kDone) == 0ull) {
+                const int G = n_act == 1 ? 64 : (n_act == 2 ? 32 : (n_act <= 4 ? 16 : 8));
                 const int g = lane / G;                       // this lane's group
                 // owner of group g: the g-th query lane (groups beyond n_act stay idle)
                 uint64_t rest = act;
@@ -713,16 +723,8 @@ k_trace(TraceArgs a) {
                 int32_t bid = __shfl(best_id, mo), bj = __shfl(best_j, mo);
                 bool ok;
                 int32_t* col = lds_stack + (tid - lane) + G * g;
-                if (G == 64) {
-                    ok = coop_search<64, kRing>(q, qlp, bt, bid, bj, col, lane, 0, has_query, nodes, tri, n_nodes,
-                                                n_tri, a.max_steps);
-                } else if (G == 32) {
-                    ok = coop_search<32, kRing>(q, qlp, bt, bid, bj, col, lane & 31, 32 * g, has_query, nodes, tri,
-                                                n_nodes, n_tri, a.max_steps);
-                } else {
-                    ok = coop_search<16, kRing>(q, qlp, bt, bid, bj, col, lane & 15, 16 * g, has_query, nodes, tri,
-                                                n_nodes, n_tri, a.max_steps);
-                }
+                ok = coop_search<kRing>(q, qlp, bt, bid, bj, col, lane & (G - 1), G * g, G, has_query, nodes, tri,
+                                        n_nodes, n_tri, a.max_steps);
                 // each owner takes its group's result (from the group's first lane)
                 const int my_g = (int)__popcll(act & lt_mask);   // an owner's group
                 const int from = (status == kQuery ? my_g : 0) * G;
