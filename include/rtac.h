@@ -175,9 +175,9 @@ typedef struct {
                                   one per accelerator complex (each has its own L2), which
                                   workgroups drain first before helping the others             */
     int32_t coop_queries;      /* 0 = default (on), -1 off: once every ray has been handed out, a
-                                  wavefront left with a single query in flight searches it with
-                                  all 64 lanes, breadth first (two queries: 32 lanes each; same
-                                  nearest hit)                                                  */
+                                  wavefront left with one to eight queries in flight searches
+                                  them with all its lanes (64, 32, 16 or 8 per query), breadth
+                                  first, two tree levels per step; same nearest hit            */
     const int32_t* record_rows; /* NULL: with record_states, ray i writes row i of `states`; else
                                   device int32[n_rays] (global ray ids in a batch): ray i writes
                                   row record_rows[i] (< 0: not recorded), so a few rays of a large
