@@ -303,7 +303,8 @@ __device__ inline uint32_t group_umin(uint32_t v, int G) {
 // groups when the step bound is reached; the owner then walks the query from
 // the root, bounded by the best hit found so far.
 template <int kRing>
-__device__ inline bool coop_search(const Ray& q, int32_t qlp, float& bt, int32_t& bid, int32_t& bj, int32_t* base_col,
+__device__ inline bool coop_search(const Ray& q, int32_t qlp, float& bt, int32_t& bid, int32_t& bj, int32_t* plane_slot,
+                                   int32_t* base_col,
                                    int li, int gbase, int G, bool active, const Node4* nodes, const float4* tri,
                                    int32_t n_nodes, int32_t n_tri, int32_t max_steps) {
     const int lg = 31 - __builtin_clz((unsigned)G);   // G is 8, 16, 32 or 64, the same in every lane
@@ -372,7 +373,7 @@ __device__ inline bool coop_search(const Ray& q, int32_t qlp, float& bt, int32_t
         float tn[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
         int32_t rf[4] = {kEmpty, kEmpty, kEmpty, kEmpty};
         float lt = bt;
-        int32_t lid = bid, lj = bj;
+        int32_t lid = bid, lj = bj, lp = 0;
         const bool live = item != kEmpty && !bad && it <= tlim;
         int32_t first = 0, ntri = 0;
         if (live && item < 0) {
@@ -436,6 +437,7 @@ __device__ inline bool coop_search(const Ray& q, int32_t qlp, float& bt, int32_t
                     lt = t;
                     lid = id;
                     lj = j;
+                    lp = __float_as_int(v0.w);
                 }
             }
         }
@@ -445,7 +447,8 @@ __device__ inline bool coop_search(const Ray& q, int32_t qlp, float& bt, int32_t
         // improve on the group's best, so otherwise it stands)
         const int lane = (int)(threadIdx.x & (kWave - 1));
         const uint64_t gmask = G == kWave ? ~0ull : (((1ull << (G & 63)) - 1ull) << gbase);
-        if (__ballot(lt != bt || lid != bid) != 0ull) {
+        const bool improved = lt != bt || lid != bid;
+        if (__ballot(improved) != 0ull) {
             const uint32_t tbits = __float_as_uint(lt);
             const uint32_t tmin = group_umin(tbits, G);
             const uint32_t idmin = group_umin(tbits == tmin ? (uint32_t)lid : 0xFFFFFFFFu, G);
@@ -454,6 +457,8 @@ __device__ inline bool coop_search(const Ray& q, int32_t qlp, float& bt, int32_t
             bt = __uint_as_float(tmin);
             bid = (int32_t)idmin;
             bj = __shfl(lj, src_lane);
+            // the holder records the hit's plane id in the owner's slot
+            if (lane == src_lane && improved) *plane_slot = lp;
         }
         // children that can still hold a nearer or equal hit join the frontier;
         // each lane's offset counts the children of the group's lanes below it
@@ -501,6 +506,8 @@ k_trace(TraceArgs a) {
     // travelled length of each lane's ray, FP64 across all its segments (kept
     // out of the registers of the node loop, which never reads it)
     __shared__ double len_s[kBlock];
+    // plane id of each lane's nearest hit so far (read when the query is shaded)
+    __shared__ int32_t hitp_s[kBlock];
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     if (!kBatch && tid < a.n_rcv * 4) rcv_s[tid >> 2][tid & 3] = (double)a.rcv[tid];
@@ -527,6 +534,7 @@ k_trace(TraceArgs a) {
     int32_t ray = 0;
     int k = 0;
     len_s[tid] = 0.0;
+    hitp_s[tid] = -1;
     int32_t last_plane = -1;
     Ray r;
     r.ox = r.oy = r.oz = r.ux = r.uy = r.uz = 0.f;
@@ -723,8 +731,8 @@ k_trace(TraceArgs a) {
                 int32_t bid = __shfl(best_id, mo), bj = __shfl(best_j, mo);
                 bool ok;
                 int32_t* col = lds_stack + (tid - lane) + G * g;
-                ok = coop_search<kRing>(q, qlp, bt, bid, bj, col, lane & (G - 1), G * g, G, has_query, nodes, tri,
-                                        n_nodes, n_tri, a.max_steps);
+                ok = coop_search<kRing>(q, qlp, bt, bid, bj, hitp_s + (tid - lane) + mo, col, lane & (G - 1), G * g, G,
+                                        has_query, nodes, tri, n_nodes, n_tri, a.max_steps);
                 // each owner takes its group's result (from the group's first lane)
                 const int my_g = (int)__popcll(act & lt_mask);   // an owner's group
                 const int from = (status == kQuery ? my_g : 0) * G;
@@ -875,6 +883,7 @@ k_trace(TraceArgs a) {
                         (t < best_t || (t == best_t && id < best_id))) {
                         best_t = t;
                         best_j = j;
+                        hitp_s[tid] = __float_as_int(v0.w);
                         best_id = id;
                     }
                 }
@@ -895,8 +904,8 @@ k_trace(TraceArgs a) {
             if (best_j >= 0) {
                 // plane crossing of the chosen triangle in FP64 from its plane (unit
                 // normal and point of the plane id's representative)
-                hit_plane = __float_as_int(tri[3 * best_j].w);
-                hit_id = __float_as_int(tri[3 * best_j + 1].w);
+                hit_plane = hitp_s[tid];
+                hit_id = best_id;
                 const double* pn = pl_n + 3 * (int64_t)hit_plane;
                 const double* pp = pl_p + 3 * (int64_t)hit_plane;
                 const double nx = pn[0], ny = pn[1], nz = pn[2];
@@ -906,6 +915,7 @@ k_trace(TraceArgs a) {
                 if (!(dl > 0.0)) dl = 0.0;
             }
             if (uu > 0.0) {
+                const double inv_uu = 1.0 / uu;   // one division for all receivers
                 for (int m = 0; m < n_rcv; m++) {
                     double cx, cy, cz, cr;
                     if (kBatch) {
@@ -921,7 +931,7 @@ k_trace(TraceArgs a) {
                         cr = rcv_s[m][3];
                     }
                     const double wx = cx - ox, wy = cy - oy, wz = cz - oz;
-                    double ts = (wx * ux + wy * uy + wz * uz) / uu;
+                    double ts = (wx * ux + wy * uy + wz * uz) * inv_uu;
                     if (ts < 0.0) ts = 0.0;
                     if (ts > dl) ts = dl;
                     const double qx = ox + ts * ux - cx;
