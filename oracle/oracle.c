@@ -273,7 +273,11 @@ static void query(const or_scene* s, const double* o, const double* u, int last_
             if (dist > tol) continue;
             if ((int)j != best) {
                 if (best >= 0 && fabs(d - bd) * un <= tol) r->flags |= OR_FLAG_TIE;
-                if (dist > 0 && d > 0) r->flags |= OR_FLAG_NEAR_MISS;
+                /* another triangle passing within tol of the ray is a near miss;
+                   in front of the chosen hit also at distance 0, where the
+                   closed-triangle test rejected it only by the rounding of
+                   lambda and mu (a ray through a shared edge or vertex) */
+                if (d > 0 && (dist > 0 || d < bd)) r->flags |= OR_FLAG_NEAR_MISS;
             }
             if (fabs(d) * un <= tol) r->flags |= OR_FLAG_TINY;
         }

@@ -809,6 +809,33 @@ def surface_query_states(scene: Scene, n: int, seed: int, toward=None):
             length.astype(np.float32))
 
 
+def tie_query_states(scene: Scene, n: int, seed: int):
+    """Seeded one-segment query states aimed at mesh vertices (fans of
+    triangles that share them) and at shared-edge midpoints, where several
+    triangles are crossed at the same or nearly the same point.  Target: a
+    random vertex of a random triangle, or the FP32-rounded midpoint of one of
+    its edges (half each); origin: the target moved 0.5-3 m along the
+    triangle's unit normal (either side) plus a lateral offset of up to 1 m per
+    axis (FP32); direction: target - origin (FP32, not normalised, so the
+    target lies at parameter 1); no plane excluded, no travelled length.
+    Returns (origins, dirs, plane, length)."""
+    rng = np.random.default_rng(seed)
+    t = rng.integers(0, scene.n_tri, n)
+    k = rng.integers(0, 3, n)
+    vv = scene.vtx.astype(np.float64)
+    v = vv[scene.tri[t, k]]
+    w = vv[scene.tri[t, (k + 1) % 3]]
+    mid = rng.random(n) < 0.5
+    target = np.where(mid[:, None], (v + w) / 2, v).astype(np.float32).astype(np.float64)
+    a = vv[scene.tri[t, 0]]
+    nrm = np.cross(vv[scene.tri[t, 1]] - a, vv[scene.tri[t, 2]] - a)
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    side = np.where(rng.random(n) < 0.5, -1.0, 1.0)[:, None]
+    o = (target + side * nrm * rng.uniform(0.5, 3.0, (n, 1)) + rng.uniform(-1.0, 1.0, (n, 3))).astype(np.float32)
+    u = (target - o.astype(np.float64)).astype(np.float32)
+    return o, u, np.full(n, -1, np.int32), np.zeros(n, np.float32)
+
+
 def interior_query_states(scene: Scene, n: int, seed: int, lo=None, hi=None):
     """Seeded query states starting inside the scene's bounding box (no last
     plane), random directions, zero travelled length."""
