@@ -159,6 +159,44 @@ def test_interior_query_parity(rt, oracle_lib, scenes, name, n):
     _query_parity(rt, oracle_lib, s, sc, o, u, lp, L, "interior " + name)
 
 
+@pytest.mark.parametrize("name", ["c2flat", "c3"])
+def test_ties_at_shared_vertices_and_edges_are_order_robust(rt, oracle_lib, scenes, name):
+    """Exact FP32 ties go to the lowest triangle id whatever order the search
+    takes: rays aimed at shared vertices and edge midpoints (many ties and
+    near ties) give the same first hit with the per-lane walk only, with the
+    cooperative search (rays traced one, three and eight per launch, so one
+    wavefront searches them with 64, 16 or 8 lanes per query), with LDS stack
+    depths 8 and 32, another register budget, rays in index order and the rays
+    split into other launches; and the hits match the oracle's query by query
+    (flagged mismatches must be valid answers)."""
+    s, sc = scenes[name]
+    n = 20_000
+    o, u, lp, L = synth.tie_query_states(s, n, seed=23)
+    _query_parity(rt, oracle_lib, s, sc, o, u, lp, L, "ties " + name)
+    osc = oracle_lib.OracleScene.of(s)
+    flags = oracle_lib.query_batch(osc, o, u, lp, L, s.rcv)["flags"]
+    _say("ties %s: oracle tie flags %d, edge flags %d of %d" % (
+        name, ((flags & oracle_lib.FLAG_TIE) != 0).sum(), ((flags & oracle_lib.FLAG_EDGE) != 0).sum(), n))
+
+    def first_hits(idx, **kw):
+        tr = rt.trace_rays(sc, u[idx], s.rcv, 0, origins=o[idx], start_plane=lp[idx], start_len=L[idx], **kw)
+        assert int(tr.counters[3]) == 0
+        return tr.hit_seq[:, 0].cpu().numpy()
+
+    every = np.arange(n)
+    ref = first_hits(every)
+    for kw in (dict(coop_queries=-1), dict(stack_depth=8), dict(stack_depth=32), dict(waves_per_simd=5),
+               dict(keep_order=True)):
+        assert np.array_equal(first_hits(every, **kw), ref), kw
+    for part in (every[::3], every[1::3]):
+        assert np.array_equal(first_hits(part), ref[part])
+    sample = np.random.default_rng(5).choice(n, 120, replace=False)
+    for size in (1, 3, 8):
+        for c in range(0, len(sample), size):
+            idx = sample[c:c + size]
+            assert np.array_equal(first_hits(idx), ref[idx]), (size, idx)
+
+
 def test_c1_trajectory_parity(rt, oracle_lib, scenes):
     s, sc = scenes["c1"]
     dirs = oracle_lib.fibonacci(s.n_rays)
