@@ -95,3 +95,50 @@ def _point_triangle_distance(p, a, b, c):
         w = np.clip(np.dot(p - s0, d) / np.dot(d, d), 0.0, 1.0)
         best = min(best, float(np.linalg.norm(p - (s0 + w * d))))
     return best
+
+
+def _segment_distance(p, a, b):
+    """Row-wise distance from points p to segments ab (arrays [n, 3])."""
+    d = b - a
+    den = np.einsum("ij,ij->i", d, d)
+    w = np.clip(np.einsum("ij,ij->i", p - a, d) / np.where(den > 0, den, 1.0), 0.0, 1.0)
+    return np.linalg.norm(p - (a + w[:, None] * d), axis=1)
+
+
+def skips_only_at_boundaries(o, u, t_hit, vtx, tri, eps):
+    """Whether the ray o + t u, answered by a hit at parameter t_hit (inf for
+    an escape), passes every triangle it crosses before t_hit - eps / |u|
+    within eps of that triangle's boundary: the answer then skipped only edge
+    or vertex seams, a decision within rounding; a triangle crossed well
+    inside before t_hit makes the answer wrong.  FP64 plain geometry over the
+    whole mesh (plane crossing, barycentric inside test, distance to the three
+    edge segments); no arithmetic of the method."""
+    o = np.asarray(o, np.float64)
+    u = np.asarray(u, np.float64)
+    v0, v1, v2 = (np.asarray(vtx, np.float64)[np.asarray(tri)[:, k]] for k in range(3))
+    e1, e2 = v1 - v0, v2 - v0
+    n = np.cross(e1, e2)
+    den = n @ u
+    ok = den != 0.0
+    t = np.full(len(n), np.inf)
+    t[ok] = np.einsum("ij,ij->i", v0[ok] - o, n[ok]) / den[ok]
+    lim = t_hit - eps / np.linalg.norm(u)
+    cand = np.nonzero(ok & (t > 0) & (t < lim))[0]
+    if len(cand) == 0:
+        return True
+    p = o + t[cand, None] * u
+    # barycentric coordinates in the triangle's plane
+    a, b, c = v0[cand], v1[cand], v2[cand]
+    f1, f2, w = b - a, c - a, p - a
+    d11, d12, d22 = (np.einsum("ij,ij->i", x, y) for x, y in ((f1, f1), (f1, f2), (f2, f2)))
+    w1, w2 = np.einsum("ij,ij->i", w, f1), np.einsum("ij,ij->i", w, f2)
+    det = d11 * d22 - d12 * d12
+    lam = (d22 * w1 - d12 * w2) / det
+    mu = (d11 * w2 - d12 * w1) / det
+    inside = (lam >= 0) & (mu >= 0) & (lam + mu <= 1)
+    if not inside.any():
+        return True
+    pi, ai, bi, ci = p[inside], a[inside], b[inside], c[inside]
+    edge = np.minimum(np.minimum(_segment_distance(pi, ai, bi), _segment_distance(pi, bi, ci)),
+                      _segment_distance(pi, ci, ai))
+    return bool(np.all(edge <= eps))

@@ -29,3 +29,23 @@ def test_crossing_behind_and_on_edge():
     assert t[0] == -5.0 and miss[0] == 0.0          # behind the origin: negative t
     t, miss = crossing_and_miss([[1, 0, 0]], [[0, 0, 2]], [[0, 0, 5]], [[2, 0, 5]], [[0, 2, 5]])
     assert t[0] == 2.5 and miss[0] == 0.0           # on the edge y = 0
+
+
+def test_skips_only_at_boundaries():
+    """Two unit triangles side by side in z = 0 that share no vertices (a seam
+    along x = 1, y in [0, 1]) and a third in z = 2: a ray straight down
+    through the seam may be answered by the far triangle (it passes the near
+    ones at their boundary); through a near triangle's interior it may not;
+    an escape is judged the same way."""
+    from tests._util import skips_only_at_boundaries
+    vtx = np.array([[0, 0, 0], [1, 0, 0], [1, 1, 0],       # near triangle A (edge x = 1)
+                    [1, 0, 0], [2, 0, 0], [1, 1, 0],       # near triangle B, separate copies of the vertices
+                    [-5, -5, -2], [5, -5, -2], [0, 5, -2]], np.float64)
+    tri = np.array([[0, 1, 2], [3, 4, 5], [6, 7, 8]])
+    down = np.array([0.0, 0.0, -1.0])
+    eps = 1e-9
+    assert skips_only_at_boundaries([1.0, 0.5, 1.0], down, 3.0, vtx, tri, eps)          # through the seam
+    assert not skips_only_at_boundaries([0.9, 0.5, 1.0], down, 3.0, vtx, tri, eps)      # through A's interior
+    assert skips_only_at_boundaries([0.9, 0.5, 1.0], down, 1.0, vtx, tri, eps)          # A itself answered
+    assert skips_only_at_boundaries([1.0, 1.0, 1.0], down, np.inf, vtx, tri, 1e-9) is False  # far one missed
+    assert skips_only_at_boundaries([7.0, 7.0, 1.0], down, np.inf, vtx, tri, eps)       # crosses nothing
