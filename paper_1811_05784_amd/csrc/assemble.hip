@@ -368,15 +368,31 @@ __global__ void k_sum_bands(const float* __restrict__ band_ir, int64_t L, int32_
 // ---------------------------------------------------------------------------
 constexpr int kAdjThreads = 256;
 
-// partial[block][m][b]: per-block sums in a fixed order (tree reduction).
+constexpr int kAdjDistinct = 16;   // distinct materials of one path kept in LDS (more: the path is rescanned)
+
+// partial[block][m][b]: per-block sums in a fixed order.  Each image source
+// first lists the distinct materials of its path with their multiplicities
+// (once), and the block marks the materials that occur; a material absent
+// from the block gets a zero partial without a reduction.  For a present one,
+// d/d alpha_(mat,b) of prod_j (1 - alpha_(m_j,b)) = -c (1 - alpha_(mat,b))^(c-1)
+// x the product over the path's other materials is summed over the
+// wavefront by a butterfly of lane exchanges and over the block's four
+// wavefronts in order (bitwise reproducible).
 __global__ void __launch_bounds__(kAdjThreads) k_adjoint_partial(IsArgs a, int32_t n_mat, const float* __restrict__ g,
                                                                  double* __restrict__ partial) {
-    __shared__ double red[kAdjThreads][8];
-    const int64_t i = (int64_t)blockIdx.x * kAdjThreads + threadIdx.x;
+    __shared__ double red[kAdjThreads / kWave][8];
+    __shared__ uint32_t present[128];   // materials on the block's paths (n_mat <= 4096)
+    __shared__ int32_t dmat[kAdjDistinct][kAdjThreads];
+    __shared__ int32_t dcnt[kAdjDistinct][kAdjThreads];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    for (int w = tid; w < 128; w += kAdjThreads) present[w] = 0u;
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * kAdjThreads + tid;
     const int64_t n = is_count_of(a);
     bool ok = i < n;
     const int32_t* row = ok ? a.key + i * (int64_t)(a.R1 + 1) : nullptr;
-    int32_t m = 0, k = 0;
+    int32_t m = 0, k = 0, nd = 0;
+    bool rescan = false;   // more distinct materials than the list holds
     double base[8];
     MatView mv{a.plane_mat, a.n_tri, 0, a.n_rays};
     if (ok) {
@@ -392,46 +408,96 @@ __global__ void __launch_bounds__(kAdjThreads) k_adjoint_partial(IsArgs a, int32
             base[b] = ok ? (double)a.count[i] / (double)mv.n_rays * exp(-(double)a.beta[b] * d) * (double)g[8 * m + b]
                          : 0.0;
     }
+    if (ok) {
+        for (int j = 0; j < k; j++) {
+            const int32_t mt = mv.mat_off + mv.plane_mat[row[2 + j]];
+            if (mt < 0 || mt >= n_mat) continue;   // not a differentiated material
+            int f = -1;
+            for (int q = 0; q < nd; q++)
+                if (dmat[q][tid] == mt) f = q;
+            if (f >= 0) {
+                dcnt[f][tid]++;
+            } else if (nd < kAdjDistinct) {
+                dmat[nd][tid] = mt;
+                dcnt[nd][tid] = 1;
+                nd++;
+            } else {
+                rescan = true;
+            }
+            atomicOr(&present[mt >> 5], 1u << (mt & 31));
+        }
+    }
+    __syncthreads();
     for (int mat = 0; mat < n_mat; mat++) {
-        double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (((present[mat >> 5] >> (mat & 31)) & 1u) == 0u) {
+            if (tid < 8) partial[((int64_t)blockIdx.x * n_mat + mat) * 8 + tid] = 0.0;
+            continue;
+        }
+        int cm = 0;
         if (ok) {
-            int cm = 0;
-            for (int j = 0; j < k; j++) cm += mv.mat_off + mv.plane_mat[row[2 + j]] == mat;
-            if (cm > 0) {
-                for (int b = 0; b < 8; b++) {
-                    const double om = 1.0 - (double)a.alpha[8 * mat + b];
-                    double dv = -(double)cm;
-                    for (int e = 0; e < cm - 1; e++) dv *= om;
+            if (rescan) {
+                for (int j = 0; j < k; j++) cm += mv.mat_off + mv.plane_mat[row[2 + j]] == mat;
+            } else {
+                for (int q = 0; q < nd; q++)
+                    if (dmat[q][tid] == mat) cm = dcnt[q][tid];
+            }
+        }
+        double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (cm > 0) {
+            for (int b = 0; b < 8; b++) {
+                const double om = 1.0 - (double)a.alpha[8 * mat + b];
+                double dv = -(double)cm;
+                for (int e = 0; e < cm - 1; e++) dv *= om;
+                if (rescan) {
                     for (int j = 0; j < k; j++) {
                         const int32_t mt = mv.mat_off + mv.plane_mat[row[2 + j]];
                         if (mt != mat) dv *= 1.0 - (double)a.alpha[8 * mt + b];
                     }
-                    v[b] = base[b] * dv;
+                } else {
+                    for (int q = 0; q < nd; q++) {
+                        const int32_t mt = dmat[q][tid];
+                        if (mt == mat) continue;
+                        const double oq = 1.0 - (double)a.alpha[8 * mt + b];
+                        for (int e = 0; e < dcnt[q][tid]; e++) dv *= oq;
+                    }
                 }
+                v[b] = base[b] * dv;
             }
         }
-        for (int b = 0; b < 8; b++) red[threadIdx.x][b] = v[b];
-        __syncthreads();
-        for (int off = kAdjThreads / 2; off > 0; off >>= 1) {
-            if ((int)threadIdx.x < off)
-                for (int b = 0; b < 8; b++) red[threadIdx.x][b] += red[threadIdx.x + off][b];
-            __syncthreads();
+        if (__ballot(cm > 0) != 0ull) {
+            for (int b = 0; b < 8; b++) {
+                double sum = v[b];
+                for (int off = kWave / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+                if (lane == 0) red[wave][b] = sum;
+            }
+        } else if (lane < 8) {
+            red[wave][lane] = 0.0;
         }
-        if (threadIdx.x < 8) partial[((int64_t)blockIdx.x * n_mat + mat) * 8 + threadIdx.x] = red[0][threadIdx.x];
+        __syncthreads();
+        if (tid < 8) {
+            double sum = 0.0;
+            for (int w = 0; w < kAdjThreads / kWave; w++) sum += red[w][tid];
+            partial[((int64_t)blockIdx.x * n_mat + mat) * 8 + tid] = sum;
+        }
         __syncthreads();
     }
 }
 
+// grad[t] = sum over the used blocks of partial[block][t]: one wavefront per
+// entry t, lane l summing blocks l, l + 64, ... in order, then a butterfly of
+// lane exchanges (a fixed order: bitwise reproducible).
 __global__ void k_adjoint_final(const double* __restrict__ partial, int nblocks, int32_t n_mat, const int64_t* n_is,
                                 int64_t is_cap, float* __restrict__ grad) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_mat * 8) return;
+    const int t = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave);
+    const int lane = threadIdx.x & (kWave - 1);
+    if (t >= n_mat * 8) return;   // whole wavefronts leave together
     int64_t n = *n_is;
     if (n > is_cap) n = is_cap;
     const int used = (int)((n + kAdjThreads - 1) / kAdjThreads);
     double s = 0.0;
-    for (int b = 0; b < used && b < nblocks; b++) s += partial[(int64_t)b * n_mat * 8 + t];
-    grad[t] = (float)s;
+    for (int b = lane; b < used && b < nblocks; b += kWave) s += partial[(int64_t)b * n_mat * 8 + t];
+    for (int off = kWave / 2; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) grad[t] = (float)s;
 }
 
 inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t > 0 ? (n + t - 1) / t : 1); }
@@ -651,8 +717,8 @@ int adjoint_common(const rt_scene* scene, const rt_batch* bt, const int32_t* is_
     }
     double* part = s->ws.asm_partial.as<double>();
     hipLaunchKernelGGL(k_adjoint_partial, dim3(nb), dim3(kAdjThreads), 0, st, a, n_mat, grad_band_energy, part);
-    hipLaunchKernelGGL(k_adjoint_final, dim3(nblk(n_mat * 8)), dim3(256), 0, st, part, nb, n_mat, n_is, is_cap,
-                       grad_alpha);
+    hipLaunchKernelGGL(k_adjoint_final, dim3(nblk((int64_t)n_mat * 8 * kWave)), dim3(256), 0, st, part, nb, n_mat,
+                       n_is, is_cap, grad_alpha);
     RT_HIP(hipGetLastError());
     return RT_OK;
 }
