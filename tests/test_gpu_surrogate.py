@@ -14,9 +14,13 @@ full curve is >= -60 dB).  It must beat two predictors that use no network:
   exponential decay (where fewer than two bins fall in that range, the
   training mean).
 
-The truncated 8-bounce curve itself is reported, not used as the bar (it
-drops to the floor once the early energy ends).  The extension's 0.5 dB goal
-is not asserted here: it is not met (the numbers are printed)."""
+The truncated 8-bounce curve itself is a weak bar (it drops to the floor once
+the early energy ends); the network must beat it as well.  On the 436k-
+triangle theater (10^6 rays, its 8 receivers; open air, while every training
+room is closed) the network must beat the plain 8-bounce truncation; it does
+not beat the training-mean curve there (printed: a shift of domain).  The
+extension's 0.5 dB goal is not asserted: it is not met (the numbers are
+printed)."""
 import sys
 
 import numpy as np
@@ -83,3 +87,21 @@ def test_surrogate_beats_predictors_without_network():
     assert np.isfinite(e_mlp).all()
     assert e_mlp.mean() < e_mean.mean()
     assert e_mlp.mean() < e_ext.mean()
+    assert e_mlp.mean() < e_trunc.mean()
+    # the 436k-triangle theater (10^6 rays, its 8 receivers): an open-air scene,
+    # while every training room is closed
+    th = synth.theater_c3()
+    xt, tt, mt, bt = sg.dataset([th], n_rays=th.n_rays, full_order=60, T=2.0, device=DEV, rooms_per_batch=1)
+    nt = len(tt)
+    t_mlp = sg.band_rms_db(net.forward(xt.contiguous()), tt).cpu().numpy()
+    t_trunc = sg.band_rms_db(bt, tt).cpu().numpy()
+    t_mean = sg.band_rms_db(torch.as_tensor(np.broadcast_to(mean_curve, (nt, 8, 128)).reshape(nt, -1)
+                                            .astype(np.float32), device=DEV), tt).cpu().numpy()
+    bt_np = bt.cpu().numpy().reshape(-1, 8, 128).astype(np.float64)
+    t_ext = sg.band_rms_db(torch.as_tensor(extrapolated_decay(bt_np, mean_curve).reshape(nt, -1).astype(np.float32),
+                                           device=DEV), tt).cpu().numpy()
+    _say("theater (%d receivers): mean per-band RMS dB  network %.2f | training-mean curve %.2f | extrapolated "
+         "8-bounce decay %.2f | truncated 8-bounce curve %.2f" % (nt, t_mlp.mean(), t_mean.mean(), t_ext.mean(),
+                                                                 t_trunc.mean()))
+    assert np.isfinite(t_mlp).all()
+    assert t_mlp.mean() < t_trunc.mean()
