@@ -75,8 +75,10 @@ typedef struct {
  *   out_scene receives the scene handle (host pointer).
  * Errors: RT_EINVAL (index out of range, plane group not coplanar or of mixed
  * material, n_tri < 1), RT_EDEGENERATE (zero-area triangle, NaN/Inf vertex),
- * RT_ENOMEM, RT_EHIP.  Synchronises `stream` twice (validation and the
- * reference count, then the tree facts).
+ * RT_ENOMEM, RT_EHIP.  Synchronises `stream` once (validation and the
+ * reference count, which sizes the per-reference arrays); the rest of the
+ * build runs on after the call returns (the first rt_scene_info call waits for
+ * it; the build's temporaries are kept until then or rt_scene_destroy).
  */
 int rt_build_tree(const float* vtx, int64_t n_vtx, const int32_t* tri, int64_t n_tri,
                   const int32_t* material, const int32_t* plane_id, const rt_build_params* params,
@@ -89,7 +91,9 @@ int rt_scene_destroy(rt_scene* scene);
  * materials (max material + 1), [2] = 4-wide tree nodes, [3] = tree depth,
  * [4] = leaf size, [5] = references (triangle records of the tree, >= n_tri:
  * thin triangles are cut into several); diag_host[0] = bounding-box
- * diagonal D (m). */
+ * diagonal D (m).  With info_host, the first call waits for the build to
+ * finish and reads the node count and depth from the device (RT_EHIP if they
+ * are inconsistent); diag_host alone never waits. */
 int rt_scene_info(const rt_scene* scene, int64_t* info_host, double* diag_host);
 
 /*

@@ -64,11 +64,23 @@ class Scene:
             check(lib.rt_build_tree(_ptr(self.vtx), self.vtx.shape[0], _ptr(self.tri), self.tri.shape[0],
                                     _ptr(self.material), _ptr(self.plane_id), ctypes.byref(prm),
                                     _stream(self.device), ctypes.byref(self._h)), "rt_build_tree")
-        info = (ctypes.c_int64 * 6)()
-        diag = (ctypes.c_double * 1)()
-        check(lib.rt_scene_info(self._h, info, diag), "rt_scene_info")
-        self.n_tri, self.n_mat, self.n_nodes, self.depth, self.leaf_size, self.n_ref = [int(v) for v in info]
-        self.diag = float(diag[0])
+        self.n_tri = int(self.tri.shape[0])
+        self.leaf_size = int(leaf_size)
+        self._info = None   # read on first use: rt_scene_info waits for the build to finish
+
+    def _scene_info(self):
+        if self._info is None:
+            info = (ctypes.c_int64 * 6)()
+            diag = (ctypes.c_double * 1)()
+            check(_lib.load().rt_scene_info(self.handle, info, diag), "rt_scene_info")
+            self._info = [int(v) for v in info] + [float(diag[0])]
+        return self._info
+
+    n_mat = property(lambda self: self._scene_info()[1])
+    n_nodes = property(lambda self: self._scene_info()[2])
+    depth = property(lambda self: self._scene_info()[3])
+    n_ref = property(lambda self: self._scene_info()[5])
+    diag = property(lambda self: self._scene_info()[6])
 
     @classmethod
     def from_synth(cls, s, leaf_size: int = 1, device=None) -> "Scene":

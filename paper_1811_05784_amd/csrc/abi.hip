@@ -128,6 +128,10 @@ extern "C" const char* rt_version(void) { return "librtac 0.1 (gfx950)"; }
 extern "C" int rt_scene_destroy(rt_scene* s) {
     if (!s) return RT_OK;
     (void)hipDeviceSynchronize();
+    for (void* p : s->pending) rtac::dcache_free(p);
+    s->pending.clear();
+    rtac::dcache_free(s->info_dev);
+    if (s->built) (void)hipEventDestroy(s->built);
     rtac::dcache_free(s->nodes);
     rtac::dcache_free(s->tri_rec);
     rtac::dcache_free(s->plane_n);
@@ -139,8 +143,22 @@ extern "C" int rt_scene_destroy(rt_scene* s) {
     return RT_OK;
 }
 
-extern "C" int rt_scene_info(const rt_scene* s, int64_t* info, double* diag) {
-    RT_CHECK(s != nullptr, RT_EINVAL, "rt_scene_info: null scene");
+extern "C" int rt_scene_info(const rt_scene* cs, int64_t* info, double* diag) {
+    RT_CHECK(cs != nullptr, RT_EINVAL, "rt_scene_info: null scene");
+    rt_scene* s = const_cast<rt_scene*>(cs);
+    if (info && !s->exact) {
+        // the first query waits for the build and reads the node count and depth
+        uint32_t h[4];
+        RT_HIP(hipEventSynchronize(s->built));
+        RT_HIP(hipMemcpy(h, s->info_dev, sizeof(h), hipMemcpyDeviceToHost));
+        RT_CHECK(h[3] >= 1 && (int64_t)h[3] <= s->n_nodes && (int32_t)h[2] <= s->depth, RT_EHIP,
+                 "rt_scene_info: inconsistent tree");
+        s->n_nodes = (int32_t)h[3];
+        s->depth = (int32_t)h[2];
+        s->exact = true;
+        for (void* p : s->pending) rtac::dcache_free(p);
+        s->pending.clear();
+    }
     if (info) {
         info[0] = s->n_tri;
         info[1] = s->n_mat;

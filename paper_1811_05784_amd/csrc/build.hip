@@ -838,7 +838,9 @@ extern "C" int rt_build_tree(const float* vtx, int64_t n_vtx, const int32_t* tri
     float* tri_box = tmp.get<float>(6 * nt);
     float* cen = tmp.get<float>(3 * nt);
     uint32_t* bounds = tmp.get<uint32_t>(12);
-    uint32_t* info = tmp.get<uint32_t>(8);   // [0] errors [1] max material [2] depth [3] 4-wide nodes [4] references
+    // [0] errors [1] max material [2] depth [3] 4-wide nodes [4] references; kept with the scene
+    uint32_t* info = (uint32_t*)dcache_alloc(sizeof(uint32_t) * 8);
+    s->info_dev = info;
     uint32_t* prep_part = tmp.get<uint32_t>(14 * (int64_t)blocks(nt));
     int32_t* prep = tmp.get<int32_t>(nt);
     uint32_t* ref_cnt = tmp.get<uint32_t>(nt);
@@ -863,8 +865,11 @@ extern "C" int rt_build_tree(const float* vtx, int64_t n_vtx, const int32_t* tri
     if (rc) return fail(rc);
     hipLaunchKernelGGL(k_copy_u32, dim3(1), dim3(1), 0, st, ref_off + nt, info + 4);
     RT_HIP(hipGetLastError());
+    // the one wait of the build: the reference count sizes the per-reference
+    // arrays; the scene box and the largest material are final by now
     uint32_t h_info[5], h_bounds[12];
     RT_HIP(hipMemcpyAsync(h_info, info, sizeof(h_info), hipMemcpyDeviceToHost, st));
+    RT_HIP(hipMemcpyAsync(h_bounds, bounds, sizeof(h_bounds), hipMemcpyDeviceToHost, st));
     RT_HIP(hipStreamSynchronize(st));
     if (h_info[0]) {
         set_error("rt_build_tree: %s", err_text(h_info[0]));
@@ -963,9 +968,10 @@ extern "C" int rt_build_tree(const float* vtx, int64_t n_vtx, const int32_t* tri
     hipLaunchKernelGGL(k_tri_records, dim3(blocks(nr)), dim3(256), 0, st, vtx, n_vtx, (const int3*)tri, nr, material,
                        s->tri_plane, order, ref_tri, s->tri_rec);
     RT_HIP(hipGetLastError());
-    RT_HIP(hipMemcpyAsync(h_info, info, sizeof(h_info), hipMemcpyDeviceToHost, st));
-    RT_HIP(hipMemcpyAsync(h_bounds, bounds, sizeof(h_bounds), hipMemcpyDeviceToHost, st));
-    RT_HIP(hipStreamSynchronize(st));
+    // No wait at the end: the node count and depth stay on the device until
+    // rt_scene_info asks for them (the trace sizes its stack spill area from a
+    // bound on the depth and checks node references against the capacity), and
+    // the temporaries are released once the build is known to have finished.
     s->n_mat = (int32_t)h_info[1] + 1;
     double d2 = 0;
     for (int c = 0; c < 3; c++) {
@@ -975,9 +981,21 @@ extern "C" int rt_build_tree(const float* vtx, int64_t n_vtx, const int32_t* tri
         d2 += e * e;
     }
     s->diag = std::sqrt(d2);
-    s->n_nodes = single ? 1 : (int32_t)h_info[3];
-    s->depth = single ? 1 : (int32_t)h_info[2];
-    RT_CHECK(s->n_nodes >= 1 && s->n_nodes <= node_cap, RT_EHIP, "rt_build_tree: inconsistent tree");
+    if (single) {
+        s->n_nodes = 1;
+        s->depth = 1;
+    } else {
+        // a root-to-leaf path of the binary tree fixes one more bit of the
+        // (30-bit Morton code, reference index) key per level
+        int bits = 1;
+        while (bits < 40 && ((int64_t)1 << bits) < nr) bits++;
+        s->n_nodes = (int32_t)node_cap;
+        s->depth = (30 + bits + 1) / 2 + 2;
+        s->exact = false;
+    }
+    RT_HIP(hipEventCreateWithFlags(&s->built, hipEventDisableTiming));
+    RT_HIP(hipEventRecord(s->built, st));
+    s->pending.swap(tmp.ptrs);
     *out_scene = s;
     return RT_OK;
 }

@@ -152,8 +152,12 @@ struct rt_scene {
     int64_t n_vtx = 0;
     int32_t n_mat = 0;
     int32_t leaf_size = 1;
-    int32_t n_nodes = 0;
-    int32_t depth = 0;          // 4-wide tree depth (levels of inner nodes)
+    int32_t n_nodes = 0;        // 4-wide nodes; until `exact`, the allocated capacity
+    int32_t depth = 0;          // 4-wide tree depth (levels of inner nodes); until `exact`, a bound
+    bool exact = true;          // n_nodes and depth read back from the device
+    uint32_t* info_dev = nullptr;   // build counters on the device ([2] depth, [3] 4-wide nodes)
+    hipEvent_t built = nullptr;     // recorded after the build's last kernel
+    std::vector<void*> pending;     // build temporaries, released once the build has finished
     double diag = 0.0;
     float bounds[6] = {0, 0, 0, 0, 0, 0};
     // device arrays
