@@ -308,6 +308,23 @@ def test_scheduling_leaves_results_unchanged(rt, scenes, name, R, n, kw):
     assert np.array_equal(_sorted_det(a), _sorted_det(b))
 
 
+def test_trace_before_scene_info_matches_after(rt):
+    """rt_build_tree returns before its last kernels finish; a trace launched
+    right away uses the node capacity and a depth bound, and must give the same
+    results as one launched after rt_scene_info has read the exact node count
+    and depth back (which lie within that capacity and bound)."""
+    s = synth.tessellated_box_c2(jitter=True)
+    sc = rt.Scene.from_synth(s, device="cuda:0")
+    dirs = rt.fibonacci_directions(50_000, device="cuda:0")
+    a = rt.trace_rays(sc, dirs, s.rcv, 20, src=s.src)
+    n_nodes, depth, n_ref = sc.n_nodes, sc.depth, sc.n_ref
+    assert 1 <= n_nodes <= n_ref - 1 and 1 <= depth <= 40 and n_ref >= s.n_tri
+    b = rt.trace_rays(sc, dirs, s.rcv, 20, src=s.src)
+    assert torch.equal(a.hit_seq, b.hit_seq)
+    assert torch.equal(a.counters[:3], b.counters[:3]) and int(a.counters[3]) == 0 and int(b.counters[3]) == 0
+    assert np.array_equal(_sorted_det(a), _sorted_det(b))
+
+
 def test_trace_rays_graph_replay_matches_eager(rt, scenes):
     """rt_trace_rays captured in a HIP graph (reset, ray ordering, -1 fill of
     the hit rows, traversal): every replay, after eager work has zeroed the
