@@ -5,14 +5,23 @@ from a point source, up to 60 reflections, 8 receiver spheres (r = 2 m), 2 s
 impulse response at 48 kHz, 8 octave bands (K = 4095 FIR taps):
 scene ingest + tree build, ray generation, trace, image-source collection,
 impulse-response assembly.  Inputs are resident in HBM before timing.
+Steps are independent jobs kept in flight on --streams streams (default 3):
+step i runs on stream i mod 3 with that stream's own scene, rebuilt in place
+each step, and output buffers, so the builds, collections and IRs of some
+steps overlap the traces of others; --streams 1 runs one step at a time.
 
-value = device-counted ray segments (rays x bounces) / step time.
+value = device-counted ray segments (rays x bounces) per step x steps / wall
+time of the timed steps.
+phase_ms and roofline: as many steps again, run one at a time on one stream
+after the timed steps (with --streams 1 these are the timed steps).
 roofline: the traversal kernel's algorithmic bytes per query
 B(M) = 76 + 48 ceil(log2 M) + 40 (ray state, one root-to-leaf path of 2-child
 boxes, one triangle) times queries per launch, over the traversal kernel's
-own HIP-event time (events recorded by the library around its launch, on
-its stream), vs the 8 TB/s HBM peak.  cpu_baseline: the FP64 brute-force oracle on a bounded
-sample of the same rays.
+own HIP-event time (events recorded by the library around its launch, on its
+stream) in those one-at-a-time steps, vs the 8 TB/s HBM peak; the same events
+in the timed steps, where a launch shares the GPU with the steps in flight
+beside it, are reported as kernel_ms_in_flight.
+cpu_baseline: the FP64 brute-force oracle on a bounded sample of the same rays.
 """
 import argparse
 import json
@@ -36,7 +45,7 @@ def algorithmic_bytes_per_query(m: int) -> int:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--rays", type=int, default=1_000_000)
     ap.add_argument("--cpu-rays", type=int, default=30000, help="oracle sample size (rays)")
@@ -52,6 +61,8 @@ def main():
     ap.add_argument("--suspend", type=int, default=0,
                     help="queue rays continuing past this segment for a second launch (0 = off)")
     ap.add_argument("--stats", action="store_true", help="count traversal work (extra pass, not timed)")
+    ap.add_argument("--streams", type=int, default=3,
+                    help="theater: steps in flight, one stream each (1 = one step at a time)")
     ap.add_argument("--no-copy-bw", action="store_true",
                     help="skip the device-copy bandwidth measurement (profiling runs: it adds copy kernels)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -104,40 +115,50 @@ def run_theater(args):
     beta = torch.as_tensor(s.beta, device=dev)
     fir = torch.as_tensor(taps, device=dev)
     det_cap = 6 * args.rays
-    stream = torch.cuda.current_stream()
+    # Steps in flight: step i runs on stream i mod n_streams, with that
+    # stream's own scene (rebuilt in place every step) and output buffers, so
+    # one step's build, collection and IR overlap the neighbouring steps'
+    # traces.  n_streams = 1: one step at a time on the current stream.
+    n_streams = max(1, args.streams)
+    streams = ([torch.cuda.current_stream()] if n_streams == 1 else
+               [torch.cuda.Stream(device=dev) for _ in range(n_streams)])
+    slots = [{} for _ in range(n_streams)]
+    phases = ("build", "raygen", "trace", "collect", "assemble", "k_trace")
 
-    ev = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for k in ("build", "raygen", "trace", "collect", "assemble", "k_trace")}
-    state = {}
-
-    def step(record=False):
-        def mark(name, i):
-            if record:
-                ev[name][i].record(stream)
-        mark("build", 0)
-        sc = rt.Scene(vtx, tri, mat, pid, leaf_size=args.leaf, device=dev)
-        mark("build", 1)
-        mark("raygen", 0)
-        dirs = rt.fibonacci_directions(args.rays, device=dev)
-        mark("raygen", 1)
-        mark("trace", 0)
-        tr = rt.trace_rays(sc, dirs, rcv, R, src=s.src, max_path_length=s.max_path_length, det_cap=det_cap,
-                           check_capacity=False, out=state.get("tr"), shade_threshold=args.shade,
-                           fetch_threshold=args.fetch, blocks_per_cu=args.bpc, keep_order=args.keep_order,
-                           rounds=args.rounds, spill_threshold=args.spill, waves_per_simd=args.wps,
-                           kernel_events=ev["k_trace"] if record else None, suspend_after=args.suspend)
-        mark("trace", 1)
-        state["tr"] = tr
-        mark("collect", 0)
-        isrc = rt.collect_image_sources(sc, s.src, rcv, tr, is_cap=det_cap, check_capacity=False)
-        mark("collect", 1)
-        mark("assemble", 0)
-        ir = rt.assemble_ir(sc, isrc, args.rays, n_rcv, alpha, beta, s.c, s.fs, L, fir, out=state.get("ir"))
-        mark("assemble", 1)
-        state["ir"] = ir
-        state["isrc"] = isrc
-        state["scene"] = sc
-        return sc
+    def step(i, ev=None):
+        k = i % n_streams
+        sl = slots[k]
+        with torch.cuda.stream(streams[k]):
+            def mark(name, j):
+                if ev is not None:
+                    ev[name][j].record()
+            mark("build", 0)
+            if "scene" in sl:
+                sl["scene"].rebuild(vtx, tri, mat, pid, leaf_size=args.leaf)
+            else:
+                sl["scene"] = rt.Scene(vtx, tri, mat, pid, leaf_size=args.leaf, device=dev)
+            sc = sl["scene"]
+            mark("build", 1)
+            mark("raygen", 0)
+            dirs = rt.fibonacci_directions(args.rays, device=dev)
+            mark("raygen", 1)
+            mark("trace", 0)
+            tr = rt.trace_rays(sc, dirs, rcv, R, src=s.src, max_path_length=s.max_path_length, det_cap=det_cap,
+                               check_capacity=False, check_errors=False, out=sl.get("tr"),
+                               shade_threshold=args.shade, fetch_threshold=args.fetch, blocks_per_cu=args.bpc,
+                               keep_order=args.keep_order, rounds=args.rounds, spill_threshold=args.spill,
+                               waves_per_simd=args.wps, kernel_events=ev["k_trace"] if ev is not None else None,
+                               suspend_after=args.suspend)
+            mark("trace", 1)
+            sl["tr"] = tr
+            mark("collect", 0)
+            isrc = rt.collect_image_sources(sc, s.src, rcv, tr, is_cap=det_cap, check_capacity=False)
+            mark("collect", 1)
+            mark("assemble", 0)
+            ir = rt.assemble_ir(sc, isrc, args.rays, n_rcv, alpha, beta, s.c, s.fs, L, fir, out=sl.get("ir"))
+            mark("assemble", 1)
+            sl["ir"] = ir
+            sl["isrc"] = isrc
 
     if args.calib_copy_mb:
         src_buf = torch.ones(args.calib_copy_mb * (1 << 20) // 4, dtype=torch.float32, device=dev)
@@ -146,29 +167,47 @@ def run_theater(args):
         dst_buf.copy_(src_buf)
         torch.cuda.synchronize()
         del src_buf, dst_buf
-    for _ in range(args.warmup):
-        step()
+    # set-up: each stream's scene and buffers are made by one step of its own
+    for k in range(n_streams):
+        step(k)
     torch.cuda.synchronize()
-    c = state["tr"].counters.cpu()
-    if int(c[0]) > det_cap or int(c[3]) != 0 or state["isrc"].n_is() > det_cap:
-        raise SystemExit("capacity or device error: counters=%s n_is=%d" % (c.tolist(), state["isrc"].n_is()))
-    phase = {k: 0.0 for k in ev}
+    for i in range(args.warmup):
+        step(i)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(record=True)
+    for sl in slots:
+        c = sl["tr"].counters.cpu()
+        if int(c[0]) > det_cap or int(c[3]) != 0 or sl["isrc"].n_is() > det_cap:
+            raise SystemExit("capacity or device error: counters=%s n_is=%d" % (c.tolist(), sl["isrc"].n_is()))
+    def timed(n, base, one_at_a_time):
+        evs = [{k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for k in phases}
+               for _ in range(n)]
         torch.cuda.synchronize()
-        for k, (a, b) in ev.items():
-            phase[k] += a.elapsed_time(b)
-    t1 = time.perf_counter()
-    ms = (t1 - t0) * 1e3 / args.steps
-    phase = {k: v / args.steps for k, v in phase.items()}
+        t0 = time.perf_counter()
+        for i in range(n):
+            step(base + i * (n_streams if one_at_a_time else 1), evs[i])
+            if one_at_a_time:
+                torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        return (t1 - t0) * 1e3 / n, {k: sum(e[k][0].elapsed_time(e[k][1]) for e in evs) / n for k in phases}
+
+    # throughput: the timed steps, n_streams of them in flight
+    ms, phase_in_flight = timed(args.steps, args.warmup, n_streams == 1)
+    for sl in slots:
+        c = sl["tr"].counters.cpu()
+        if int(c[0]) > det_cap or int(c[3]) != 0:
+            raise SystemExit("capacity or device error in the timed steps: counters=%s" % (c.tolist(),))
+    # phases and the trace kernel on their own: as many steps again, one at a
+    # time on the first stream (the same as the timed steps when n_streams = 1)
+    serial_ms, phase = (ms, phase_in_flight) if n_streams == 1 else timed(args.steps, 0, True)
+    state = slots[0]
     c = state["tr"].counters.cpu()
     queries = int(c[1])
     value = queries / (ms * 1e-3)
     B = algorithmic_bytes_per_query(s.n_tri)
     trace_ms = phase["trace"]
     kernel_ms = phase.pop("k_trace")
+    kernel_in_flight_ms = phase_in_flight.pop("k_trace")
     achieved = queries * B / (kernel_ms * 1e-3) / 1e9
 
     out = {
@@ -187,15 +226,23 @@ def run_theater(args):
         "config": {"workload": "open-air theater 436,120 tris, 1e6 rays, R=60, 8 receivers r=2 m, 2 s IR "
                                "@48 kHz, 8 bands, K=4095", "n_tri": s.n_tri, "rays": args.rays,
                    "max_reflections": R, "receivers": n_rcv, "ir_samples": L, "leaf_size": args.leaf},
+        "steps_in_flight": n_streams,
+        "serial_ms_per_step": serial_ms,
         "queries": queries,
         "detections": int(c[0]),
         "escapes": int(c[2]),
         "image_sources": state["isrc"].n_is(),
         "phase_ms": phase,
+        "phase_ms_in_flight": phase_in_flight,
         "trace_rays_bounces_per_s": queries / (trace_ms * 1e-3),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_trace", "bytes_per_query": B, "kernel_ms": kernel_ms},
+                     "kernel": "k_trace", "bytes_per_query": B, "kernel_ms": kernel_ms,
+                     "kernel_ms_in_flight": kernel_in_flight_ms,
+                     "timing": "kernel_ms: the library's HIP events around k_trace, averaged over steps run one "
+                               "at a time (the kernel alone on the GPU); kernel_ms_in_flight: the same events "
+                               "in the timed steps, where a launch shares the GPU with the steps in flight "
+                               "beside it"},
     }
     if args.stats:
         st = torch.zeros(4, dtype=torch.int64, device=dev)

@@ -9,12 +9,15 @@
  *     parameter name ends in _host.  Layouts are row-major, C-contiguous.
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *     Calls enqueue kernels on it and return without waiting, except
- *     rt_build_tree, which synchronises once to validate the mesh.
+ *     rt_build_tree and rt_rebuild_tree, which synchronise once to validate
+ *     the mesh.
  *   - The caller owns every input and output buffer; the library owns the
  *     rt_scene object and the scratch memory attached to it.  Scratch grows
  *     on demand (hipMalloc outside any kernel) and is freed by
  *     rt_scene_destroy.  Calls sharing one scene must be ordered on one
- *     stream.
+ *     stream; different scenes may work on different streams at the same
+ *     time (freed scratch is reused only once the freeing call's stream has
+ *     passed the point of the free).
  *   - Return value: RT_OK (0) or a negative status; rt_last_error() gives a
  *     thread-local message.  No call throws or aborts.  Outputs that the
  *     device can only size after the fact (detections, image sources) are
@@ -78,11 +81,33 @@ typedef struct {
  * RT_ENOMEM, RT_EHIP.  Synchronises `stream` once (validation and the
  * reference count, which sizes the per-reference arrays); the rest of the
  * build runs on after the call returns (the first rt_scene_info call waits for
- * it; the build's temporaries are kept until then or rt_scene_destroy).
+ * it; the build's temporaries are kept until then, or until rt_scene_destroy).
  */
 int rt_build_tree(const float* vtx, int64_t n_vtx, const int32_t* tri, int64_t n_tri,
                   const int32_t* material, const int32_t* plane_id, const rt_build_params* params,
                   void* stream, rt_scene** out_scene);
+
+/*
+ * rt_rebuild_tree -- the same build as rt_build_tree (same section, same
+ * arguments and errors), into an existing scene: the tree, triangle records
+ * and plane table are replaced by those of the new mesh, reusing the scene's
+ * device memory (nothing is allocated when the mesh is no larger than the
+ * one of an earlier build of this scene and rt_scene_info has not released
+ * the temporaries since).  For a caller that re-runs the whole path per frame
+ * or per job, e.g. one scene per stream with the jobs of several streams
+ * overlapping on the GPU.
+ *   scene   a scene from rt_build_tree on the current device.  Earlier calls
+ *           that use it must be on `stream` (in stream order they finish
+ *           before the rebuild overwrites what they read) or finished.
+ *   others  as for rt_build_tree.
+ * Batches made from the scene (rt_batch_create) hold its old sizes and
+ * addresses: destroy and recreate them after a rebuild.  On any error the
+ * scene is marked invalid (every call that takes it returns RT_EINVAL) until
+ * a rebuild succeeds; rt_scene_destroy still frees it.
+ */
+int rt_rebuild_tree(rt_scene* scene, const float* vtx, int64_t n_vtx, const int32_t* tri, int64_t n_tri,
+                    const int32_t* material, const int32_t* plane_id, const rt_build_params* params,
+                    void* stream);
 
 /* Frees the scene and its scratch (synchronises the device). */
 int rt_scene_destroy(rt_scene* scene);

@@ -37,6 +37,7 @@ class Job(ctypes.Structure):
 # symbol -> (restype, argtypes); mirrors include/rtac.h
 SIGNATURES = {
     "rt_build_tree": (ctypes.c_int, [P, I64, P, I64, P, P, ctypes.POINTER(BuildParams), P, ctypes.POINTER(P)]),
+    "rt_rebuild_tree": (ctypes.c_int, [P, P, I64, P, I64, P, P, ctypes.POINTER(BuildParams), P]),
     "rt_scene_destroy": (ctypes.c_int, [P]),
     "rt_scene_info": (ctypes.c_int, [P, P, P]),
     "rt_fibonacci_directions": (ctypes.c_int, [I64, P, P]),

@@ -76,6 +76,29 @@ class Scene:
             self._info = [int(v) for v in info] + [float(diag[0])]
         return self._info
 
+    def rebuild(self, vtx, tri, material, plane_id=None, leaf_size=None) -> "Scene":
+        """Replace this scene's mesh and tree with those of a new (or the same)
+        mesh, built on the current stream into the scene's own device memory
+        (rt_rebuild_tree).  Earlier calls on the scene must be on the same
+        stream or finished; batches made from it must be recreated."""
+        lib = _lib.load()
+        v = _to_dev(vtx, torch.float32, self.device)
+        t = _to_dev(tri, torch.int32, self.device)
+        m = _to_dev(material, torch.int32, self.device)
+        pid = None if plane_id is None else _to_dev(plane_id, torch.int32, self.device)
+        leaf = self.leaf_size if leaf_size is None else int(leaf_size)
+        prm = BuildParams(leaf)
+        with torch.cuda.device(self.device):
+            rc = lib.rt_rebuild_tree(self.handle, _ptr(v), v.shape[0], _ptr(t), t.shape[0], _ptr(m), _ptr(pid),
+                                     ctypes.byref(prm), _stream(self.device))
+        # the build reads its inputs after the call returns: keep them with the scene
+        self.vtx, self.tri, self.material, self.plane_id = v, t, m, pid
+        self._info = None
+        check(rc, "rt_rebuild_tree")
+        self.n_tri = int(t.shape[0])
+        self.leaf_size = leaf
+        return self
+
     n_mat = property(lambda self: self._scene_info()[1])
     n_nodes = property(lambda self: self._scene_info()[2])
     depth = property(lambda self: self._scene_info()[3])

@@ -18,16 +18,53 @@ void set_error(const char* fmt, ...) {
 }
 
 namespace {
+struct Held {
+    hipEvent_t ev;   // recorded on the freeing call's stream
+    std::pair<int, size_t> key;
+    void* p;
+};
 struct Cache {
     std::mutex mu;
     std::map<void*, std::pair<int, size_t>> live;          // ptr -> (device, bytes)
     std::multimap<std::pair<int, size_t>, void*> free_;    // (device, bytes) -> ptr
+    std::vector<Held> held;                                 // freed, waiting for their event
+    std::vector<hipEvent_t> spare;                          // completed events for reuse
 };
 Cache& cache() {
     static Cache* c = new Cache();   // never destroyed: freed blocks live until exit
     return *c;
 }
+thread_local hipStream_t t_stream = nullptr;
+thread_local bool t_has_stream = false;
+
+// Moves held blocks whose event has completed to the free lists (lock held).
+void release_completed(Cache& c) {
+    bool queried_busy = false;
+    for (size_t i = 0; i < c.held.size();) {
+        const hipError_t q = hipEventQuery(c.held[i].ev);
+        if (q == hipSuccess) {
+            c.free_.insert({c.held[i].key, c.held[i].p});
+            c.spare.push_back(c.held[i].ev);
+            c.held[i] = c.held.back();
+            c.held.pop_back();
+        } else {
+            queried_busy = true;
+            i++;
+        }
+    }
+    if (queried_busy) (void)hipGetLastError();   // "not ready" is no error of the caller's
+}
 }  // namespace
+
+CallStream::CallStream(hipStream_t s) : prev(t_stream), had(t_has_stream) {
+    t_stream = s;
+    t_has_stream = true;
+}
+
+CallStream::~CallStream() {
+    t_stream = prev;
+    t_has_stream = had;
+}
 
 void* dcache_alloc(size_t bytes) {
     if (bytes == 0) bytes = 1;
@@ -37,6 +74,7 @@ void* dcache_alloc(size_t bytes) {
     Cache& c = cache();
     {
         std::lock_guard<std::mutex> g(c.mu);
+        if (!c.held.empty()) release_completed(c);
         auto it = c.free_.lower_bound({dev, bytes});
         if (it != c.free_.end() && it->first.first == dev && it->first.second <= 2 * bytes) {
             void* p = it->second;
@@ -50,6 +88,7 @@ void* dcache_alloc(size_t bytes) {
         (void)hipGetLastError();
         // give cached blocks back to the runtime and retry once
         std::lock_guard<std::mutex> g(c.mu);
+        release_completed(c);
         for (auto it = c.free_.begin(); it != c.free_.end();) {
             if (it->first.first == dev) {
                 (void)hipFree(it->second);
@@ -75,8 +114,29 @@ void dcache_free(void* p) {
     std::lock_guard<std::mutex> g(c.mu);
     auto it = c.live.find(p);
     if (it == c.live.end()) return;
-    c.free_.insert({it->second, p});
+    const std::pair<int, size_t> key = it->second;
     c.live.erase(it);
+    if (t_has_stream) {
+        // fence the block on the calling stream (not while it is being
+        // captured into a graph: there the caller keeps its buffers alive)
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(t_stream, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) {
+            hipEvent_t ev = nullptr;
+            if (!c.spare.empty()) {
+                ev = c.spare.back();
+                c.spare.pop_back();
+            } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+                ev = nullptr;
+            }
+            if (ev && hipEventRecord(ev, t_stream) == hipSuccess) {
+                c.held.push_back({ev, key, p});
+                return;
+            }
+            if (ev) c.spare.push_back(ev);
+        }
+        (void)hipGetLastError();
+    }
+    c.free_.insert({key, p});
 }
 
 int Buf::ensure(size_t n) {
@@ -128,16 +188,11 @@ extern "C" const char* rt_version(void) { return "librtac 0.1 (gfx950)"; }
 extern "C" int rt_scene_destroy(rt_scene* s) {
     if (!s) return RT_OK;
     (void)hipDeviceSynchronize();
-    for (void* p : s->pending) rtac::dcache_free(p);
-    s->pending.clear();
-    rtac::dcache_free(s->info_dev);
+    for (rtac::Buf& b : s->tmp) b.release();
+    for (rtac::Buf* b : {&s->m_nodes, &s->m_tri_rec, &s->m_plane_n, &s->m_plane_p, &s->m_plane_mat, &s->m_tri_plane,
+                         &s->m_info})
+        b->release();
     if (s->built) (void)hipEventDestroy(s->built);
-    rtac::dcache_free(s->nodes);
-    rtac::dcache_free(s->tri_rec);
-    rtac::dcache_free(s->plane_n);
-    rtac::dcache_free(s->plane_p);
-    rtac::dcache_free(s->plane_mat);
-    rtac::dcache_free(s->tri_plane);
     s->ws.release_all();
     delete s;
     return RT_OK;
@@ -145,6 +200,7 @@ extern "C" int rt_scene_destroy(rt_scene* s) {
 
 extern "C" int rt_scene_info(const rt_scene* cs, int64_t* info, double* diag) {
     RT_CHECK(cs != nullptr, RT_EINVAL, "rt_scene_info: null scene");
+    RT_CHECK(cs->valid, RT_EINVAL, "rt_scene_info: the scene's last rebuild failed");
     rt_scene* s = const_cast<rt_scene*>(cs);
     if (info && !s->exact) {
         // the first query waits for the build and reads the node count and depth
@@ -156,8 +212,9 @@ extern "C" int rt_scene_info(const rt_scene* cs, int64_t* info, double* diag) {
         s->n_nodes = (int32_t)h[3];
         s->depth = (int32_t)h[2];
         s->exact = true;
-        for (void* p : s->pending) rtac::dcache_free(p);
-        s->pending.clear();
+        // the build has finished: its temporaries go back to the cache (a
+        // rebuild takes them again)
+        for (rtac::Buf& b : s->tmp) b.release();
     }
     if (info) {
         info[0] = s->n_tri;

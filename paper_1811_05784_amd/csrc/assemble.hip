@@ -513,6 +513,7 @@ int check_is_args(const rt_scene* s, const int32_t* is_key, const int32_t* is_co
                   const int64_t* n_is, int64_t is_cap, int32_t R, int64_t n_rays, int32_t n_rcv, const float* alpha,
                   const float* beta, float c, float fs, int64_t L) {
     RT_CHECK(s && n_is && alpha && beta, RT_EINVAL, "null argument");
+    RT_CHECK(s->valid, RT_EINVAL, "the scene's last rebuild failed");
     RT_CHECK(is_cap >= 0 && (is_cap == 0 || (is_key && is_count && is_dist)), RT_EINVAL, "null image-source table");
     RT_CHECK(is_cap < ((int64_t)1 << 31), RT_EINVAL, "is_cap must be < 2^31");
     RT_CHECK(R >= 0 && R < 4096, RT_EINVAL, "max_reflections out of range");
@@ -675,6 +676,7 @@ extern "C" int rt_assemble_ir(const rt_scene* scene, const int32_t* is_key, cons
                               int64_t n_rays, int32_t n_rcv, const float* alpha, const float* beta, float c, float fs,
                               int64_t L, const float* fir, int32_t K, float* band_energy, float* hist, float* band_ir,
                               float* ir, void* stream) {
+    CallStream call_stream((hipStream_t)stream);
     return assemble_common(scene, nullptr, is_key, is_count, is_dist, n_is, is_cap, max_reflections, n_rays, n_rcv,
                            alpha, beta, c, fs, L, fir, K, band_energy, hist, band_ir, ir, stream);
 }
@@ -683,6 +685,7 @@ extern "C" int rt_assemble_batch(rt_batch* b, const int32_t* is_key, const int32
                                  const int64_t* n_is, int64_t is_cap, int32_t max_reflections, const float* alpha,
                                  const float* beta, float c, float fs, int64_t L, const float* fir, int32_t K,
                                  float* band_energy, float* hist, float* band_ir, float* ir, void* stream) {
+    CallStream call_stream((hipStream_t)stream);
     RT_CHECK(b, RT_EINVAL, "rt_assemble_batch: null batch");
     return assemble_common(b->ws_owner, b, is_key, is_count, is_dist, n_is, is_cap, max_reflections, b->n_rays,
                            b->n_rcv, alpha, beta, c, fs, L, fir, K, band_energy, hist, band_ir, ir, stream);
@@ -730,6 +733,7 @@ extern "C" int rt_band_energy_adjoint(const rt_scene* scene, const int32_t* is_k
                                       int32_t max_reflections, int64_t n_rays, int32_t n_rcv, const float* alpha,
                                       int32_t n_mat, const float* beta, float c, float fs, int64_t L,
                                       const float* grad_band_energy, float* grad_alpha, void* stream) {
+    CallStream call_stream((hipStream_t)stream);
     return adjoint_common(scene, nullptr, is_key, is_count, is_dist, n_is, is_cap, max_reflections, n_rays, n_rcv,
                           alpha, n_mat, beta, c, fs, L, grad_band_energy, grad_alpha, stream);
 }
@@ -738,6 +742,7 @@ extern "C" int rt_adjoint_batch(rt_batch* b, const int32_t* is_key, const int32_
                                 const int64_t* n_is, int64_t is_cap, int32_t max_reflections, const float* alpha,
                                 const float* beta, float c, float fs, int64_t L, const float* grad_band_energy,
                                 float* grad_alpha, void* stream) {
+    CallStream call_stream((hipStream_t)stream);
     RT_CHECK(b, RT_EINVAL, "rt_adjoint_batch: null batch");
     return adjoint_common(b->ws_owner, b, is_key, is_count, is_dist, n_is, is_cap, max_reflections, b->n_rays,
                           b->n_rcv, alpha, b->n_mat, beta, c, fs, L, grad_band_energy, grad_alpha, stream);

@@ -1,4 +1,4 @@
-// Scene ingest and acceleration tree (rt_build_tree).
+// Scene ingest and acceleration tree (rt_build_tree, rt_rebuild_tree).
 //
 // The paper builds its tree once per mesh: a mother box holding every
 // element is split into two daughter boxes, recursively, down to one element
@@ -790,56 +790,56 @@ const char* err_text(uint32_t e) {
     return "invalid mesh";
 }
 
-struct TmpBufs {
-    std::vector<void*> ptrs;
-    ~TmpBufs() {
-        for (void* p : ptrs) dcache_free(p);
+// Device memory of one build: the scene's own arrays and its temporaries are
+// growable buffers of the scene, so a rebuild of a scene of the same size (or
+// smaller) allocates nothing.  A buffer that must grow returns its old block
+// fenced on the build's stream (work queued earlier may still read it).
+struct BuildMem {
+    rt_scene* s;
+    size_t next = 0;
+    template <class T>
+    T* keep(Buf& b, size_t count) {
+        return b.ensure(sizeof(T) * (count ? count : 1)) ? nullptr : b.as<T>();
     }
     template <class T>
     T* get(size_t count) {
-        void* p = dcache_alloc(sizeof(T) * (count ? count : 1));
-        if (p) ptrs.push_back(p);
-        return reinterpret_cast<T*>(p);
+        if (next == s->tmp.size()) s->tmp.emplace_back();
+        return keep<T>(s->tmp[next++], count);
     }
 };
 
-}  // namespace
+// Builds (fresh) or rebuilds the scene `s` on stream `st`.  On failure the
+// caller destroys a fresh scene; a rebuilt one is left marked invalid.
+// Host-side argument checks of a build (before any device call).
+int check_build_args(const char* who, const float* vtx, int64_t n_vtx, const int32_t* tri, int64_t n_tri,
+                     const int32_t* material, const rt_build_params* params) {
+    RT_CHECK(vtx && tri && material, RT_EINVAL, "%s: null input array", who);
+    RT_CHECK(n_tri >= 1 && n_vtx >= 3, RT_EINVAL, "%s: need n_tri >= 1 and n_vtx >= 3", who);
+    RT_CHECK(n_tri < kMaxTris, RT_EINVAL, "%s: n_tri must be < 2^27", who);
+    const int leaf = params ? params->leaf_size : 1;
+    RT_CHECK(leaf >= 1 && leaf <= kMaxLeaf, RT_EINVAL, "%s: leaf_size must be in [1, %d]", who, kMaxLeaf);
+    return RT_OK;
+}
 
-}  // namespace rtac
-
-using namespace rtac;
-
-extern "C" int rt_build_tree(const float* vtx, int64_t n_vtx, const int32_t* tri, int64_t n_tri,
-                             const int32_t* material, const int32_t* plane_id, const rt_build_params* params,
-                             void* stream, rt_scene** out_scene) {
-    RT_CHECK(out_scene != nullptr, RT_EINVAL, "rt_build_tree: out_scene is NULL");
-    *out_scene = nullptr;
-    RT_CHECK(vtx && tri && material, RT_EINVAL, "rt_build_tree: null input array");
-    RT_CHECK(n_tri >= 1 && n_vtx >= 3, RT_EINVAL, "rt_build_tree: need n_tri >= 1 and n_vtx >= 3");
-    RT_CHECK(n_tri < kMaxTris, RT_EINVAL, "rt_build_tree: n_tri must be < 2^27");
-    int leaf = params ? params->leaf_size : 1;
-    RT_CHECK(leaf >= 1 && leaf <= kMaxLeaf, RT_EINVAL, "rt_build_tree: leaf_size must be in [1, %d]", kMaxLeaf);
-    hipStream_t st = (hipStream_t)stream;
+int build_scene(rt_scene* s, const char* who, const float* vtx, int64_t n_vtx, const int32_t* tri, int64_t n_tri,
+                const int32_t* material, const int32_t* plane_id, const rt_build_params* params, hipStream_t st) {
+    s->valid = false;
+    const int leaf = params ? params->leaf_size : 1;
     const int64_t nt = n_tri;
-    TmpBufs tmp;
-    rt_scene* s = new rt_scene();
-    auto fail = [&](int code) {
-        rt_scene_destroy(s);
-        return code;
-    };
-    if (hipGetDevice(&s->device) != hipSuccess) return fail(RT_EHIP);
+    BuildMem tmp{s};
     s->n_tri = nt;
     s->n_vtx = n_vtx;
     s->leaf_size = leaf;
-    s->plane_n = (double*)dcache_alloc(sizeof(double) * 3 * nt);
-    s->plane_p = (double*)dcache_alloc(sizeof(double) * 3 * nt);
-    s->plane_mat = (int32_t*)dcache_alloc(sizeof(int32_t) * nt);
-    s->tri_plane = (int32_t*)dcache_alloc(sizeof(int32_t) * nt);
+    s->exact = true;
+    s->plane_n = tmp.keep<double>(s->m_plane_n, 3 * nt);
+    s->plane_p = tmp.keep<double>(s->m_plane_p, 3 * nt);
+    s->plane_mat = tmp.keep<int32_t>(s->m_plane_mat, nt);
+    s->tri_plane = tmp.keep<int32_t>(s->m_tri_plane, nt);
     float* tri_box = tmp.get<float>(6 * nt);
     float* cen = tmp.get<float>(3 * nt);
     uint32_t* bounds = tmp.get<uint32_t>(12);
     // [0] errors [1] max material [2] depth [3] 4-wide nodes [4] references; kept with the scene
-    uint32_t* info = (uint32_t*)dcache_alloc(sizeof(uint32_t) * 8);
+    uint32_t* info = tmp.keep<uint32_t>(s->m_info, 8);
     s->info_dev = info;
     uint32_t* prep_part = tmp.get<uint32_t>(14 * (int64_t)blocks(nt));
     int32_t* prep = tmp.get<int32_t>(nt);
@@ -847,8 +847,8 @@ extern "C" int rt_build_tree(const float* vtx, int64_t n_vtx, const int32_t* tri
     uint32_t* ref_off = tmp.get<uint32_t>(nt + 1);
     if (!s->plane_n || !s->plane_p || !s->plane_mat || !s->tri_plane || !tri_box || !cen || !bounds || !info ||
         !prep_part || !prep || !ref_cnt || !ref_off) {
-        set_error("rt_build_tree: out of device memory");
-        return fail(RT_ENOMEM);
+        set_error("%s: out of device memory", who);
+        return RT_ENOMEM;
     }
     hipLaunchKernelGGL(k_init_bounds, dim3(1), dim3(64), 0, st, bounds, info);
     hipLaunchKernelGGL(k_fill_i32, dim3(blocks(nt)), dim3(256), 0, st, prep, nt, INT32_MAX);
@@ -862,7 +862,7 @@ extern "C" int rt_build_tree(const float* vtx, int64_t n_vtx, const int32_t* tri
     // references: slab counts per triangle, their offsets, then the total
     hipLaunchKernelGGL(k_esc_count, dim3(blocks(nt)), dim3(256), 0, st, vtx, n_vtx, (const int3*)tri, nt, ref_cnt);
     int rc = exclusive_scan_u32(s->ws, ref_cnt, ref_off, nt, nullptr, st);
-    if (rc) return fail(rc);
+    if (rc) return rc;
     hipLaunchKernelGGL(k_copy_u32, dim3(1), dim3(1), 0, st, ref_off + nt, info + 4);
     RT_HIP(hipGetLastError());
     // the one wait of the build: the reference count sizes the per-reference
@@ -872,20 +872,20 @@ extern "C" int rt_build_tree(const float* vtx, int64_t n_vtx, const int32_t* tri
     RT_HIP(hipMemcpyAsync(h_bounds, bounds, sizeof(h_bounds), hipMemcpyDeviceToHost, st));
     RT_HIP(hipStreamSynchronize(st));
     if (h_info[0]) {
-        set_error("rt_build_tree: %s", err_text(h_info[0]));
+        set_error("%s: %s", who, err_text(h_info[0]));
         const bool degen = (h_info[0] & (kErrNonFinite | kErrZeroArea)) &&
                            !(h_info[0] & (kErrIndex | kErrPlaneRange | kErrMaterial));
-        return fail(degen ? RT_EDEGENERATE : RT_EINVAL);
+        return degen ? RT_EDEGENERATE : RT_EINVAL;
     }
     const int64_t nr = h_info[4];
-    RT_CHECK(nr >= nt && nr < kMaxTris, RT_EINVAL, "rt_build_tree: %lld references (at most 2^27)", (long long)nr);
+    RT_CHECK(nr >= nt && nr < kMaxTris, RT_EINVAL, "%s: %lld references (at most 2^27)", who, (long long)nr);
     const int64_t n_in = nr - 1;
     const bool single = n_in == 0 || nr <= leaf;
     // upper bound of 4-wide nodes: inner binary nodes (one per adjacent pair)
     const int64_t node_cap = single ? 1 : n_in;
     s->n_ref = nr;
-    s->tri_rec = (float4*)dcache_alloc(sizeof(float4) * 3 * nr);
-    s->nodes = (Node4*)dcache_alloc(sizeof(Node4) * node_cap);
+    s->tri_rec = tmp.keep<float4>(s->m_tri_rec, 3 * nr);
+    s->nodes = tmp.keep<Node4>(s->m_nodes, node_cap);
     float* ref_box = tmp.get<float>(6 * nr);
     uint32_t* ref_tri = tmp.get<uint32_t>(nr);
     uint64_t* codes0 = tmp.get<uint64_t>(nr);
@@ -893,8 +893,8 @@ extern "C" int rt_build_tree(const float* vtx, int64_t n_vtx, const int32_t* tri
     uint32_t* ord0 = tmp.get<uint32_t>(nr);
     uint32_t* ord1 = tmp.get<uint32_t>(nr);
     if (!s->tri_rec || !s->nodes || !ref_box || !ref_tri || !codes0 || !codes1 || !ord0 || !ord1) {
-        set_error("rt_build_tree: out of device memory");
-        return fail(RT_ENOMEM);
+        set_error("%s: out of device memory", who);
+        return RT_ENOMEM;
     }
     hipLaunchKernelGGL(k_esc_owner, dim3(blocks(nt)), dim3(256), 0, st, nt, ref_off, ref_tri);
     hipLaunchKernelGGL(k_esc_emit, dim3(blocks(nr)), dim3(256), 0, st, vtx, n_vtx, (const int3*)tri, nt, ref_off, nr,
@@ -902,7 +902,7 @@ extern "C" int rt_build_tree(const float* vtx, int64_t n_vtx, const int32_t* tri
     hipLaunchKernelGGL(k_morton, dim3(blocks(nr)), dim3(256), 0, st, ref_box, nr, bounds, codes0);
     int which = 0;
     rc = radix_sort_pairs(s->ws, codes0, ord0, codes1, ord1, nr, nullptr, 0, 3 * kMortonBits, st, &which, true);
-    if (rc) return fail(rc);
+    if (rc) return rc;
     uint64_t* codes = which ? codes1 : codes0;
     uint32_t* order = which ? ord1 : ord0;
     uint32_t* n4_dev = info + 3;
@@ -922,8 +922,8 @@ extern "C" int rt_build_tree(const float* vtx, int64_t n_vtx, const int32_t* tri
         int32_t* list4 = tmp.get<int32_t>(n_in);
         if (!left || !right || !first || !last || !par_in || !par_leaf || !depth || !box_in || !flag ||
             !index || !list4) {
-            set_error("rt_build_tree: out of device memory");
-            return fail(RT_ENOMEM);
+            set_error("%s: out of device memory", who);
+            return RT_ENOMEM;
         }
         hipLaunchKernelGGL(k_radix_tree, dim3(blocks(n_in)), dim3(256), 0, st, codes, nr, left, right, first, last,
                            par_in, par_leaf);
@@ -938,8 +938,8 @@ extern "C" int rt_build_tree(const float* vtx, int64_t n_vtx, const int32_t* tri
         }
         SegBox* segbuf = tmp.get<SegBox>(total);
         if (!segbuf) {
-            set_error("rt_build_tree: out of device memory");
-            return fail(RT_ENOMEM);
+            set_error("%s: out of device memory", who);
+            return RT_ENOMEM;
         }
         {
             SegOut segw;
@@ -959,7 +959,7 @@ extern "C" int rt_build_tree(const float* vtx, int64_t n_vtx, const int32_t* tri
         hipLaunchKernelGGL(k_flag4, dim3(blocks(n_in)), dim3(256), 0, st, n_in, first, last, par_in, leaf, flag,
                            depth);
         rc = exclusive_scan_u32(s->ws, flag, index, n_in, nullptr, st);
-        if (rc) return fail(rc);
+        if (rc) return rc;
         hipLaunchKernelGGL(k_list4, dim3(blocks(n_in)), dim3(256), 0, st, n_in, flag, index, list4);
         hipLaunchKernelGGL(k_emit4, dim3(blocks(n_in)), dim3(256), 0, st, n_in, left, right, first, last, list4,
                            index, depth, box_in, ref_box, order, leaf, s->nodes, info);
@@ -993,9 +993,52 @@ extern "C" int rt_build_tree(const float* vtx, int64_t n_vtx, const int32_t* tri
         s->depth = (30 + bits + 1) / 2 + 2;
         s->exact = false;
     }
-    RT_HIP(hipEventCreateWithFlags(&s->built, hipEventDisableTiming));
+    if (!s->built) RT_HIP(hipEventCreateWithFlags(&s->built, hipEventDisableTiming));
     RT_HIP(hipEventRecord(s->built, st));
-    s->pending.swap(tmp.ptrs);
+    s->valid = true;
+    return RT_OK;
+}
+
+}  // namespace
+
+}  // namespace rtac
+
+using namespace rtac;
+
+extern "C" int rt_build_tree(const float* vtx, int64_t n_vtx, const int32_t* tri, int64_t n_tri,
+                             const int32_t* material, const int32_t* plane_id, const rt_build_params* params,
+                             void* stream, rt_scene** out_scene) {
+    RT_CHECK(out_scene != nullptr, RT_EINVAL, "rt_build_tree: out_scene is NULL");
+    *out_scene = nullptr;
+    if (check_build_args("rt_build_tree", vtx, n_vtx, tri, n_tri, material, params)) return RT_EINVAL;
+    CallStream call_stream((hipStream_t)stream);
+    rt_scene* s = new rt_scene();
+    int rc = hipGetDevice(&s->device) == hipSuccess ? RT_OK : RT_EHIP;
+    if (rc) set_error("rt_build_tree: hipGetDevice failed");
+    if (!rc)
+        rc = build_scene(s, "rt_build_tree", vtx, n_vtx, tri, n_tri, material, plane_id, params,
+                         (hipStream_t)stream);
+    if (rc) {
+        rt_scene_destroy(s);
+        return rc;
+    }
     *out_scene = s;
     return RT_OK;
+}
+
+extern "C" int rt_rebuild_tree(rt_scene* scene, const float* vtx, int64_t n_vtx, const int32_t* tri, int64_t n_tri,
+                               const int32_t* material, const int32_t* plane_id, const rt_build_params* params,
+                               void* stream) {
+    RT_CHECK(scene != nullptr, RT_EINVAL, "rt_rebuild_tree: null scene");
+    if (check_build_args("rt_rebuild_tree", vtx, n_vtx, tri, n_tri, material, params)) {
+        scene->valid = false;
+        return RT_EINVAL;
+    }
+    int dev = -1;
+    RT_HIP(hipGetDevice(&dev));
+    RT_CHECK(dev == scene->device, RT_EINVAL, "rt_rebuild_tree: scene lives on device %d, current device is %d",
+             scene->device, dev);
+    CallStream call_stream((hipStream_t)stream);
+    return build_scene(scene, "rt_rebuild_tree", vtx, n_vtx, tri, n_tri, material, plane_id, params,
+                       (hipStream_t)stream);
 }

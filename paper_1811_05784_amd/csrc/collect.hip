@@ -342,7 +342,9 @@ int collect_common(rt_scene* s, const rt_batch* b, const float* src_host, const 
                    const int32_t* hit_seq, int64_t n_rays, int32_t max_reflections, const int32_t* det,
                    int64_t det_cap, const int64_t* n_det, int32_t* is_key, int32_t* is_count, double* is_pos,
                    double* is_dist, int64_t is_cap, int64_t* n_is, void* stream) {
+    CallStream call_stream((hipStream_t)stream);
     RT_CHECK(s && src_host && n_det && n_is, RT_EINVAL, "rt_collect_image_sources: null argument");
+    RT_CHECK(s->valid, RT_EINVAL, "rt_collect_image_sources: the scene's last rebuild failed");
     RT_CHECK(max_reflections >= 0 && max_reflections < 4096, RT_EINVAL,
              "rt_collect_image_sources: max_reflections out of range");
     RT_CHECK(n_rcv >= 1 && (b || n_rcv <= kMaxRcv) && rcv, RT_EINVAL, "rt_collect_image_sources: bad receivers");

@@ -155,9 +155,14 @@ struct rt_scene {
     int32_t n_nodes = 0;        // 4-wide nodes; until `exact`, the allocated capacity
     int32_t depth = 0;          // 4-wide tree depth (levels of inner nodes); until `exact`, a bound
     bool exact = true;          // n_nodes and depth read back from the device
+    bool valid = false;         // a build has succeeded (a failed rebuild clears it)
     uint32_t* info_dev = nullptr;   // build counters on the device ([2] depth, [3] 4-wide nodes)
     hipEvent_t built = nullptr;     // recorded after the build's last kernel
-    std::vector<void*> pending;     // build temporaries, released once the build has finished
+    // device memory of the build, kept so that a rebuild reuses it: the
+    // scene's arrays below, and the temporaries (released by rt_scene_info
+    // once the build has finished, taken again by the next rebuild)
+    rtac::Buf m_nodes, m_tri_rec, m_plane_n, m_plane_p, m_plane_mat, m_tri_plane, m_info;
+    std::vector<rtac::Buf> tmp;
     double diag = 0.0;
     float bounds[6] = {0, 0, 0, 0, 0, 0};
     // device arrays
@@ -194,9 +199,23 @@ int device_sm_count();
 
 // Process-wide caching device allocator (per device, best fit within 2x):
 // repeated scene builds and scratch growth reuse freed blocks instead of
-// calling hipMalloc/hipFree again.  Blocks are only returned to the cache
-// once no queued kernel uses them (after a synchronisation).
+// calling hipMalloc/hipFree again.  A block freed inside a call that works on
+// a stream (see CallStream) is held back until an event recorded on that
+// stream at the free has completed, so work already queued there can still
+// read it while other streams allocate; a block freed outside such a call
+// (after a synchronisation) is reusable at once.
 void* dcache_alloc(size_t bytes);
 void dcache_free(void* p);
+
+// Marks the stream of the entry point running on this thread for the
+// lifetime of the object (frees made meanwhile are fenced on it).
+struct CallStream {
+    explicit CallStream(hipStream_t s);
+    ~CallStream();
+    CallStream(const CallStream&) = delete;
+    CallStream& operator=(const CallStream&) = delete;
+    hipStream_t prev;
+    bool had;
+};
 
 }  // namespace rtac

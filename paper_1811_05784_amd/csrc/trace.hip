@@ -1311,7 +1311,9 @@ extern "C" int rt_trace_rays(const rt_scene* scene, const float* src_host, const
                              const int32_t* start_plane, const float* start_len, int64_t n_rays, const float* rcv,
                              int32_t n_rcv, const rt_trace_params* p, int32_t* hit_seq, int32_t* det, int64_t det_cap,
                              int64_t* counters, float* states, void* stream) {
+    CallStream call_stream((hipStream_t)stream);
     RT_CHECK(scene && p, RT_EINVAL, "rt_trace_rays: null scene or params");
+    RT_CHECK(scene->valid, RT_EINVAL, "rt_trace_rays: the scene's last rebuild failed");
     RT_CHECK(n_rays >= 0 && n_rays < ((int64_t)1 << 31), RT_EINVAL, "rt_trace_rays: n_rays out of range");
     if (check_params(p)) return RT_EINVAL;
     RT_CHECK(n_rcv >= 0 && n_rcv <= kMaxRcv, RT_EINVAL, "rt_trace_rays: n_rcv must be in [0, %d]", kMaxRcv);
@@ -1383,6 +1385,7 @@ extern "C" int rt_batch_create(const rt_scene* const* scenes, int32_t n_scenes, 
     for (int i = 0; i < n_scenes; i++) {
         const rt_scene* s = scenes[i];
         RT_CHECK(s, RT_EINVAL, "rt_batch_create: scene %d is NULL", i);
+        RT_CHECK(s->valid, RT_EINVAL, "rt_batch_create: scene %d: its last rebuild failed", i);
         hs[i] = DevScene{s->nodes, s->tri_rec, s->plane_n, s->plane_p, s->plane_mat, s->tri_plane, s->n_nodes,
                          (int32_t)s->n_tri, mat_off, s->n_mat, (int32_t)s->n_ref, 0};
         mat_off += s->n_mat;
@@ -1463,6 +1466,7 @@ extern "C" int rt_batch_info(const rt_batch* b, int64_t* info_host) {
 
 extern "C" int rt_trace_batch(rt_batch* b, const float* rcv, const rt_trace_params* p, int32_t* hit_seq, int32_t* det,
                               int64_t det_cap, int64_t* counters, float* states, void* stream) {
+    CallStream call_stream((hipStream_t)stream);
     RT_CHECK(b && rcv && hit_seq && counters, RT_EINVAL, "rt_trace_batch: null argument");
     if (check_params(p)) return RT_EINVAL;
     RT_CHECK(!p->record_states || states, RT_EINVAL, "rt_trace_batch: record_states needs states");
