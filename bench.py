@@ -199,7 +199,7 @@ def run_theater(args):
             raise SystemExit("capacity or device error in the timed steps: counters=%s" % (c.tolist(),))
     # phases and the trace kernel on their own: as many steps again, one at a
     # time on the first stream (the same as the timed steps when n_streams = 1)
-    serial_ms, phase = (ms, phase_in_flight) if n_streams == 1 else timed(args.steps, 0, True)
+    serial_ms, phase = (ms, dict(phase_in_flight)) if n_streams == 1 else timed(args.steps, 0, True)
     state = slots[0]
     c = state["tr"].counters.cpu()
     queries = int(c[1])

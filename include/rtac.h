@@ -486,6 +486,19 @@ int rt_room_params_noalloc(const float* hist, int32_t n_rcv, int64_t L, float fs
  * only speed changes. */
 int rt_debug_set_hash_bits(int bits);
 
+/* Test hook for the library's internal radix sort (used by the tree build,
+ * the ray order, the image-source collection and the IR assembly): sorts
+ * keys[0, n) by bits [begin_bit, end_bit) of each key, stably, in place, and
+ * writes to order[0, n) the position each key had before the sort.
+ *   keys   [cap] uint64 in/out;  order [cap] uint32 out
+ *   n_dev  device int64 count n (clamped to [0, cap]), or NULL for n = cap;
+ *          keys[n, cap) and order[n, cap) are unspecified afterwards
+ *   0 <= begin_bit < end_bit <= 64.
+ * Allocates its scratch per call (fenced frees on `stream`).  Errors: RT_EINVAL,
+ * RT_ENOMEM, RT_EHIP. */
+int rt_debug_radix_sort(uint64_t* keys, uint32_t* order, int64_t cap, const int64_t* n_dev, int32_t begin_bit,
+                        int32_t end_bit, void* stream);
+
 /* Thread-local message describing the last non-OK status of this thread. */
 const char* rt_last_error(void);
 

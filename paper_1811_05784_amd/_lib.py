@@ -69,6 +69,7 @@ SIGNATURES = {
     "rt_room_params": (ctypes.c_int, [P, I32, I64, F32, P, P]),
     "rt_room_params_noalloc": (ctypes.c_int, [P, I32, I64, F32, P, P]),
     "rt_debug_set_hash_bits": (ctypes.c_int, [ctypes.c_int]),
+    "rt_debug_radix_sort": (ctypes.c_int, [P, P, I64, P, I32, I32, P]),
     "rt_last_error": (ctypes.c_char_p, []),
     "rt_version": (ctypes.c_char_p, []),
 }

@@ -29,7 +29,7 @@ __device__ inline int64_t count_of(const int64_t* n_dev, int64_t cap) {
 __device__ inline int used_tiles(int64_t n) { return (int)((n + kTile - 1) / kTile); }
 
 __global__ void __launch_bounds__(kThreads) k_digit_hist(const uint64_t* __restrict__ keys, int64_t cap,
-                                                          const int64_t* n_dev, int shift,
+                                                          const int64_t* n_dev, int shift, uint32_t dmask,
                                                           uint32_t* __restrict__ hist) {
     __shared__ uint32_t h[256];
     const int tid = threadIdx.x;
@@ -42,7 +42,7 @@ __global__ void __launch_bounds__(kThreads) k_digit_hist(const uint64_t* __restr
 #pragma unroll 4
     for (int i = 0; i < kItems; i++) {
         int64_t idx = base + (int64_t)i * kThreads + tid;
-        if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & 255u], 1u);
+        if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & dmask], 1u);
     }
     __syncthreads();
     hist[(int64_t)tid * used + blockIdx.x] = h[tid];
@@ -149,7 +149,7 @@ __global__ void __launch_bounds__(kThreads) k_rank_scatter(const uint64_t* __res
                                                             const uint32_t* __restrict__ vin,
                                                             uint64_t* __restrict__ kout,
                                                             uint32_t* __restrict__ vout, int64_t cap,
-                                                            const int64_t* n_dev, int shift,
+                                                            const int64_t* n_dev, int shift, uint32_t dmask,
                                                             const uint32_t* __restrict__ offs,
                                                             const uint32_t* __restrict__ rowtot) {
     __shared__ uint32_t run[256];
@@ -183,7 +183,7 @@ __global__ void __launch_bounds__(kThreads) k_rank_scatter(const uint64_t* __res
         const bool valid = idx < n;
         uint64_t key = valid ? kin[idx] : 0ull;
         uint32_t val = valid ? (vin ? vin[idx] : (uint32_t)idx) : 0u;
-        uint32_t d = (uint32_t)(key >> shift) & 255u;
+        uint32_t d = (uint32_t)(key >> shift) & dmask;
 #pragma unroll
         for (int w = 0; w < kWaves; w++) wcnt[w][tid] = 0;
         __syncthreads();
@@ -275,6 +275,8 @@ int radix_sort_pairs(Workspace& ws, uint64_t* k0, uint32_t* v0, uint64_t* k1, ui
                      bool iota_values) {
     *out_index = 0;
     if (cap <= 0) return RT_OK;
+    RT_CHECK(begin_bit >= 0 && end_bit <= 64, RT_EINVAL, "radix sort: bits [%d, %d) out of range", begin_bit,
+             end_bit);
     const int nblocks = (int)((cap + kTile - 1) / kTile);
     const int64_t hlen = (int64_t)256 * nblocks;
     if (ws.sort_hist.ensure(sizeof(uint32_t) * (size_t)(hlen + 256))) return RT_ENOMEM;
@@ -287,11 +289,13 @@ int radix_sort_pairs(Workspace& ws, uint64_t* k0, uint32_t* v0, uint64_t* k1, ui
     int cur = 0;
     bool first = true;
     for (int shift = begin_bit; shift < end_bit; shift += 8) {
-        hipLaunchKernelGGL(k_digit_hist, dim3(nblocks), dim3(kThreads), 0, st, kin, cap, n_dev, shift, hist);
+        // the last digit ends at end_bit
+        const uint32_t dmask = end_bit - shift >= 8 ? 255u : (1u << (end_bit - shift)) - 1u;
+        hipLaunchKernelGGL(k_digit_hist, dim3(nblocks), dim3(kThreads), 0, st, kin, cap, n_dev, shift, dmask, hist);
         hipLaunchKernelGGL(k_row_scan, dim3(256), dim3(kThreads), 0, st, hist, cap, n_dev, rowtot);
         hipLaunchKernelGGL(k_rank_scatter, dim3(nblocks), dim3(kThreads), 0, st, kin,
                            first && iota_values ? (const uint32_t*)nullptr : vin, kout, vout, cap, n_dev,
-                           shift, hist, rowtot);
+                           shift, dmask, hist, rowtot);
         first = false;
         std::swap(kin, kout);
         std::swap(vin, vout);
@@ -317,3 +321,45 @@ int exclusive_scan_u32(Workspace& ws, const uint32_t* in, uint32_t* out, int64_t
 }
 
 }  // namespace rtac
+
+extern "C" int rt_debug_radix_sort(uint64_t* keys, uint32_t* order, int64_t cap, const int64_t* n_dev,
+                                   int32_t begin_bit, int32_t end_bit, void* stream) {
+    using namespace rtac;
+    RT_CHECK(keys && order, RT_EINVAL, "rt_debug_radix_sort: null keys or order");
+    RT_CHECK(cap >= 0 && cap < ((int64_t)1 << 32), RT_EINVAL, "rt_debug_radix_sort: cap out of range");
+    RT_CHECK(begin_bit >= 0 && begin_bit < end_bit && end_bit <= 64, RT_EINVAL,
+             "rt_debug_radix_sort: bits [%d, %d) out of range", begin_bit, end_bit);
+    if (cap == 0) return RT_OK;
+    hipStream_t st = (hipStream_t)stream;
+    CallStream call_stream(st);
+    Workspace ws;
+    Buf k1, v0;
+    int rc = RT_OK;
+    if (k1.ensure(sizeof(uint64_t) * (size_t)cap) || v0.ensure(sizeof(uint32_t) * (size_t)cap)) {
+        rc = RT_ENOMEM;
+    } else {
+        int which = 0;
+        rc = radix_sort_pairs(ws, keys, v0.as<uint32_t>(), k1.as<uint64_t>(), order, cap, n_dev, begin_bit, end_bit,
+                              st, &which, true);
+        if (rc == RT_OK && which == 0) {
+            // the result is in (keys, v0): the order goes to `order`
+            if (hipMemcpyAsync(order, v0.p, sizeof(uint32_t) * (size_t)cap, hipMemcpyDeviceToDevice, st) !=
+                hipSuccess) {
+                set_error("rt_debug_radix_sort: copy failed");
+                rc = RT_EHIP;
+            }
+        } else if (rc == RT_OK) {
+            // the result is in (k1, order): the keys go back to `keys`
+            if (hipMemcpyAsync(keys, k1.p, sizeof(uint64_t) * (size_t)cap, hipMemcpyDeviceToDevice, st) !=
+                hipSuccess) {
+                set_error("rt_debug_radix_sort: copy failed");
+                rc = RT_EHIP;
+            }
+        }
+    }
+    k1.release();
+    v0.release();
+    ws.release_all();
+    return rc;
+}
+

@@ -43,6 +43,7 @@ def test_argument_validation_without_device(lib):
     assert b"null" in lib.rt_last_error().lower()
     assert lib.rt_rebuild_tree(None, None, 0, None, 0, None, None, None, None) == -1
     assert b"null scene" in lib.rt_last_error()
+    assert lib.rt_debug_radix_sort(None, None, 8, None, 0, 8, None) == -1
     assert lib.rt_fibonacci_directions(-1, None, None) == -1
     assert lib.rt_fibonacci_directions(0, None, None) == 0
     assert lib.rt_trace_rays(None, None, None, None, None, None, 0, None, 0, None, None, None, 0, None, None,
