@@ -394,7 +394,8 @@ __global__ void k_esc_owner(int64_t nt, const uint32_t* __restrict__ off, uint32
 }
 
 // Reference r: piece i of triangle t = ref_tri[r] (one thread per reference,
-// so triangles cut into many pieces do not hold up a wavefront).  An unsplit triangle keeps its FP32 box;
+// so triangles cut into many pieces do not hold up a wavefront).  An unsplit triangle keeps its FP32 box
+// (tri_box, from the validated mesh);
 // piece i of k is the triangle clipped to slab i of its box's longest side
 // (FP64), its box rounded outward to FP32 and widened by `margin` (8 units in
 // the last place of the scene's extent: the FP32 watertight test decides hits
@@ -402,23 +403,21 @@ __global__ void k_esc_owner(int64_t nt, const uint32_t* __restrict__ off, uint32
 // triangle's own box did not have).
 __global__ void k_esc_emit(const float* __restrict__ vtx, int64_t nv, const int3* __restrict__ tri, int64_t nt,
                            const uint32_t* __restrict__ off, int64_t nr, const uint32_t* __restrict__ bounds,
-                           const uint32_t* __restrict__ ref_tri, float* __restrict__ ref_box) {
+                           const uint32_t* __restrict__ ref_tri, const float* __restrict__ tri_box,
+                           float* __restrict__ ref_box) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nr) return;
     const int64_t t = ref_tri[r];
     if (t >= nt) return;
     const int i = (int)(r - (int64_t)off[t]);
     const int k = (int)(off[t + 1] - off[t]);
+    if (k == 1) {
+        for (int c = 0; c < 6; c++) ref_box[6 * r + c] = tri_box[6 * t + c];
+        return;
+    }
     double p[3][3];
     if (!esc_vertices(vtx, nv, tri, t, p)) {
         for (int c = 0; c < 6; c++) ref_box[6 * r + c] = 0.f;
-        return;
-    }
-    if (k == 1) {
-        for (int c = 0; c < 3; c++) {
-            ref_box[6 * r + c] = (float)fmin(p[0][c], fmin(p[1][c], p[2][c]));
-            ref_box[6 * r + 3 + c] = (float)fmax(p[0][c], fmax(p[1][c], p[2][c]));
-        }
         return;
     }
     int ax;
@@ -460,9 +459,9 @@ __device__ inline int prefix_len(const uint64_t* __restrict__ k, int64_t n, int6
 // Binary radix tree over sorted codes (one inner node per adjacent pair):
 // node i covers [first, last]; its split is where the common prefix ends.
 // Children: >= 0 inner node, < 0 leaf ~j.  parent arrays: -1 for the root.
-__global__ void k_radix_tree(const uint64_t* __restrict__ k, int64_t n, int32_t* __restrict__ left,
-                             int32_t* __restrict__ right, int32_t* __restrict__ first, int32_t* __restrict__ last,
-                             int32_t* __restrict__ parent_in, int32_t* __restrict__ parent_leaf) {
+__global__ void k_radix_tree(const uint64_t* __restrict__ k, int64_t n, int2* __restrict__ kids,
+                             int2* __restrict__ range, int32_t* __restrict__ parent_in,
+                             int32_t* __restrict__ parent_leaf) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n - 1) return;
     const int d = (prefix_len(k, n, i, i + 1) - prefix_len(k, n, i, i - 1)) >= 0 ? 1 : -1;
@@ -496,10 +495,8 @@ __global__ void k_radix_tree(const uint64_t* __restrict__ k, int64_t n, int32_t*
         rc = (int32_t)(g + 1);
         parent_in[g + 1] = (int32_t)i;
     }
-    left[i] = lc;
-    right[i] = rc;
-    first[i] = (int32_t)lo;
-    last[i] = (int32_t)hi;
+    kids[i] = make_int2(lc, rc);
+    range[i] = make_int2((int32_t)lo, (int32_t)hi);
     if (i == 0) parent_in[0] = -1;
 }
 
@@ -601,11 +598,12 @@ __global__ __launch_bounds__(1024) void k_seg_top(int64_t n, SegOut seg) {
     }
 }
 
-__global__ void k_node_boxes(int64_t n_in, const int32_t* __restrict__ first, const int32_t* __restrict__ last,
+__global__ void k_node_boxes(int64_t n_in, const int2* __restrict__ range,
                              SegLevels seg, float* __restrict__ box_in) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_in) return;
-    int64_t l = first[i], r = (int64_t)last[i] + 1;
+    const int2 fl = range[i];
+    int64_t l = fl.x, r = (int64_t)fl.y + 1;
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (int lv = 0; l < r && lv < seg.n_levels; lv++) {
         if (l & 1) {
@@ -627,12 +625,14 @@ __global__ void k_node_boxes(int64_t n_in, const int32_t* __restrict__ first, co
     }
 }
 
-__device__ inline int32_t node_size(const int32_t* first, const int32_t* last, int32_t c) {
-    return c < 0 ? 1 : last[c] - first[c] + 1;
+__device__ inline int32_t node_size(const int2* range, int32_t c) {
+    if (c < 0) return 1;
+    const int2 fl = range[c];
+    return fl.y - fl.x + 1;
 }
 
 // Inner nodes above the leaf-cluster level at even depth become 4-wide nodes.
-__global__ void k_flag4(int64_t n_in, const int32_t* __restrict__ first, const int32_t* __restrict__ last,
+__global__ void k_flag4(int64_t n_in, const int2* __restrict__ range,
                         const int32_t* __restrict__ parent_in, int32_t leaf_size, uint32_t* __restrict__ flag,
                         int32_t* __restrict__ depth_out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -640,7 +640,7 @@ __global__ void k_flag4(int64_t n_in, const int32_t* __restrict__ first, const i
     int depth = 0;
     for (int32_t p = parent_in[i]; p >= 0 && depth < 4096; p = parent_in[p]) depth++;
     depth_out[i] = depth;
-    const int32_t size = last[i] - first[i] + 1;
+    const int32_t size = node_size(range, (int32_t)i);
     flag[i] = (size > leaf_size && (depth & 1) == 0) ? 1u : 0u;
 }
 
@@ -648,16 +648,18 @@ __global__ void k_flag4(int64_t n_in, const int32_t* __restrict__ first, const i
 // Its slots are the two children, each replaced by its own two children when
 // it is an inner node larger than a leaf: with eA, eB those two choices the
 // slot refs have closed forms, so every slot's loads can be in flight at once.
-__device__ inline uint32_t emit4_one(int64_t i, const int32_t* __restrict__ left, const int32_t* __restrict__ right,
-                                     const int32_t* __restrict__ first, const int32_t* __restrict__ last,
+__device__ inline uint32_t emit4_one(int64_t i, const int2* __restrict__ kids, const int2* __restrict__ range,
                                      const uint32_t* __restrict__ index, const int32_t* __restrict__ depth_in,
                                      const float* __restrict__ box_in, const float* __restrict__ tri_box,
                                      const uint32_t* __restrict__ order, int32_t leaf_size, Node4* __restrict__ nodes) {
-    const int32_t c0 = left[i], c1 = right[i];
-    const bool eA = c0 >= 0 && node_size(first, last, c0) > leaf_size;
-    const bool eB = c1 >= 0 && node_size(first, last, c1) > leaf_size;
-    const int32_t a0 = eA ? left[c0] : c0, a1 = eA ? right[c0] : 0;
-    const int32_t b0 = eB ? left[c1] : c1, b1 = eB ? right[c1] : 0;
+    const int2 cc = kids[i];
+    const int32_t c0 = cc.x, c1 = cc.y;
+    const bool eA = c0 >= 0 && node_size(range, c0) > leaf_size;
+    const bool eB = c1 >= 0 && node_size(range, c1) > leaf_size;
+    const int2 ka = eA ? kids[c0] : make_int2(c0, 0);
+    const int2 kb = eB ? kids[c1] : make_int2(c1, 0);
+    const int32_t a0 = ka.x, a1 = ka.y;
+    const int32_t b0 = kb.x, b1 = kb.y;
     int32_t ref[4];
     bool use[4];
     ref[0] = a0;
@@ -675,14 +677,20 @@ __device__ inline uint32_t emit4_one(int64_t i, const int32_t* __restrict__ left
         int32_t child = kEmpty;
         if (use[sl]) {
             const int32_t c = ref[sl];
+            // a box is 6 floats at a multiple of 24 bytes: three 8-byte loads
+            const float2* b = c < 0 ? reinterpret_cast<const float2*>(tri_box + 6 * (int64_t)order[~c])
+                                    : reinterpret_cast<const float2*>(box_in + 6 * (int64_t)c);
+            for (int q = 0; q < 3; q++) {
+                const float2 v = b[q];
+                bx[2 * q] = v.x;
+                bx[2 * q + 1] = v.y;
+            }
             if (c < 0) {
-                const uint32_t t = order[~c];
-                for (int q = 0; q < 6; q++) bx[q] = tri_box[6 * (int64_t)t + q];
                 child = leaf_ref(~c, 1);
             } else {
-                for (int q = 0; q < 6; q++) bx[q] = box_in[6 * (int64_t)c + q];
-                const int32_t sz = last[c] - first[c] + 1;
-                child = sz <= leaf_size ? leaf_ref(first[c], sz) : (int32_t)index[c];
+                const int2 fl = range[c];
+                const int32_t sz = fl.y - fl.x + 1;
+                child = sz <= leaf_size ? leaf_ref(fl.x, sz) : (int32_t)index[c];
             }
         } else {
             bx[0] = bx[1] = bx[2] = INFINITY;
@@ -709,8 +717,7 @@ __global__ void k_list4(int64_t n_in, const uint32_t* __restrict__ flag, const u
 }
 
 // One thread per 4-wide node (the count index[n_in] is read on the device).
-__global__ void k_emit4(int64_t n_in, const int32_t* __restrict__ left, const int32_t* __restrict__ right,
-                        const int32_t* __restrict__ first, const int32_t* __restrict__ last,
+__global__ void k_emit4(int64_t n_in, const int2* __restrict__ kids, const int2* __restrict__ range,
                         const int32_t* __restrict__ list, const uint32_t* __restrict__ index,
                         const int32_t* __restrict__ depth_in, const float* __restrict__ box_in,
                         const float* __restrict__ tri_box, const uint32_t* __restrict__ order, int32_t leaf_size,
@@ -719,7 +726,7 @@ __global__ void k_emit4(int64_t n_in, const int32_t* __restrict__ left, const in
     const int64_t n4 = (int64_t)index[n_in];
     uint32_t d = 0;
     if (j < n4)
-        d = emit4_one(list[j], left, right, first, last, index, depth_in, box_in, tri_box, order, leaf_size, nodes);
+        d = emit4_one(list[j], kids, range, index, depth_in, box_in, tri_box, order, leaf_size, nodes);
     // tree depth: one atomic per wavefront
     for (int off = kWave / 2; off > 0; off >>= 1) {
         const uint32_t o = __shfl_down(d, off);
@@ -898,7 +905,7 @@ int build_scene(rt_scene* s, const char* who, const float* vtx, int64_t n_vtx, c
     }
     hipLaunchKernelGGL(k_esc_owner, dim3(blocks(nt)), dim3(256), 0, st, nt, ref_off, ref_tri);
     hipLaunchKernelGGL(k_esc_emit, dim3(blocks(nr)), dim3(256), 0, st, vtx, n_vtx, (const int3*)tri, nt, ref_off, nr,
-                       bounds, ref_tri, ref_box);
+                       bounds, ref_tri, tri_box, ref_box);
     hipLaunchKernelGGL(k_morton, dim3(blocks(nr)), dim3(256), 0, st, ref_box, nr, bounds, codes0);
     int which = 0;
     rc = radix_sort_pairs(s->ws, codes0, ord0, codes1, ord1, nr, nullptr, 0, 3 * kMortonBits, st, &which, true);
@@ -909,10 +916,8 @@ int build_scene(rt_scene* s, const char* who, const float* vtx, int64_t n_vtx, c
     if (single) {
         hipLaunchKernelGGL(k_single_leaf_root, dim3(1), dim3(1), 0, st, bounds, (int32_t)nr, s->nodes);
     } else {
-        int32_t* left = tmp.get<int32_t>(n_in);
-        int32_t* right = tmp.get<int32_t>(n_in);
-        int32_t* first = tmp.get<int32_t>(n_in);
-        int32_t* last = tmp.get<int32_t>(n_in);
+        int2* kids = tmp.get<int2>(n_in);    // (left, right) child refs; ~leaf for a leaf child
+        int2* range = tmp.get<int2>(n_in);   // (first, last) reference covered
         int32_t* par_in = tmp.get<int32_t>(n_in);
         int32_t* par_leaf = tmp.get<int32_t>(nr);
         int32_t* depth = tmp.get<int32_t>(n_in);
@@ -920,12 +925,12 @@ int build_scene(rt_scene* s, const char* who, const float* vtx, int64_t n_vtx, c
         uint32_t* flag = tmp.get<uint32_t>(n_in);
         uint32_t* index = tmp.get<uint32_t>(n_in + 1);
         int32_t* list4 = tmp.get<int32_t>(n_in);
-        if (!left || !right || !first || !last || !par_in || !par_leaf || !depth || !box_in || !flag ||
+        if (!kids || !range || !par_in || !par_leaf || !depth || !box_in || !flag ||
             !index || !list4) {
             set_error("%s: out of device memory", who);
             return RT_ENOMEM;
         }
-        hipLaunchKernelGGL(k_radix_tree, dim3(blocks(n_in)), dim3(256), 0, st, codes, nr, left, right, first, last,
+        hipLaunchKernelGGL(k_radix_tree, dim3(blocks(n_in)), dim3(256), 0, st, codes, nr, kids, range,
                            par_in, par_leaf);
         // segment tree over the ordered reference boxes, then one range query per inner node
         SegLevels seg;
@@ -955,13 +960,13 @@ int build_scene(rt_scene* s, const char* who, const float* vtx, int64_t n_vtx, c
             if (seg.n_levels > kSegBlockLevels + 1)
                 hipLaunchKernelGGL(k_seg_top, dim3(1), dim3(1024), 0, st, nr, segw);
         }
-        hipLaunchKernelGGL(k_node_boxes, dim3(blocks(n_in)), dim3(256), 0, st, n_in, first, last, seg, box_in);
-        hipLaunchKernelGGL(k_flag4, dim3(blocks(n_in)), dim3(256), 0, st, n_in, first, last, par_in, leaf, flag,
+        hipLaunchKernelGGL(k_node_boxes, dim3(blocks(n_in)), dim3(256), 0, st, n_in, range, seg, box_in);
+        hipLaunchKernelGGL(k_flag4, dim3(blocks(n_in)), dim3(256), 0, st, n_in, range, par_in, leaf, flag,
                            depth);
         rc = exclusive_scan_u32(s->ws, flag, index, n_in, nullptr, st);
         if (rc) return rc;
         hipLaunchKernelGGL(k_list4, dim3(blocks(n_in)), dim3(256), 0, st, n_in, flag, index, list4);
-        hipLaunchKernelGGL(k_emit4, dim3(blocks(n_in)), dim3(256), 0, st, n_in, left, right, first, last, list4,
+        hipLaunchKernelGGL(k_emit4, dim3(blocks(n_in)), dim3(256), 0, st, n_in, kids, range, list4,
                            index, depth, box_in, ref_box, order, leaf, s->nodes, info);
         hipLaunchKernelGGL(k_copy_u32, dim3(1), dim3(1), 0, st, index + n_in, n4_dev);
     }
