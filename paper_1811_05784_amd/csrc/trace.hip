@@ -915,7 +915,8 @@ k_trace(TraceArgs a) {
                 if (!(dl > 0.0)) dl = 0.0;
             }
             if (uu > 0.0) {
-                const double inv_uu = 1.0 / uu;   // one division for all receivers
+                const float inv_uuf = 1.0f / (r.ux * r.ux + r.uy * r.uy + r.uz * r.uz);
+                double inv_uu = 0.0;   // FP64 1/|u|^2, computed for the first receiver past the screen
                 for (int m = 0; m < n_rcv; m++) {
                     double cx, cy, cz, cr;
                     if (kBatch) {
@@ -930,6 +931,19 @@ k_trace(TraceArgs a) {
                         cz = rcv_s[m][2];
                         cr = rcv_s[m][3];
                     }
+                    {
+                        // FP32 screen.  The squared distance of the centre from the ray's
+                        // line bounds the segment's from below; computed in FP32 from the
+                        // FP32 inputs it is within about 30 units of 2^-24 |w|^2 of the
+                        // exact value (w = centre - origin), so a line that clears the
+                        // sphere by 64 such units misses it in the FP64 test too
+                        const float wxf = (float)cx - r.ox, wyf = (float)cy - r.oy, wzf = (float)cz - r.oz;
+                        const float af = wxf * wxf + wyf * wyf + wzf * wzf;
+                        const float bf = wxf * r.ux + wyf * r.uy + wzf * r.uz;
+                        const float crf = (float)cr;
+                        if (af - bf * bf * inv_uuf > crf * crf + 0x1p-18f * af) continue;
+                    }
+                    if (inv_uu == 0.0) inv_uu = 1.0 / uu;
                     const double wx = cx - ox, wy = cy - oy, wz = cz - oz;
                     double ts = (wx * ux + wy * uy + wz * uz) * inv_uu;
                     if (ts < 0.0) ts = 0.0;
