@@ -20,6 +20,7 @@ void set_error(const char* fmt, ...) {
 namespace {
 struct Held {
     hipEvent_t ev;   // recorded on the freeing call's stream
+    int ev_dev;      // the device the event belongs to
     std::pair<int, size_t> key;
     void* p;
 };
@@ -28,7 +29,7 @@ struct Cache {
     std::map<void*, std::pair<int, size_t>> live;          // ptr -> (device, bytes)
     std::multimap<std::pair<int, size_t>, void*> free_;    // (device, bytes) -> ptr
     std::vector<Held> held;                                 // freed, waiting for their event
-    std::vector<hipEvent_t> spare;                          // completed events for reuse
+    std::vector<std::pair<int, hipEvent_t>> spare;          // (device, completed event) for reuse
 };
 Cache& cache() {
     static Cache* c = new Cache();   // never destroyed: freed blocks live until exit
@@ -44,7 +45,7 @@ void release_completed(Cache& c) {
         const hipError_t q = hipEventQuery(c.held[i].ev);
         if (q == hipSuccess) {
             c.free_.insert({c.held[i].key, c.held[i].p});
-            c.spare.push_back(c.held[i].ev);
+            c.spare.push_back({c.held[i].ev_dev, c.held[i].ev});
             c.held[i] = c.held.back();
             c.held.pop_back();
         } else {
@@ -121,18 +122,24 @@ void dcache_free(void* p) {
         // captured into a graph: there the caller keeps its buffers alive)
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         if (hipStreamIsCapturing(t_stream, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) {
+            // an event of the current device (the calling stream's)
+            int cur = 0;
+            (void)hipGetDevice(&cur);
             hipEvent_t ev = nullptr;
-            if (!c.spare.empty()) {
-                ev = c.spare.back();
-                c.spare.pop_back();
-            } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
-                ev = nullptr;
+            for (size_t i = 0; i < c.spare.size(); i++) {
+                if (c.spare[i].first == cur) {
+                    ev = c.spare[i].second;
+                    c.spare[i] = c.spare.back();
+                    c.spare.pop_back();
+                    break;
+                }
             }
+            if (!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) ev = nullptr;
             if (ev && hipEventRecord(ev, t_stream) == hipSuccess) {
-                c.held.push_back({ev, key, p});
+                c.held.push_back({ev, cur, key, p});
                 return;
             }
-            if (ev) c.spare.push_back(ev);
+            if (ev) c.spare.push_back({cur, ev});
         }
         (void)hipGetLastError();
     }
