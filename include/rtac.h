@@ -183,7 +183,7 @@ typedef struct {
     int64_t* stats;            /* NULL or device int64[4], overwritten: inner nodes visited,
                                   leaves visited, triangle tests, stack spills.  Counts the
                                   per-lane traversal, so a call with stats runs with
-                                  coop_queries off (same results)                               */
+                                  coop_queries off and 4 waves per SIMD (same results)          */
     int32_t rounds;            /* 0 = default (1); kernel launches: once the ray pool is empty,
                                   a wavefront with few rays left hands them to the next launch  */
     int32_t spill_threshold;   /* 0 = default; most rays a wavefront may still hold to hand over */

@@ -132,6 +132,11 @@ struct Ray {
     int kx, ky, kz;
 };
 
+// Number of set bits of m in the lanes below this one.
+__device__ inline uint32_t lanes_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 __device__ inline float pick(float a, float b, float c, int k) { return k == 0 ? a : (k == 1 ? b : c); }
 
 __device__ inline void setup_ray(Ray& r) {
@@ -197,10 +202,13 @@ struct Stack {
     int base, cnt, gsp;
 };
 
+// The lane's spill area is spill_all + (block * kBlock + tid) * spill_n, formed
+// only on the (rare) spill and refill paths so that no register holds it.
 template <int kRing>
-__device__ inline bool stack_push(Stack& s, int32_t* lds, int32_t* spill, int spill_n, int tid, int32_t item) {
+__device__ inline bool stack_push(Stack& s, int32_t* lds, int32_t* spill_all, int spill_n, int tid, int32_t item) {
     if (s.cnt == kRing) {
         if (s.gsp + kSpillChunk > spill_n) return false;
+        int32_t* spill = spill_all + ((int64_t)blockIdx.x * kBlock + tid) * spill_n;
         for (int i = 0; i < kSpillChunk; i++) spill[s.gsp + i] = lds[((s.base + i) & (kRing - 1)) * kBlock + tid];
         s.gsp += kSpillChunk;
         s.base = (s.base + kSpillChunk) & (kRing - 1);
@@ -213,9 +221,11 @@ __device__ inline bool stack_push(Stack& s, int32_t* lds, int32_t* spill, int sp
 
 // Returns false when the stack is empty.
 template <int kRing>
-__device__ inline bool stack_pop(Stack& s, int32_t* lds, const int32_t* spill, int tid, int32_t& item) {
+__device__ inline bool stack_pop(Stack& s, int32_t* lds, const int32_t* spill_all, int spill_n, int tid,
+                                 int32_t& item) {
     if (s.cnt == 0) {
         if (s.gsp == 0) return false;
+        const int32_t* spill = spill_all + ((int64_t)blockIdx.x * kBlock + tid) * spill_n;
         const int h = s.gsp < kSpillChunk ? s.gsp : kSpillChunk;
         s.gsp -= h;
         s.base = (s.base - h) & (kRing - 1);
@@ -498,7 +508,7 @@ __device__ inline bool coop_search(const Ray& q, int32_t qlp, float& bt, int32_t
     return ok;
 }
 
-template <int kWavesPerEU, bool kBatch, int kRing>
+template <int kWavesPerEU, bool kBatch, int kRing, bool kStats>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWavesPerEU, 8)))
 k_trace(TraceArgs a) {
     __shared__ int32_t lds_stack[kRing * kBlock];
@@ -526,8 +536,6 @@ k_trace(TraceArgs a) {
         lim = fminf(lim, beam_range(r_max, a.n_rays, a.beam_n));
     }
 
-    int32_t* spill = a.spill + ((int64_t)blockIdx.x * kBlock + tid) * a.spill_per_lane;
-    const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
     const int R1 = a.R + 1;
 
     int status = kIdle;
@@ -544,9 +552,9 @@ k_trace(TraceArgs a) {
     float best_t = INFINITY;
     int32_t best_j = -1, best_id = 0x7FFFFFFF;
     int32_t steps = 0;
-    uint32_t n_query = 0, n_escape = 0;
+    uint32_t n_query = 0, n_escape = 0;   // wave totals (the same in every lane)
     uint32_t st_nodes = 0, st_leaves = 0, st_tris = 0, st_spill = 0;
-    const bool want_stats = a.stats != nullptr;
+    constexpr bool want_stats = kStats;
     unsigned long long pool_n = a.q_in ? *a.q_in_count : (unsigned long long)a.n_rays;
     if (a.q_in && pool_n > (unsigned long long)a.q_cap) pool_n = (unsigned long long)a.q_cap;
     bool pool_empty = pool_n == 0;
@@ -591,7 +599,7 @@ k_trace(TraceArgs a) {
                 if (base + (unsigned long long)n_idle >= pool_n) pool_empty = true;
             }
             if (status == kIdle && base != ~0ull) {
-                const unsigned long long my = base + (unsigned long long)__popcll(idle & lt_mask);
+                const unsigned long long my = base + (unsigned long long)lanes_below(idle);
                 if (my < hi) {
                     if (kBatch && !a.q_in) {
                         const int64_t g = a.order ? (int64_t)a.order[my] : (int64_t)my;
@@ -681,7 +689,7 @@ k_trace(TraceArgs a) {
                     base = __shfl(base, leader);
                     if (status != kIdle) {
                         // the current segment restarts from its input state
-                        const unsigned long long pos = base + (unsigned long long)__popcll(act & lt_mask);
+                        const unsigned long long pos = base + (unsigned long long)lanes_below(act);
                         int4* q = a.q_out + 3 * pos;
                         q[0] = make_int4((int)ray, k, last_plane, 0);
                         const double lq = len_s[tid];
@@ -734,7 +742,7 @@ k_trace(TraceArgs a) {
                 ok = coop_search<kRing>(q, qlp, bt, bid, bj, hitp_s + (tid - lane) + mo, col, lane & (G - 1), G * g, G,
                                         has_query, nodes, tri, n_nodes, n_tri, a.max_steps);
                 // each owner takes its group's result (from the group's first lane)
-                const int my_g = (int)__popcll(act & lt_mask);   // an owner's group
+                const int my_g = (int)lanes_below(act);   // an owner's group
                 const int from = (status == kQuery ? my_g : 0) * G;
                 const float rbt = __shfl(bt, from);
                 const int32_t rbid = __shfl(bid, from), rbj = __shfl(bj, from);
@@ -847,7 +855,7 @@ k_trace(TraceArgs a) {
 #pragma unroll
                 for (int sl = 3; sl >= 0; sl--)
                     if (tn[sl] < INFINITY && sl != ii && sl != li)
-                        ok &= stack_push<kRing>(st, lds_stack, spill, a.spill_per_lane, tid, rf[sl]);
+                        ok &= stack_push<kRing>(st, lds_stack, a.spill, a.spill_per_lane, tid, rf[sl]);
                 leaf = li == 0 ? rf[0] : li == 1 ? rf[1] : li == 2 ? rf[2] : li == 3 ? rf[3] : kEmpty;
                 cur = ii == 0 ? rf[0] : ii == 1 ? rf[1] : ii == 2 ? rf[2] : ii == 3 ? rf[3] : kEmpty;
             } else {
@@ -888,13 +896,15 @@ k_trace(TraceArgs a) {
                     }
                 }
             }
-            if (cur == kEmpty) have = stack_pop<kRing>(st, lds_stack, spill, tid, cur);
+            if (cur == kEmpty) have = stack_pop<kRing>(st, lds_stack, a.spill, a.spill_per_lane, tid, cur);
             if (!have) status = kDone;
             asm volatile("" ::"v"(touch));   // keeps the touch load
         }
 
         // ---- shade the finished queries (FP64), record, reflect ---------------
         const bool shading = status == kDone;
+        n_query += (uint32_t)__popcll(__ballot(shading));
+        n_escape += (uint32_t)__popcll(__ballot(shading && best_j < 0));
         uint32_t dm = 0;
         double dl = INFINITY;
         int32_t hit_id = -1, hit_plane = -1;
@@ -987,7 +997,6 @@ k_trace(TraceArgs a) {
         }
         bool susp = false;
         if (shading) {
-            n_query++;
             int32_t* hs = a.hit_seq + (int64_t)ray * R1;
             hs[k] = hit_id;
             const double Lc = len_s[tid];
@@ -1004,9 +1013,7 @@ k_trace(TraceArgs a) {
                 sp[7] = __int_as_float(last_plane);
             }
             bool stop = true;
-            if (hit_id < 0) {
-                n_escape++;
-            } else {
+            if (hit_id >= 0) {
                 const double nx = pl_n[3 * (int64_t)hit_plane], ny = pl_n[3 * (int64_t)hit_plane + 1],
                              nz = pl_n[3 * (int64_t)hit_plane + 2];
                 const double udn = ux * nx + uy * ny + uz * nz;
@@ -1059,7 +1066,7 @@ k_trace(TraceArgs a) {
                 if (lane == leader) base = atomicAdd(a.q_out_count, (unsigned long long)__popcll(sm));
                 base = __shfl(base, leader);
                 if (susp) {
-                    const unsigned long long pos = base + (unsigned long long)__popcll(sm & lt_mask);
+                    const unsigned long long pos = base + (unsigned long long)lanes_below(sm);
                     if (pos < (unsigned long long)a.q_cap) {
                         int4* q = a.q_out + 3 * pos;
                         q[0] = make_int4((int)ray, k, last_plane, 0);
@@ -1077,8 +1084,6 @@ k_trace(TraceArgs a) {
     }
     // per-wave totals
     for (int off = kWave / 2; off > 0; off >>= 1) {
-        n_query += __shfl_down(n_query, off);
-        n_escape += __shfl_down(n_escape, off);
         if (want_stats) {
             st_nodes += __shfl_down(st_nodes, off);
             st_leaves += __shfl_down(st_leaves, off);
@@ -1175,11 +1180,15 @@ __global__ void k_fibonacci(int64_t n, float* __restrict__ out) {
 
 template <bool kBatch, int kRing>
 void launch_trace_ring(int occ, unsigned nblk, hipStream_t st, const TraceArgs& a) {
+    if (a.stats) {   // traversal counts: the 4-wave instance that keeps them
+        hipLaunchKernelGGL((k_trace<4, kBatch, kRing, true>), dim3(nblk), dim3(kBlock), 0, st, a);
+        return;
+    }
     switch (occ) {
-        case 8: hipLaunchKernelGGL((k_trace<8, kBatch, kRing>), dim3(nblk), dim3(kBlock), 0, st, a); break;
-        case 6: hipLaunchKernelGGL((k_trace<6, kBatch, kRing>), dim3(nblk), dim3(kBlock), 0, st, a); break;
-        case 5: hipLaunchKernelGGL((k_trace<5, kBatch, kRing>), dim3(nblk), dim3(kBlock), 0, st, a); break;
-        default: hipLaunchKernelGGL((k_trace<4, kBatch, kRing>), dim3(nblk), dim3(kBlock), 0, st, a); break;
+        case 8: hipLaunchKernelGGL((k_trace<8, kBatch, kRing, false>), dim3(nblk), dim3(kBlock), 0, st, a); break;
+        case 6: hipLaunchKernelGGL((k_trace<6, kBatch, kRing, false>), dim3(nblk), dim3(kBlock), 0, st, a); break;
+        case 5: hipLaunchKernelGGL((k_trace<5, kBatch, kRing, false>), dim3(nblk), dim3(kBlock), 0, st, a); break;
+        default: hipLaunchKernelGGL((k_trace<4, kBatch, kRing, false>), dim3(nblk), dim3(kBlock), 0, st, a); break;
     }
 }
 
