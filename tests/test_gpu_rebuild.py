@@ -101,6 +101,24 @@ def test_rebuild_in_place_reproduces_fresh_builds(rt, meshes, fresh):
     sc.close()
 
 
+def test_rebuild_with_another_leaf_size(rt, meshes):
+    """A rebuild may change the leaf size; the tree then matches a fresh build
+    with that leaf size, and the results the fresh scene's."""
+    taps = synth.octave_fir_taps(K_FIR)
+    s = meshes["c2"]
+    sc = rt.Scene.from_synth(s, device="cuda:0")
+    for leaf in (4, 1, 8):
+        _say("rebuild with leaf size %d" % leaf)
+        ref_sc = rt.Scene.from_synth(s, leaf_size=leaf, device="cuda:0")
+        want = _summary(_run(rt, ref_sc, s, taps))
+        sc.rebuild(s.vtx, s.tri, s.material, s.plane_id, leaf_size=leaf)
+        got = _summary(_run(rt, sc, s, taps))
+        _same(got, want, "leaf size %d" % leaf)
+        assert (sc.n_nodes, sc.depth, sc.n_ref, sc.leaf_size) == (ref_sc.n_nodes, ref_sc.depth, ref_sc.n_ref, leaf)
+        ref_sc.close()
+    sc.close()
+
+
 def test_failed_rebuild_marks_the_scene_invalid_until_the_next_success(rt, meshes, fresh):
     taps = synth.octave_fir_taps(K_FIR)
     s = meshes["c1"]
