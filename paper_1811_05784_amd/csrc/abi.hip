@@ -38,6 +38,18 @@ Cache& cache() {
 thread_local hipStream_t t_stream = nullptr;
 thread_local bool t_has_stream = false;
 
+// Whether the calling entry point's stream is being captured into a graph
+// (no event is recorded or queried then).
+bool call_stream_capturing() {
+    if (!t_has_stream) return false;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(t_stream, &cs) != hipSuccess) {
+        (void)hipGetLastError();
+        return true;   // unknown: treat as capturing (free at once, query nothing)
+    }
+    return cs != hipStreamCaptureStatusNone;
+}
+
 // Moves held blocks whose event has completed to the free lists (lock held).
 void release_completed(Cache& c) {
     bool queried_busy = false;
@@ -75,7 +87,7 @@ void* dcache_alloc(size_t bytes) {
     Cache& c = cache();
     {
         std::lock_guard<std::mutex> g(c.mu);
-        if (!c.held.empty()) release_completed(c);
+        if (!c.held.empty() && !call_stream_capturing()) release_completed(c);
         auto it = c.free_.lower_bound({dev, bytes});
         if (it != c.free_.end() && it->first.first == dev && it->first.second <= 2 * bytes) {
             void* p = it->second;
@@ -89,7 +101,7 @@ void* dcache_alloc(size_t bytes) {
         (void)hipGetLastError();
         // give cached blocks back to the runtime and retry once
         std::lock_guard<std::mutex> g(c.mu);
-        release_completed(c);
+        if (!call_stream_capturing()) release_completed(c);
         for (auto it = c.free_.begin(); it != c.free_.end();) {
             if (it->first.first == dev) {
                 (void)hipFree(it->second);
@@ -117,31 +129,33 @@ void dcache_free(void* p) {
     if (it == c.live.end()) return;
     const std::pair<int, size_t> key = it->second;
     c.live.erase(it);
-    if (t_has_stream) {
-        // fence the block on the calling stream (not while it is being
-        // captured into a graph: there the caller keeps its buffers alive)
-        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-        if (hipStreamIsCapturing(t_stream, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) {
-            // an event of the current device (the calling stream's)
-            int cur = 0;
-            (void)hipGetDevice(&cur);
-            hipEvent_t ev = nullptr;
-            for (size_t i = 0; i < c.spare.size(); i++) {
-                if (c.spare[i].first == cur) {
-                    ev = c.spare[i].second;
-                    c.spare[i] = c.spare.back();
-                    c.spare.pop_back();
-                    break;
-                }
+    // fence the block on the calling stream (not while it is being captured
+    // into a graph: there the caller keeps its buffers alive)
+    if (t_has_stream && !call_stream_capturing()) {
+        // an event of the current device (the calling stream's)
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        hipEvent_t ev = nullptr;
+        for (size_t i = 0; i < c.spare.size(); i++) {
+            if (c.spare[i].first == cur) {
+                ev = c.spare[i].second;
+                c.spare[i] = c.spare.back();
+                c.spare.pop_back();
+                break;
             }
-            if (!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) ev = nullptr;
-            if (ev && hipEventRecord(ev, t_stream) == hipSuccess) {
-                c.held.push_back({ev, cur, key, p});
-                return;
-            }
-            if (ev) c.spare.push_back({cur, ev});
         }
-        (void)hipGetLastError();
+        if (!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            ev = nullptr;
+        }
+        if (ev && hipEventRecord(ev, t_stream) == hipSuccess) {
+            c.held.push_back({ev, cur, key, p});
+            return;
+        }
+        if (ev) {
+            (void)hipGetLastError();   // the record failed: the block is free at once
+            c.spare.push_back({cur, ev});
+        }
     }
     c.free_.insert({key, p});
 }
