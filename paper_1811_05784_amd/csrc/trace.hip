@@ -1157,12 +1157,17 @@ __global__ void k_ray_keys(const float* __restrict__ dirs, const float* __restri
 }
 
 // hit_seq <- -1 with 16-byte stores (rows are then written only where hit).
+// The -1 fill of the hit rows streams past the caches (non-temporal stores), so
+// that the tree and triangle records the trace is about to read stay in L2 and
+// the Infinity Cache (a million rows of 61 entries are larger than both).
+typedef int32_t v4i32 __attribute__((ext_vector_type(4)));
 __global__ void k_fill_rows(int32_t* __restrict__ p, int64_t n) {
     const int64_t n4 = n >> 2;
-    int4* q = reinterpret_cast<int4*>(p);
+    v4i32* q = reinterpret_cast<v4i32*>(p);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const v4i32 m1 = {-1, -1, -1, -1};
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride)
-        q[i] = make_int4(-1, -1, -1, -1);
+        __builtin_nontemporal_store(m1, q + i);
     for (int64_t i = 4 * n4 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = -1;
 }
 
